@@ -1,0 +1,757 @@
+/*
+ * lbm_oracle.c -- plain FP64 CPU oracle (test infrastructure only; see the
+ * header for what may load it).  Written for clarity, not speed: every step
+ * follows the paper's equations in the paper's order and notation.
+ *
+ * Build: gcc -O2 -fno-fast-math -ffp-contract=off -fopenmp -shared -fPIC
+ */
+#include "lbm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define Q 19
+#define HIST 19 /* doubles per fiber per recorded step: F3 M3 X3 q4 V3 W3 */
+
+/* ------------------------------------------------------------------------ */
+/* D3Q19 lattice (Sec. 4.1, Eq. SpeedOfSound and the weights after it).     */
+/* The paper fixes only the weights: 1/3 for the rest velocity, 1/18 for    */
+/* the six axis velocities, 1/36 for the twelve diagonals.  The order below */
+/* (rest, +-x, +-y, +-z, then the xy, xz, yz diagonals, opposites adjacent) */
+/* is this oracle's own choice; it only affects rounding order.             */
+/* ------------------------------------------------------------------------ */
+static const int CV[Q][3] = {
+    {0, 0, 0},
+    {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1},
+};
+static const double W0 = 1.0 / 3.0, W1 = 1.0 / 18.0, W2 = 1.0 / 36.0;
+
+static double weight(int q) { return q == 0 ? W0 : (q <= 6 ? W1 : W2); }
+
+/* opposite direction: c_opp(q) = -c_q, found by search (no index tricks) */
+static int opposite(int q)
+{
+    for (int p = 0; p < Q; ++p)
+        if (CV[p][0] == -CV[q][0] && CV[p][1] == -CV[q][1] && CV[p][2] == -CV[q][2]) return p;
+    return -1;
+}
+
+void or_lattice(int32_t *c, double *w, int32_t *opp)
+{
+    for (int q = 0; q < Q; ++q) {
+        for (int k = 0; k < 3; ++k) c[3 * q + k] = CV[q][k];
+        w[q] = weight(q);
+        opp[q] = opposite(q);
+    }
+}
+
+/* He-Luo incompressible equilibrium (Eq. fequ_Incompr) with c_s^2 = 1/3:   */
+/* f_eq = w [rho + rho0 (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)]                    */
+void or_feq(double rho, double rho0, const double u[3], double *feq)
+{
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int q = 0; q < Q; ++q) {
+        double cu = CV[q][0] * u[0] + CV[q][1] * u[1] + CV[q][2] * u[2];
+        feq[q] = weight(q) * (rho + rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+    }
+}
+
+/* odd relaxation rate from the TRT parameter Lambda:                        */
+/* Lambda = (1/omega_e - 1/2)(1/omega_o - 1/2)  (Sec. 4.1; Lambda = 3/16 is   */
+/* the value for which lambda_o = -8(2-omega)/(8-omega), i.e. walls exactly  */
+/* half-way).  SRT uses omega_o = omega_e.                                   */
+double or_omega_odd(double tau, double magic, int srt)
+{
+    if (srt) return 1.0 / tau;
+    return 1.0 / (0.5 + magic / (tau - 0.5));
+}
+
+/* TRT collision of one cell (Eqs. TRTOp, EqPDF_TRT, LBMCollide).            */
+/* lambda_e = -omega_e, lambda_o = -omega_o.  With a body force g the        */
+/* velocity carries the half-force shift and the odd part receives           */
+/* (1 - omega_o/2) 3 w rho0 c.g; the paper writes no forcing term, this is   */
+/* the reading used for the Poiseuille and drag pins only.                   */
+void or_collide_cell(const double *f, double rho0, double omega_e, double omega_o,
+                     const double g[3], double *fpost)
+{
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < Q; ++q) {
+        rho += f[q];
+        for (int k = 0; k < 3; ++k) j[k] += CV[q][k] * f[q];
+    }
+    double u[3];
+    for (int k = 0; k < 3; ++k) u[k] = j[k] / rho0 + 0.5 * g[k];
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int q = 0; q < Q; ++q) {
+        int qb = opposite(q);
+        double w = weight(q);
+        double cu = CV[q][0] * u[0] + CV[q][1] * u[1] + CV[q][2] * u[2];
+        double cg = CV[q][0] * g[0] + CV[q][1] * g[1] + CV[q][2] * g[2];
+        double feq_e = w * (rho - 1.5 * rho0 * uu + 4.5 * rho0 * cu * cu);
+        double feq_o = w * 3.0 * rho0 * cu;
+        double fe = 0.5 * (f[q] + f[qb]);
+        double fo = 0.5 * (f[q] - f[qb]);
+        fpost[q] = f[q] - omega_e * (fe - feq_e) - omega_o * (fo - feq_o)
+                 + (1.0 - 0.5 * omega_o) * 3.0 * w * rho0 * cg;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry: fibers are circular cylinders of length L and radius r.  The   */
+/* axis is t = R(q) e_x for the unit quaternion q = (w, x, y, z).  A cell   */
+/* belongs to a particle when its centre lies inside it (Sec. 4.2).         */
+/* All expressions are written so that no fused multiply-add is formed.     */
+/* ------------------------------------------------------------------------ */
+void or_fiber_axis(const double q[4], double t[3])
+{
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    t[0] = 1.0 - 2.0 * (y * y + z * z);
+    t[1] = 2.0 * (x * y + w * z);
+    t[2] = 2.0 * (x * z - w * y);
+}
+
+/* minimum-image component of a periodic difference */
+static double min_image(double d, int n, int periodic)
+{
+    if (!periodic) return d;
+    double h = 0.5 * n;
+    if (d > h) return d - n;
+    if (d < -h) return d + n;
+    return d;
+}
+
+int or_cell_inside(const double c[3], const double X[3], const double t[3],
+                   double length, double radius, int nx, int ny, int nz, int zper)
+{
+    double dx = min_image(c[0] - X[0], nx, 1);
+    double dy = min_image(c[1] - X[1], ny, 1);
+    double dz = min_image(c[2] - X[2], nz, zper);
+    double a = dx * t[0] + dy * t[1] + dz * t[2];
+    double dd = dx * dx + dy * dy + dz * dz;
+    double hl = 0.5 * length;
+    return (a * a <= hl * hl) && (dd - a * a <= radius * radius);
+}
+
+static int wrapi(int i, int n) { return ((i % n) + n) % n; }
+
+/* map np particles onto a lattice: pid = lowest covering id, -1 = fluid.    */
+/* Only cells within L/2 + r of the centre in each axis are tested; any     */
+/* cell inside the cylinder satisfies |d|^2 <= (L/2)^2 + r^2 <= (L/2 + r)^2. */
+void or_map(int nx, int ny, int nz, int zper, int np, const double *X, const double *q,
+            const double *length, const double *radius, int32_t *pid, int64_t *overlaps)
+{
+    int64_t ncell = (int64_t)nx * ny * nz, ov = 0;
+    for (int64_t i = 0; i < ncell; ++i) pid[i] = -1;
+    for (int p = 0; p < np; ++p) {
+        double t[3];
+        or_fiber_axis(q + 4 * p, t);
+        double ext = 0.5 * length[p] + radius[p];
+        int lo[3], hi[3], n[3] = {nx, ny, nz};
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = (int)floor(X[3 * p + k] - ext) - 1;
+            hi[k] = (int)ceil(X[3 * p + k] + ext) + 1;
+            if (hi[k] - lo[k] + 1 > n[k]) { lo[k] = 0; hi[k] = n[k] - 1; }
+        }
+        int zp = zper;
+        for (int kz = lo[2]; kz <= hi[2]; ++kz) {
+            if (!zp && (kz < 0 || kz >= nz)) continue;
+            int z = zp ? wrapi(kz, nz) : kz;
+            for (int ky = lo[1]; ky <= hi[1]; ++ky) {
+                int y = wrapi(ky, ny);
+                for (int kx = lo[0]; kx <= hi[0]; ++kx) {
+                    int x = wrapi(kx, nx);
+                    double c[3] = {(double)x, (double)y, (double)z};
+                    if (!or_cell_inside(c, X + 3 * p, t, length[p], radius[p], nx, ny, nz, zper))
+                        continue;
+                    int64_t idx = ((int64_t)z * ny + y) * nx + x;
+                    if (pid[idx] < 0) pid[idx] = p;
+                    else if (pid[idx] != p) ++ov; /* claimed twice: lowest id keeps it */
+                }
+            }
+        }
+    }
+    if (overlaps) *overlaps = ov;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Rigid-body update (Sec. 4.3).  The paper does not state the integrator;  */
+/* this oracle uses semi-implicit Euler with dt = 1:                        */
+/*   V' = V + F/m,  X' = X + V' (periodic wrap),                            */
+/*   Lang' = Lang + M (world-frame angular momentum),                       */
+/*   W' = I(q)^-1 Lang'  with I(q)^-1 = 1/I_perp + (1/I_par - 1/I_perp) t t^T */
+/*   q' = normalize(exp(W'/2) (x) q).                                       */
+/* ------------------------------------------------------------------------ */
+static void quat_mul(const double a[4], const double b[4], double out[4])
+{
+    double r[4];
+    r[0] = a[0] * b[0] - (a[1] * b[1] + a[2] * b[2] + a[3] * b[3]);
+    r[1] = a[0] * b[1] + b[0] * a[1] + (a[2] * b[3] - a[3] * b[2]);
+    r[2] = a[0] * b[2] + b[0] * a[2] + (a[3] * b[1] - a[1] * b[3]);
+    r[3] = a[0] * b[3] + b[0] * a[3] + (a[1] * b[2] - a[2] * b[1]);
+    memcpy(out, r, sizeof r);
+}
+
+static double wrap_pos(double x, int n, int periodic)
+{
+    if (!periodic) return x;
+    if (x >= n) return x - n;
+    if (x < 0.0) return x + n;
+    return x;
+}
+
+void or_rigid_step(const double *s, double mass, double i_par, double i_perp,
+                   const double F[3], const double M[3], int nx, int ny, int nz, int zper,
+                   double *out)
+{
+    const double *X = s, *q = s + 3, *V = s + 7, *La = s + 13;
+    double t[3];
+    or_fiber_axis(q, t);
+    double Vn[3], Xn[3], Ln[3], Wn[3];
+    int n[3] = {nx, ny, nz}, per[3] = {1, 1, zper};
+    for (int k = 0; k < 3; ++k) {
+        Vn[k] = V[k] + F[k] / mass;
+        Xn[k] = wrap_pos(X[k] + Vn[k], n[k], per[k]);
+        Ln[k] = La[k] + M[k];
+    }
+    double tl = t[0] * Ln[0] + t[1] * Ln[1] + t[2] * Ln[2];
+    for (int k = 0; k < 3; ++k) Wn[k] = Ln[k] / i_perp + (1.0 / i_par - 1.0 / i_perp) * tl * t[k];
+    double ang = sqrt(Wn[0] * Wn[0] + Wn[1] * Wn[1] + Wn[2] * Wn[2]);
+    double dq[4] = {1.0, 0.0, 0.0, 0.0};
+    if (ang > 0.0) {
+        double sh = sin(0.5 * ang) / ang;
+        dq[0] = cos(0.5 * ang);
+        dq[1] = sh * Wn[0];
+        dq[2] = sh * Wn[1];
+        dq[3] = sh * Wn[2];
+    }
+    double qn[4];
+    quat_mul(dq, q, qn);
+    double nrm = sqrt(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
+    for (int k = 0; k < 4; ++k) qn[k] /= nrm;
+    memcpy(out, Xn, sizeof Xn);
+    memcpy(out + 3, qn, sizeof qn);
+    memcpy(out + 7, Vn, sizeof Vn);
+    memcpy(out + 10, Wn, sizeof Wn);
+    memcpy(out + 13, Ln, sizeof Ln);
+}
+
+/* Solve the 6x6 system K x = b by Gaussian elimination with partial pivoting. */
+static void solve6(double K[6][6], double b[6], double x[6])
+{
+    for (int col = 0; col < 6; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 6; ++r)
+            if (fabs(K[r][col]) > fabs(K[piv][col])) piv = r;
+        if (piv != col) {
+            for (int c = 0; c < 6; ++c) { double t = K[col][c]; K[col][c] = K[piv][c]; K[piv][c] = t; }
+            double t = b[col]; b[col] = b[piv]; b[piv] = t;
+        }
+        for (int r = col + 1; r < 6; ++r) {
+            double fct = K[r][col] / K[col][col];
+            for (int c = col; c < 6; ++c) K[r][c] -= fct * K[col][c];
+            b[r] -= fct * b[col];
+        }
+    }
+    for (int r = 5; r >= 0; --r) {
+        double acc = b[r];
+        for (int c = r + 1; c < 6; ++c) acc -= K[r][c] * x[c];
+        x[r] = acc / K[r][r];
+    }
+}
+
+/* Implicit velocity update: the part of the momentum-exchange force that is  */
+/* linear in the surface velocity u_s = V + W x r is evaluated at the new     */
+/* velocities, giving the linear system                                      */
+/*   (m I + A) V' + B W'           = m V + F0                                */
+/*   B^T V'       + (I(q) + C) W'  = Lang + M0                               */
+/* after which X, Lang and q advance as in the explicit step.                */
+void or_rigid_step_implicit(const double *s, double mass, double i_par, double i_perp,
+                            const double F0[3], const double M0[3], const double *A,
+                            const double *B, const double *Cm, int nx, int ny, int nz,
+                            int zper, double *out, double *Fap, double *Map)
+{
+    const double *X = s, *q = s + 3, *V = s + 7, *La = s + 13;
+    double t[3];
+    or_fiber_axis(q, t);
+    double K[6][6], b[6], x[6];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double Iw = (i == j ? i_perp : 0.0) + (i_par - i_perp) * t[i] * t[j];
+            K[i][j] = (i == j ? mass : 0.0) + A[3 * i + j];
+            K[i][3 + j] = B[3 * i + j];
+            K[3 + i][j] = B[3 * j + i];
+            K[3 + i][3 + j] = Iw + Cm[3 * i + j];
+        }
+    for (int i = 0; i < 3; ++i) {
+        b[i] = mass * V[i] + F0[i];
+        b[3 + i] = La[i] + M0[i];
+    }
+    solve6(K, b, x);
+    double Vn[3] = {x[0], x[1], x[2]}, Wn[3] = {x[3], x[4], x[5]};
+    for (int i = 0; i < 3; ++i) {
+        double fa = F0[i], ma = M0[i];
+        for (int j = 0; j < 3; ++j) {
+            fa -= A[3 * i + j] * Vn[j] + B[3 * i + j] * Wn[j];
+            ma -= B[3 * j + i] * Vn[j] + Cm[3 * i + j] * Wn[j];
+        }
+        Fap[i] = fa;
+        Map[i] = ma;
+    }
+    int n[3] = {nx, ny, nz}, per[3] = {1, 1, zper};
+    double Xn[3], Ln[3];
+    for (int k = 0; k < 3; ++k) {
+        Xn[k] = wrap_pos(X[k] + Vn[k], n[k], per[k]);
+        Ln[k] = La[k] + Map[k];
+    }
+    double ang = sqrt(Wn[0] * Wn[0] + Wn[1] * Wn[1] + Wn[2] * Wn[2]);
+    double dq[4] = {1.0, 0.0, 0.0, 0.0};
+    if (ang > 0.0) {
+        double sh = sin(0.5 * ang) / ang;
+        dq[0] = cos(0.5 * ang);
+        dq[1] = sh * Wn[0];
+        dq[2] = sh * Wn[1];
+        dq[3] = sh * Wn[2];
+    }
+    double qn[4];
+    quat_mul(dq, q, qn);
+    double nrm = sqrt(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
+    for (int k = 0; k < 4; ++k) qn[k] /= nrm;
+    memcpy(out, Xn, sizeof Xn);
+    memcpy(out + 3, qn, sizeof qn);
+    memcpy(out + 7, Vn, sizeof Vn);
+    memcpy(out + 10, Wn, sizeof Wn);
+    memcpy(out + 13, Ln, sizeof Ln);
+}
+
+/* ------------------------------------------------------------------------ */
+/* The coupled simulation                                                   */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double st[16];          /* X3 q4 V3 W3 Lang3 */
+    double length, radius, mass, i_par, i_perp;
+    double F[3], M[3];
+    double *traj;           /* prescribed kinematics, 13 per step, or NULL */
+    int64_t traj_n, traj_pos;
+} fiber;
+
+struct or_sim {
+    or_params p;
+    double omega_e, omega_o;
+    int64_t ncell;
+    double *fa, *fb, *ft;   /* A, B, post-collision */
+    uint8_t *flag;          /* 0 fluid, 1 particle */
+    int32_t *pid;
+    int nf, capf;
+    fiber *fib;
+    int64_t steps, overlaps;
+    double *hist;           /* [steps][nf][HIST] */
+    int64_t hist_cap;
+};
+
+static int64_t cidx(const or_sim *s, int x, int y, int z)
+{
+    return ((int64_t)z * s->p.ny + y) * s->p.nx + x;
+}
+
+static double *slot(double *f, const or_sim *s, int q, int64_t c) { return f + (int64_t)q * s->ncell + c; }
+
+or_sim *or_create(const or_params *p)
+{
+    or_sim *s = (or_sim *)calloc(1, sizeof *s);
+    if (!s) return NULL;
+    s->p = *p;
+    s->omega_e = 1.0 / p->tau;
+    s->omega_o = or_omega_odd(p->tau, p->magic, p->srt);
+    s->ncell = (int64_t)p->nx * p->ny * p->nz;
+    size_t nf = (size_t)Q * s->ncell;
+    s->fa = (double *)malloc(nf * sizeof(double));
+    s->fb = (double *)malloc(nf * sizeof(double));
+    s->ft = (double *)malloc(nf * sizeof(double));
+    s->flag = (uint8_t *)calloc(s->ncell, 1);
+    s->pid = (int32_t *)malloc(s->ncell * sizeof(int32_t));
+    if (!s->fa || !s->fb || !s->ft || !s->flag || !s->pid) { or_destroy(s); return NULL; }
+    for (int64_t i = 0; i < s->ncell; ++i) s->pid[i] = -1;
+    /* initial state: f = f_eq(rho0, u0(z)) everywhere */
+    for (int z = 0; z < p->nz; ++z) {
+        double u[3] = {0.0, 0.0, 0.0}, feq[Q];
+        if (p->init_couette && !p->z_periodic) u[0] = p->wall_u * (2.0 * (z + 0.5) / p->nz - 1.0);
+        or_feq(p->rho0, p->rho0, u, feq);
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x)
+                for (int q = 0; q < Q; ++q) *slot(s->fa, s, q, cidx(s, x, y, z)) = feq[q];
+    }
+    memcpy(s->fb, s->fa, nf * sizeof(double));
+    return s;
+}
+
+void or_destroy(or_sim *s)
+{
+    if (!s) return;
+    free(s->fa); free(s->fb); free(s->ft); free(s->flag); free(s->pid);
+    for (int i = 0; i < s->nf; ++i) free(s->fib[i].traj);
+    free(s->fib); free(s->hist);
+    free(s);
+}
+
+/* remap all fibers with their current poses; returns overlaps counted */
+static int64_t remap(or_sim *s, int32_t *pid_out)
+{
+    int np = s->nf;
+    double *X = (double *)malloc((size_t)(3 * np + 4 * np + 2 * np + 1) * sizeof(double));
+    double *q = X + 3 * np, *L = q + 4 * np, *r = L + np;
+    for (int i = 0; i < np; ++i) {
+        memcpy(X + 3 * i, s->fib[i].st, 3 * sizeof(double));
+        memcpy(q + 4 * i, s->fib[i].st + 3, 4 * sizeof(double));
+        L[i] = s->fib[i].length;
+        r[i] = s->fib[i].radius;
+    }
+    int64_t ov = 0;
+    or_map(s->p.nx, s->p.ny, s->p.nz, s->p.z_periodic, np, X, q, L, r, pid_out, &ov);
+    free(X);
+    return ov;
+}
+
+/* velocity of particle p's rigid motion at a cell centre c: V + W x d(c, X) */
+static void surface_velocity(const or_sim *s, const double *st, int x, int y, int z, double us[3])
+{
+    const double *X = st, *V = st + 7, *W = st + 10;
+    double d[3];
+    d[0] = min_image(x - X[0], s->p.nx, 1);
+    d[1] = min_image(y - X[1], s->p.ny, 1);
+    d[2] = min_image(z - X[2], s->p.nz, s->p.z_periodic);
+    us[0] = V[0] + (W[1] * d[2] - W[2] * d[1]);
+    us[1] = V[1] + (W[2] * d[0] - W[0] * d[2]);
+    us[2] = V[2] + (W[0] * d[1] - W[1] * d[0]);
+}
+
+int or_add_fiber(or_sim *s, const double X[3], const double q[4], double length, double radius,
+                 double density_ratio, const double V[3], const double W[3])
+{
+    if (s->steps != 0) return -1;
+    if (s->nf == s->capf) {
+        int nc = s->capf ? 2 * s->capf : 8;
+        fiber *nfib = (fiber *)realloc(s->fib, nc * sizeof(fiber));
+        if (!nfib) return -1;
+        s->fib = nfib;
+        s->capf = nc;
+    }
+    fiber *f = &s->fib[s->nf];
+    memset(f, 0, sizeof *f);
+    double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int k = 0; k < 3; ++k) f->st[k] = X[k];
+    for (int k = 0; k < 4; ++k) f->st[3 + k] = q[k] / qn;
+    for (int k = 0; k < 3; ++k) f->st[7 + k] = V[k];
+    for (int k = 0; k < 3; ++k) f->st[10 + k] = W[k];
+    f->length = length;
+    f->radius = radius;
+    /* mass and inertia from the geometric cylinder, not the cell count */
+    double rho_p = density_ratio * s->p.rho0;
+    f->mass = rho_p * M_PI * radius * radius * length;
+    f->i_par = 0.5 * f->mass * radius * radius;
+    f->i_perp = f->mass * (3.0 * radius * radius + length * length) / 12.0;
+    double t[3];
+    or_fiber_axis(f->st + 3, t);
+    double tw = t[0] * W[0] + t[1] * W[1] + t[2] * W[2];
+    for (int k = 0; k < 3; ++k) f->st[13 + k] = f->i_perp * W[k] + (f->i_par - f->i_perp) * tw * t[k];
+    s->nf++;
+    int64_t ov = remap(s, s->pid);
+    if (ov > 0) { /* reject a fiber that overlaps another one */
+        s->nf--;
+        remap(s, s->pid);
+    }
+    for (int64_t i = 0; i < s->ncell; ++i) s->flag[i] = s->pid[i] >= 0;
+    return (ov > 0) ? -2 : s->nf - 1;
+}
+
+int or_set_kinematics(or_sim *s, int id, const double *traj, int64_t nsteps)
+{
+    if (id < 0 || id >= s->nf || nsteps < 0) return -1;
+    fiber *f = &s->fib[id];
+    free(f->traj);
+    f->traj = NULL;
+    f->traj_n = f->traj_pos = 0;
+    if (nsteps == 0) return 0;
+    f->traj = (double *)malloc((size_t)nsteps * 13 * sizeof(double));
+    memcpy(f->traj, traj, (size_t)nsteps * 13 * sizeof(double));
+    f->traj_n = nsteps;
+    return 0;
+}
+
+static void record(or_sim *s)
+{
+    int64_t need = (s->steps + 1) * s->nf * HIST;
+    if (need > s->hist_cap) {
+        int64_t nc = s->hist_cap ? 2 * s->hist_cap : 1024 * HIST;
+        while (nc < need) nc *= 2;
+        s->hist = (double *)realloc(s->hist, (size_t)nc * sizeof(double));
+        s->hist_cap = nc;
+    }
+    double *h = s->hist + s->steps * s->nf * HIST;
+    for (int i = 0; i < s->nf; ++i) {
+        fiber *f = &s->fib[i];
+        double *r = h + i * HIST;
+        memcpy(r, f->F, 3 * sizeof(double));
+        memcpy(r + 3, f->M, 3 * sizeof(double));
+        memcpy(r + 6, f->st, 13 * sizeof(double)); /* X q V W */
+    }
+}
+
+static void one_step(or_sim *s)
+{
+    const or_params *p = &s->p;
+    const int nx = p->nx, ny = p->ny, nz = p->nz;
+    const double rho0 = p->rho0;
+
+    /* 1. collide every fluid cell: fa -> ft */
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < s->ncell; ++c) {
+        if (s->flag[c]) continue;
+        double f[Q], fp[Q];
+        for (int q = 0; q < Q; ++q) f[q] = *slot(s->fa, s, q, c);
+        or_collide_cell(f, rho0, s->omega_e, s->omega_o, p->g, fp);
+        for (int q = 0; q < Q; ++q) *slot(s->ft, s, q, c) = fp[q];
+    }
+
+    /* 2. stream ft -> fb with bounce-back at walls and particle surfaces     */
+    /*    (Eqs. LBMStream, BBBC, LBMMovWall); every slot of fb is written by  */
+    /*    exactly one fluid cell, so the z-loop can run in parallel.          */
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                int64_t c = cidx(s, x, y, z);
+                if (s->flag[c]) continue;
+                *slot(s->fb, s, 0, c) = *slot(s->ft, s, 0, c);
+                for (int q = 1; q < Q; ++q) {
+                    int qb = opposite(q);
+                    double w = weight(q);
+                    double ft = *slot(s->ft, s, q, c);
+                    int yx = wrapi(x + CV[q][0], nx), yy = wrapi(y + CV[q][1], ny);
+                    int yz = z + CV[q][2];
+                    if (!p->z_periodic && (yz < 0 || yz >= nz)) {
+                        /* moving wall, half-way: bottom -U, top +U along x */
+                        double uw = (yz < 0) ? -p->wall_u : p->wall_u;
+                        *slot(s->fb, s, qb, c) = ft - 6.0 * w * rho0 * (CV[q][0] * uw);
+                        continue;
+                    }
+                    yz = wrapi(yz, nz);
+                    int64_t cy = cidx(s, yx, yy, yz);
+                    if (s->flag[cy]) {
+                        double us[3];
+                        surface_velocity(s, s->fib[s->pid[cy]].st, yx, yy, yz, us);
+                        double cu = CV[q][0] * us[0] + CV[q][1] * us[1] + CV[q][2] * us[2];
+                        *slot(s->fb, s, qb, c) = ft - 6.0 * w * rho0 * cu;
+                    } else {
+                        *slot(s->fb, s, q, cy) = ft;
+                    }
+                }
+            }
+
+    /* 2b. momentum exchange (Eq. LBMhydrodynForce).  Partial sums per      */
+    /*     z-plane, then added over z in order, so the result does not       */
+    /*     depend on the thread count.  Lever arm from the centre of mass to */
+    /*     the solid cell centre x_s; the torque is (x_s - x_C) x dF (the    */
+    /*     cross product written with the other operand order has the        */
+    /*     opposite sign).                                                   */
+    int nfb = s->nf;
+    /* per (z, fiber): F3 M3 (direct), F0 3, M0 3, A 9, B 9, C 9 */
+    double *part = (double *)calloc((size_t)nz * (nfb ? nfb : 1) * 39, sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                int64_t c = cidx(s, x, y, z);
+                if (s->flag[c] || nfb == 0) continue;
+                for (int q = 1; q < Q; ++q) {
+                    int yz = z + CV[q][2];
+                    if (!p->z_periodic && (yz < 0 || yz >= nz)) continue;
+                    int yx = wrapi(x + CV[q][0], nx), yy = wrapi(y + CV[q][1], ny);
+                    yz = wrapi(yz, nz);
+                    int64_t cy = cidx(s, yx, yy, yz);
+                    if (!s->flag[cy]) continue;
+                    int ip = s->pid[cy];
+                    const fiber *f = &s->fib[ip];
+                    double us[3];
+                    surface_velocity(s, f->st, yx, yy, yz, us);
+                    double cu = CV[q][0] * us[0] + CV[q][1] * us[1] + CV[q][2] * us[2];
+                    double ftq = *slot(s->ft, s, q, c);
+                    double mag = 2.0 * ftq - 6.0 * weight(q) * rho0 * cu;
+                    double dF[3] = {mag * CV[q][0], mag * CV[q][1], mag * CV[q][2]};
+                    double r[3];
+                    r[0] = min_image(yx - f->st[0], nx, 1);
+                    r[1] = min_image(yy - f->st[1], ny, 1);
+                    r[2] = min_image(yz - f->st[2], nz, p->z_periodic);
+                    double *acc = part + ((size_t)z * nfb + ip) * 39;
+                    /* direct formula, every term at the old velocity */
+                    for (int k = 0; k < 3; ++k) acc[k] += dF[k];
+                    acc[3] += r[1] * dF[2] - r[2] * dF[1];
+                    acc[4] += r[2] * dF[0] - r[0] * dF[2];
+                    acc[5] += r[0] * dF[1] - r[1] * dF[0];
+                    /* split for the implicit update: velocity-free part and the  */
+                    /* matrices of the part linear in u_s = V + W x r            */
+                    double m0 = 2.0 * ftq;
+                    double cq[3] = {(double)CV[q][0], (double)CV[q][1], (double)CV[q][2]};
+                    double rc[3] = {r[1] * cq[2] - r[2] * cq[1], r[2] * cq[0] - r[0] * cq[2],
+                                    r[0] * cq[1] - r[1] * cq[0]};
+                    double k6 = 6.0 * weight(q) * rho0;
+                    for (int k = 0; k < 3; ++k) {
+                        acc[6 + k] += m0 * cq[k];
+                        acc[9 + k] += m0 * rc[k];
+                    }
+                    for (int i = 0; i < 3; ++i)
+                        for (int j = 0; j < 3; ++j) {
+                            acc[12 + 3 * i + j] += k6 * cq[i] * cq[j];
+                            acc[21 + 3 * i + j] += k6 * cq[i] * rc[j];
+                            acc[30 + 3 * i + j] += k6 * rc[i] * rc[j];
+                        }
+                }
+            }
+    double *red = (double *)calloc((size_t)(nfb ? nfb : 1) * 39, sizeof(double));
+    for (int i = 0; i < nfb; ++i)
+        for (int z = 0; z < nz; ++z) {
+            const double *acc = part + ((size_t)z * nfb + i) * 39;
+            for (int k = 0; k < 39; ++k) red[39 * i + k] += acc[k];
+        }
+    free(part);
+
+    /* 3. rigid-body update; keep the old states for the refill             */
+    double *old = (double *)malloc((size_t)(s->nf ? s->nf : 1) * 16 * sizeof(double));
+    for (int i = 0; i < s->nf; ++i) {
+        fiber *f = &s->fib[i];
+        const double *rd = red + 39 * i;
+        memcpy(old + 16 * i, f->st, 16 * sizeof(double));
+        if (f->traj && f->traj_pos < f->traj_n) {
+            /* prescribed motion: the force reported is the direct formula */
+            memcpy(f->F, rd, 3 * sizeof(double));
+            memcpy(f->M, rd + 3, 3 * sizeof(double));
+            const double *tr = f->traj + 13 * f->traj_pos++;
+            memcpy(f->st, tr, 13 * sizeof(double));
+            double t[3];
+            or_fiber_axis(f->st + 3, t);
+            const double *Wp = f->st + 10;
+            double tw = t[0] * Wp[0] + t[1] * Wp[1] + t[2] * Wp[2];
+            for (int k = 0; k < 3; ++k)
+                f->st[13 + k] = f->i_perp * Wp[k] + (f->i_par - f->i_perp) * tw * t[k];
+        } else if (p->implicit) {
+            double out[16];
+            or_rigid_step_implicit(f->st, f->mass, f->i_par, f->i_perp, rd + 6, rd + 9, rd + 12,
+                                   rd + 21, rd + 30, nx, ny, nz, p->z_periodic, out, f->F, f->M);
+            memcpy(f->st, out, 16 * sizeof(double));
+        } else {
+            memcpy(f->F, rd, 3 * sizeof(double));
+            memcpy(f->M, rd + 3, 3 * sizeof(double));
+            double out[16];
+            or_rigid_step(f->st, f->mass, f->i_par, f->i_perp, f->F, f->M, nx, ny, nz,
+                          p->z_periodic, out);
+            memcpy(f->st, out, 16 * sizeof(double));
+        }
+    }
+    free(red);
+
+    /* 4. remap with the new poses; refill uncovered cells with             */
+    /*    f_eq(rho0, u_s) of the old owner's previous-step motion.          */
+    if (s->nf > 0) {
+        int32_t *pn = (int32_t *)malloc(s->ncell * sizeof(int32_t));
+        s->overlaps += remap(s, pn);
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    int64_t c = cidx(s, x, y, z);
+                    int po = s->pid[c];
+                    if (po >= 0 && pn[c] < 0) {
+                        double us[3], feq[Q];
+                        surface_velocity(s, old + 16 * po, x, y, z, us);
+                        or_feq(rho0, rho0, us, feq);
+                        for (int q = 0; q < Q; ++q) *slot(s->fb, s, q, c) = feq[q];
+                    }
+                    s->pid[c] = pn[c];
+                    s->flag[c] = pn[c] >= 0;
+                }
+        free(pn);
+    }
+    free(old);
+
+    /* 5. swap lattices, record the step */
+    double *tmp = s->fa;
+    s->fa = s->fb;
+    s->fb = tmp;
+    record(s);
+    s->steps++;
+}
+
+void or_step(or_sim *s, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) one_step(s);
+}
+
+void or_get_populations(const or_sim *s, double *f)
+{
+    memcpy(f, s->fa, (size_t)Q * s->ncell * sizeof(double));
+}
+
+void or_set_populations(or_sim *s, const double *f)
+{
+    memcpy(s->fa, f, (size_t)Q * s->ncell * sizeof(double));
+}
+
+void or_get_fields(const or_sim *s, double *rho, double *u, uint8_t *flags, int32_t *pid)
+{
+    const or_params *p = &s->p;
+    for (int z = 0; z < p->nz; ++z)
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                int64_t c = cidx(s, x, y, z);
+                double r = 0.0, j[3] = {0.0, 0.0, 0.0}, uc[3];
+                if (s->flag[c]) {
+                    r = p->rho0;
+                    surface_velocity(s, s->fib[s->pid[c]].st, x, y, z, uc);
+                } else {
+                    for (int q = 0; q < Q; ++q) {
+                        double fq = s->fa[(int64_t)q * s->ncell + c];
+                        r += fq;
+                        for (int k = 0; k < 3; ++k) j[k] += CV[q][k] * fq;
+                    }
+                    for (int k = 0; k < 3; ++k) uc[k] = j[k] / p->rho0 + 0.5 * p->g[k];
+                }
+                if (rho) rho[c] = r;
+                if (u)
+                    for (int k = 0; k < 3; ++k) u[(int64_t)k * s->ncell + c] = uc[k];
+                if (flags) flags[c] = s->flag[c];
+                if (pid) pid[c] = s->pid[c];
+            }
+}
+
+void or_get_fiber_state(const or_sim *s, double *X, double *q, double *V, double *W)
+{
+    for (int i = 0; i < s->nf; ++i) {
+        const double *st = s->fib[i].st;
+        if (X) memcpy(X + 3 * i, st, 3 * sizeof(double));
+        if (q) memcpy(q + 4 * i, st + 3, 4 * sizeof(double));
+        if (V) memcpy(V + 3 * i, st + 7, 3 * sizeof(double));
+        if (W) memcpy(W + 3 * i, st + 10, 3 * sizeof(double));
+    }
+}
+
+void or_get_force_torque(const or_sim *s, double *F, double *M)
+{
+    for (int i = 0; i < s->nf; ++i) {
+        if (F) memcpy(F + 3 * i, s->fib[i].F, 3 * sizeof(double));
+        if (M) memcpy(M + 3 * i, s->fib[i].M, 3 * sizeof(double));
+    }
+}
+
+int64_t or_get_history(const or_sim *s, int64_t first, int64_t count, double *out)
+{
+    if (first < 0 || first >= s->steps) return 0;
+    if (first + count > s->steps) count = s->steps - first;
+    memcpy(out, s->hist + first * s->nf * HIST, (size_t)(count * s->nf * HIST) * sizeof(double));
+    return count;
+}
+
+int64_t or_overlaps(const or_sim *s) { return s->overlaps; }
+int64_t or_steps_done(const or_sim *s) { return s->steps; }
+int or_nfibers(const or_sim *s) { return s->nf; }

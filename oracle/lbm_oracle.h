@@ -1,0 +1,99 @@
+/*
+ * lbm_oracle.h -- plain FP64 CPU oracle for the coupled D3Q19 lattice
+ * Boltzmann / momentum-exchange / rigid-fiber method of Bartuschat,
+ * Fischermeier, Gustavsson and Ruede, "Two computational models for
+ * simulating the tumbling motion of elongated particles in fluids" (2015).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This oracle exists so that the GPU library can
+ * be checked against an obviously correct implementation.  Only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark may load
+ * it.  It shares no source with the GPU library: its own lattice tables,
+ * its own equilibrium, its own mapping predicate and its own integrator.
+ *
+ * Storage: two lattices A and B (double, layout f[q][z][y][x]), push
+ * streaming A -> B, then swap.  Lattice units throughout (dx = dt = 1,
+ * c_s^2 = 1/3).  Cell centres sit at integer coordinates.
+ *
+ * Step order (the paper only outlines the coupling in Sec. 4.3):
+ *   1. TRT/SRT collision of every fluid cell          (Sec. 4.1, Eq. LBMCollide)
+ *   2. streaming with half-way bounce-back at moving walls and at moving
+ *      particle surfaces, plus the momentum-exchange force and torque
+ *                                                      (Eqs. LBMStream, BBBC,
+ *                                                       LBMMovWall,
+ *                                                       LBMhydrodynForce)
+ *   3. rigid-body update of every fiber                (Sec. 4.3)
+ *   4. re-mapping of cells and refill of uncovered cells (Sec. 4.2)
+ */
+#ifndef LBM_ORACLE_H
+#define LBM_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct or_sim or_sim;
+
+typedef struct {
+    int nx, ny, nz;
+    int z_periodic;    /* 1: periodic in z; 0: moving walls half-way below z=0 and above z=nz-1 */
+    int srt;           /* 1: single relaxation time (omega_o = omega_e); 0: TRT */
+    double tau;        /* relaxation time of the even moments, omega_e = 1/tau */
+    double magic;      /* TRT parameter Lambda = (1/omega_e - 1/2)(1/omega_o - 1/2) */
+    double rho0;       /* mean density */
+    double wall_u;     /* wall velocity along x: top wall +U, bottom wall -U */
+    double g[3];       /* body-force acceleration (Poiseuille / drag tests only) */
+    int init_couette;  /* 1: start from the linear Couette profile; 0: fluid at rest */
+    int implicit;      /* 1: velocity-dependent part of the bounce-back force taken at the
+                          new particle velocity (solid-particle scheme of Nguyen and Ladd);
+                          0: fully explicit, every term at the old velocity */
+} or_params;
+
+/* ---- building blocks (exposed so the tests can pin them one by one) ---- */
+void   or_lattice(int32_t *c /*[19*3]*/, double *w /*[19]*/, int32_t *opp /*[19]*/);
+void   or_feq(double rho, double rho0, const double u[3], double *feq /*[19]*/);
+double or_omega_odd(double tau, double magic, int srt);
+void   or_collide_cell(const double *f, double rho0, double omega_e, double omega_o,
+                       const double g[3], double *fpost);
+void   or_fiber_axis(const double q[4], double t[3]);
+int    or_cell_inside(const double c[3], const double X[3], const double t[3],
+                      double length, double radius, int nx, int ny, int nz, int zper);
+void   or_map(int nx, int ny, int nz, int zper, int np, const double *X, const double *q,
+              const double *length, const double *radius, int32_t *pid, int64_t *overlaps);
+/* one semi-implicit Euler step; state = X[3] q[4] V[3] W[3] Lang[3] */
+void   or_rigid_step(const double *state, double mass, double i_par, double i_perp,
+                     const double F[3], const double M[3], int nx, int ny, int nz, int zper,
+                     double *state_out);
+
+/* implicit variant: F = F0 - A V' - B W', M = M0 - B^T V' - C W' with the
+   new velocities V', W'; A, C symmetric 3x3 (row-major 9 each), B 3x3.
+   Writes the new state and the force/torque actually applied. */
+void   or_rigid_step_implicit(const double *state, double mass, double i_par, double i_perp,
+                              const double F0[3], const double M0[3], const double *A,
+                              const double *B, const double *Cm, int nx, int ny, int nz,
+                              int zper, double *state_out, double *F_applied,
+                              double *M_applied);
+
+/* ---- the coupled simulation ---- */
+or_sim *or_create(const or_params *p);
+void    or_destroy(or_sim *s);
+int     or_add_fiber(or_sim *s, const double X[3], const double q[4], double length,
+                     double radius, double density_ratio, const double V[3], const double W[3]);
+int     or_set_kinematics(or_sim *s, int id, const double *traj /*[nsteps][13]*/, int64_t nsteps);
+void    or_step(or_sim *s, int64_t n);
+void    or_get_populations(const or_sim *s, double *f /*[19][nz][ny][nx]*/);
+void    or_set_populations(or_sim *s, const double *f);
+void    or_get_fields(const or_sim *s, double *rho, double *u /*[3][nz][ny][nx]*/,
+                      uint8_t *flags, int32_t *pid);
+void    or_get_fiber_state(const or_sim *s, double *X, double *q, double *V, double *W);
+void    or_get_force_torque(const or_sim *s, double *F, double *M);
+int64_t or_get_history(const or_sim *s, int64_t first, int64_t count, double *out);
+int64_t or_overlaps(const or_sim *s);
+int64_t or_steps_done(const or_sim *s);
+int     or_nfibers(const or_sim *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,228 @@
+"""ctypes wrapper of the FP64 CPU oracle (oracle/lbm_oracle.c).
+
+TEST INFRASTRUCTURE ONLY (tests, the smoke check, the benchmark's CPU
+baseline).  Arrays are numpy float64 / uint8 / int32 in the layout
+[component][z][y][x] with x fastest; populations are [19][z][y][x] in the
+oracle's own velocity order (see ``lattice()``).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_u8p = C.POINTER(C.c_uint8)
+_i64p = C.POINTER(C.c_int64)
+
+
+class Params(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("z_periodic", C.c_int), ("srt", C.c_int),
+                ("tau", C.c_double), ("magic", C.c_double), ("rho0", C.c_double),
+                ("wall_u", C.c_double), ("g", C.c_double * 3), ("init_couette", C.c_int),
+                ("implicit", C.c_int)]
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(path)
+        L.or_lattice.argtypes = [_ip, _dp, _ip]
+        L.or_feq.argtypes = [C.c_double, C.c_double, _dp, _dp]
+        L.or_omega_odd.argtypes = [C.c_double, C.c_double, C.c_int]
+        L.or_omega_odd.restype = C.c_double
+        L.or_collide_cell.argtypes = [_dp, C.c_double, C.c_double, C.c_double, _dp, _dp]
+        L.or_fiber_axis.argtypes = [_dp, _dp]
+        L.or_cell_inside.argtypes = [_dp, _dp, _dp, C.c_double, C.c_double,
+                                     C.c_int, C.c_int, C.c_int, C.c_int]
+        L.or_map.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _dp,
+                             _ip, _i64p]
+        L.or_rigid_step.argtypes = [_dp, C.c_double, C.c_double, C.c_double, _dp, _dp,
+                                    C.c_int, C.c_int, C.c_int, C.c_int, _dp]
+        L.or_rigid_step_implicit.argtypes = [_dp, C.c_double, C.c_double, C.c_double, _dp,
+                                             _dp, _dp, _dp, _dp, C.c_int, C.c_int, C.c_int,
+                                             C.c_int, _dp, _dp, _dp]
+        L.or_create.argtypes = [C.POINTER(Params)]
+        L.or_create.restype = C.c_void_p
+        L.or_destroy.argtypes = [C.c_void_p]
+        L.or_add_fiber.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_double, C.c_double,
+                                   _dp, _dp]
+        L.or_set_kinematics.argtypes = [C.c_void_p, C.c_int, _dp, C.c_int64]
+        L.or_step.argtypes = [C.c_void_p, C.c_int64]
+        L.or_get_populations.argtypes = [C.c_void_p, _dp]
+        L.or_set_populations.argtypes = [C.c_void_p, _dp]
+        L.or_get_fields.argtypes = [C.c_void_p, _dp, _dp, _u8p, _ip]
+        L.or_get_fiber_state.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
+        L.or_get_force_torque.argtypes = [C.c_void_p, _dp, _dp]
+        L.or_get_history.argtypes = [C.c_void_p, C.c_int64, C.c_int64, _dp]
+        L.or_get_history.restype = C.c_int64
+        L.or_overlaps.argtypes = [C.c_void_p]
+        L.or_overlaps.restype = C.c_int64
+        L.or_steps_done.argtypes = [C.c_void_p]
+        L.or_steps_done.restype = C.c_int64
+        L.or_nfibers.argtypes = [C.c_void_p]
+        _LIB = L
+    return _LIB
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _arr(x, n=None):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    if n is not None:
+        assert a.size == n, (a.size, n)
+    return a
+
+
+# ---------------------------------------------------------------- building blocks
+def lattice():
+    c = np.zeros(57, np.int32)
+    w = np.zeros(19)
+    opp = np.zeros(19, np.int32)
+    lib().or_lattice(c.ctypes.data_as(_ip), _d(w), opp.ctypes.data_as(_ip))
+    return c.reshape(19, 3), w, opp
+
+
+def feq(rho, rho0, u):
+    out = np.zeros(19)
+    lib().or_feq(rho, rho0, _d(_arr(u, 3)), _d(out))
+    return out
+
+
+def omega_odd(tau, magic, srt=False):
+    return lib().or_omega_odd(tau, magic, int(srt))
+
+
+def collide_cell(f, rho0, omega_e, omega_o, g=(0.0, 0.0, 0.0)):
+    out = np.zeros(19)
+    lib().or_collide_cell(_d(_arr(f, 19)), rho0, omega_e, omega_o, _d(_arr(g, 3)), _d(out))
+    return out
+
+
+def fiber_axis(q):
+    t = np.zeros(3)
+    lib().or_fiber_axis(_d(_arr(q, 4)), _d(t))
+    return t
+
+
+def map_fibers(shape, X, q, length, radius, z_periodic=False):
+    """shape = (nx, ny, nz); returns (pid[nz][ny][nx], overlaps)."""
+    nx, ny, nz = shape
+    X = _arr(X).reshape(-1, 3)
+    n = X.shape[0]
+    pid = np.zeros((nz, ny, nx), np.int32)
+    ov = np.zeros(1, np.int64)
+    lib().or_map(nx, ny, nz, int(z_periodic), n, _d(X), _d(_arr(q, 4 * n)),
+                 _d(_arr(length, n)), _d(_arr(radius, n)), pid.ctypes.data_as(_ip),
+                 ov.ctypes.data_as(_i64p))
+    return pid, int(ov[0])
+
+
+def rigid_step(state, mass, i_par, i_perp, F, M, shape=(1 << 20, 1 << 20, 1 << 20),
+               z_periodic=True):
+    """state = X3 q4 V3 W3 Lang3 (16 doubles) -> new state."""
+    out = np.zeros(16)
+    nx, ny, nz = shape
+    lib().or_rigid_step(_d(_arr(state, 16)), mass, i_par, i_perp, _d(_arr(F, 3)),
+                        _d(_arr(M, 3)), nx, ny, nz, int(z_periodic), _d(out))
+    return out
+
+
+# ---------------------------------------------------------------- coupled simulation
+class Sim:
+    """One coupled simulation held by the oracle."""
+
+    def __init__(self, nx, ny, nz, tau=0.8, magic=3.0 / 16.0, wall_u=0.0, rho0=1.0,
+                 z_periodic=False, srt=False, g=(0.0, 0.0, 0.0), init_couette=False,
+                 implicit=True):
+        p = Params(nx, ny, nz, int(z_periodic), int(srt), tau, magic, rho0, wall_u,
+                   (C.c_double * 3)(*g), int(init_couette), int(implicit))
+        self.shape = (nx, ny, nz)
+        self.ncell = nx * ny * nz
+        self._h = lib().or_create(C.byref(p))
+        if not self._h:
+            raise MemoryError("oracle allocation failed")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().or_destroy(h)
+            self._h = None
+
+    def add_fiber(self, X, q, length, radius, density_ratio=1.0, V=(0, 0, 0), W=(0, 0, 0)):
+        r = lib().or_add_fiber(self._h, _d(_arr(X, 3)), _d(_arr(q, 4)), float(length),
+                               float(radius), float(density_ratio), _d(_arr(V, 3)),
+                               _d(_arr(W, 3)))
+        if r < 0:
+            raise ValueError("oracle rejected the fiber (code %d)" % r)
+        return r
+
+    def set_kinematics(self, fid, traj):
+        t = _arr(traj).reshape(-1, 13)
+        lib().or_set_kinematics(self._h, fid, _d(t), t.shape[0])
+
+    def step(self, n=1):
+        lib().or_step(self._h, int(n))
+
+    @property
+    def nfibers(self):
+        return lib().or_nfibers(self._h)
+
+    @property
+    def steps_done(self):
+        return lib().or_steps_done(self._h)
+
+    @property
+    def overlaps(self):
+        return lib().or_overlaps(self._h)
+
+    def populations(self):
+        nx, ny, nz = self.shape
+        f = np.zeros((19, nz, ny, nx))
+        lib().or_get_populations(self._h, _d(f))
+        return f
+
+    def set_populations(self, f):
+        f = _arr(f, 19 * self.ncell)
+        lib().or_set_populations(self._h, _d(f))
+
+    def fields(self):
+        nx, ny, nz = self.shape
+        rho = np.zeros((nz, ny, nx))
+        u = np.zeros((3, nz, ny, nx))
+        flags = np.zeros((nz, ny, nx), np.uint8)
+        pid = np.zeros((nz, ny, nx), np.int32)
+        lib().or_get_fields(self._h, _d(rho), _d(u), flags.ctypes.data_as(_u8p),
+                            pid.ctypes.data_as(_ip))
+        return rho, u, flags, pid
+
+    def fiber_state(self):
+        n = self.nfibers
+        X, q, V, W = np.zeros((n, 3)), np.zeros((n, 4)), np.zeros((n, 3)), np.zeros((n, 3))
+        lib().or_get_fiber_state(self._h, _d(X), _d(q), _d(V), _d(W))
+        return X, q, V, W
+
+    def force_torque(self):
+        n = self.nfibers
+        F, M = np.zeros((n, 3)), np.zeros((n, 3))
+        lib().or_get_force_torque(self._h, _d(F), _d(M))
+        return F, M
+
+    def history(self, first=0, count=None):
+        """[steps][nfibers][19]: F3 M3 X3 q4 V3 W3 after each step."""
+        n = self.nfibers
+        if count is None:
+            count = self.steps_done - first
+        out = np.zeros((max(count, 0), n, 19))
+        got = lib().or_get_history(self._h, first, count, _d(out))
+        return out[:got]

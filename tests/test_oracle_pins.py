@@ -1,0 +1,441 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the passage it follows.  None of these re-types the oracle's
+own formula: they check identities, closed forms, conservation laws,
+symmetries, hand counts and exact steady-state balances, chosen so that a
+dropped term, a wrong sign or index or a transposed operand fails one of them.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import pyoracle as O
+
+RNG = np.random.default_rng(1234)
+
+
+# ---------------------------------------------------------------- P1 lattice
+def test_lattice_tables_exact():
+    """D3Q19 (Sec. 4.1, Eq. SpeedOfSound and weights): exact rational moments
+    sum w = 1, sum w c = 0, sum w c_a c_b = d_ab/3,
+    sum w c_a c_b c_c c_d = (d_ab d_cd + d_ac d_bd + d_ad d_bc)/9."""
+    c, w, opp = O.lattice()
+    wf = [Fraction(int(round(x * 36)), 36) for x in w]
+    for q in range(19):
+        assert float(wf[q]) == w[q]
+    assert sum(wf) == 1
+    assert sorted(set(int(np.abs(ci).sum()) for ci in c)) == [0, 1, 2]
+    assert wf.count(Fraction(1, 3)) == 1 and wf.count(Fraction(1, 18)) == 6
+    assert wf.count(Fraction(1, 36)) == 12
+    for a in range(3):
+        assert sum(wf[q] * int(c[q, a]) for q in range(19)) == 0
+        for b in range(3):
+            m2 = sum(wf[q] * int(c[q, a]) * int(c[q, b]) for q in range(19))
+            assert m2 == (Fraction(1, 3) if a == b else 0)
+            for cc in range(3):
+                m3 = sum(wf[q] * int(c[q, a] * c[q, b] * c[q, cc]) for q in range(19))
+                assert m3 == 0
+                for d in range(3):
+                    m4 = sum(wf[q] * int(c[q, a] * c[q, b] * c[q, cc] * c[q, d])
+                             for q in range(19))
+                    exp = Fraction((a == b) * (cc == d) + (a == cc) * (b == d)
+                                   + (a == d) * (b == cc), 9)
+                    assert m4 == exp
+    for q in range(19):
+        assert np.all(c[opp[q]] == -c[q])
+        assert w[opp[q]] == w[q]
+
+
+# ---------------------------------------------------------------- P2 equilibrium
+def test_equilibrium_moments():
+    """He-Luo equilibrium (Eq. fequ_Incompr) and the moments after it:
+    sum f_eq = rho, sum c f_eq = rho0 u, sum c_a c_b f_eq = rho d_ab/3 + rho0 u_a u_b."""
+    c, w, _ = O.lattice()
+    for _ in range(20):
+        rho = 1.0 + 0.01 * RNG.standard_normal()
+        rho0 = 1.0
+        u = 0.05 * RNG.standard_normal(3)
+        fe = O.feq(rho, rho0, u)
+        assert abs(fe.sum() - rho) < 1e-15
+        np.testing.assert_allclose(c.T @ fe, rho0 * u, rtol=0, atol=1e-16)
+        P = np.einsum("q,qa,qb->ab", fe, c, c)
+        np.testing.assert_allclose(P, rho * np.eye(3) / 3 + rho0 * np.outer(u, u),
+                                   rtol=0, atol=2e-16)
+
+
+def test_equilibrium_even_odd_split():
+    """Eq. EqPDF_TRT: f_eq,e = w(rho - 3/2 rho0 u.u + 9/2 rho0 (c.u)^2) is the
+    symmetric part and f_eq,o = 3 w rho0 c.u the antisymmetric part of f_eq."""
+    c, w, opp = O.lattice()
+    u = np.array([0.03, -0.02, 0.01])
+    fe = O.feq(1.01, 1.0, u)
+    even = 0.5 * (fe + fe[opp])
+    odd = 0.5 * (fe - fe[opp])
+    np.testing.assert_allclose(odd, 3 * w * (c @ u), atol=1e-17)
+    np.testing.assert_allclose(even, w * (1.01 - 1.5 * u @ u + 4.5 * (c @ u) ** 2),
+                               atol=1e-17)
+
+
+# ---------------------------------------------------------------- P3 collision
+def test_collision_conserves_mass_and_momentum():
+    """Eq. LBMCollide with the TRT operator: rho and sum c f are collision
+    invariants; with a body force the momentum grows by exactly rho0 g."""
+    c, w, _ = O.lattice()
+    for tau in (0.55, 0.8, 1.7):
+        we = 1.0 / tau
+        wo = O.omega_odd(tau, 3.0 / 16.0)
+        for _ in range(10):
+            f = O.feq(1.0, 1.0, 0.03 * RNG.standard_normal(3)) + 1e-3 * RNG.standard_normal(19)
+            fp = O.collide_cell(f, 1.0, we, wo)
+            assert abs(fp.sum() - f.sum()) < 1e-15
+            np.testing.assert_allclose(c.T @ fp, c.T @ f, atol=1e-16)
+            g = np.array([1e-5, -2e-5, 3e-6])
+            fg = O.collide_cell(f, 1.0, we, wo, g)
+            assert abs(fg.sum() - f.sum()) < 1e-15
+            np.testing.assert_allclose(c.T @ fg - c.T @ f, g, atol=1e-16)
+
+
+def test_trt_rates_act_on_even_and_odd_parts():
+    """Eq. TRTOp: a non-equilibrium perturbation that is symmetric under
+    q -> q_bar relaxes with omega_e, an antisymmetric one with omega_o
+    (both chosen to leave rho and the momentum unchanged)."""
+    c, w, opp = O.lattice()
+    tau = 0.8
+    we, wo = 1.0 / tau, O.omega_odd(tau, 3.0 / 16.0)
+    base = O.feq(1.0, 1.0, np.zeros(3))
+    eps = 1e-4
+    de = np.zeros(19)
+    for q in range(19):
+        if tuple(c[q]) in [(1, 0, 0), (-1, 0, 0)]:
+            de[q] = eps
+        if tuple(c[q]) in [(0, 1, 0), (0, -1, 0)]:
+            de[q] = -eps
+    do = np.zeros(19)
+    for q in range(19):
+        t = tuple(c[q])
+        do[q] = {(1, 0, 0): 2 * eps, (-1, 0, 0): -2 * eps, (1, 1, 0): -eps, (-1, -1, 0): eps,
+                 (1, -1, 0): -eps, (-1, 1, 0): eps}.get(t, 0.0)
+    assert abs(de.sum()) == 0 and np.all(c.T @ do == 0) and np.all(do[opp] == -do)
+    np.testing.assert_allclose(O.collide_cell(base + de, 1.0, we, wo) - base, (1 - we) * de,
+                               atol=2e-16)
+    np.testing.assert_allclose(O.collide_cell(base + do, 1.0, we, wo) - base, (1 - wo) * do,
+                               atol=2e-16)
+
+
+# ---------------------------------------------------------------- P4 magic
+def test_magic_parameter():
+    """Sec. 4.1: lambda_o = -8(2 - omega)/(8 - omega) puts walls half-way; it is
+    the Lambda = 3/16 member of (1/omega_e - 1/2)(1/omega_o - 1/2) = Lambda.
+    For tau = 0.8: omega_o = 8/9."""
+    assert abs(O.omega_odd(0.8, 3.0 / 16.0) - 8.0 / 9.0) < 1e-15
+    for tau in (0.51, 0.6, 0.8, 1.0, 1.5, 3.0):
+        om = 1.0 / tau
+        assert abs(O.omega_odd(tau, 3.0 / 16.0) - 8 * (2 - om) / (8 - om)) < 1e-14
+        assert O.omega_odd(tau, 3.0 / 16.0, srt=True) == om
+
+
+# ---------------------------------------------------------------- P5 rest
+def test_rest_state_is_kept():
+    """Fluid at rest between resting walls stays f = w rho0 (Eq. BBBC); the
+    oracle holds absolute populations, so only to rounding (sum w != 1 in
+    binary floating point)."""
+    s = O.Sim(6, 5, 8, tau=0.8, wall_u=0.0)
+    s.step(400)
+    f = s.populations()
+    _, w, _ = O.lattice()
+    assert np.abs(f - w[:, None, None, None]).max() < 1e-15
+    _, u, _, _ = s.fields()
+    assert np.abs(u).max() < 1e-15
+
+
+# ---------------------------------------------------------------- P6 mass
+@pytest.mark.parametrize("zper,wall_u", [(True, 0.0), (False, 0.01)])
+def test_mass_conservation(zper, wall_u):
+    """Streaming moves populations and collision keeps rho; bounce-back at
+    walls moving tangentially returns what it receives (the wall term
+    -6 w rho0 c.u_w cancels between q and its mirror in each cell)."""
+    nx, ny, nz = 6, 5, 8
+    s = O.Sim(nx, ny, nz, tau=0.7, wall_u=wall_u, z_periodic=zper)
+    f = s.populations() + 1e-3 * RNG.random((19, nz, ny, nx))
+    s.set_populations(f)
+    m0 = f.sum()
+    s.step(200)
+    assert abs(s.populations().sum() - m0) / m0 < 1e-13
+
+
+# ---------------------------------------------------------------- P7 Couette
+def test_couette_closed_form():
+    """Plane Couette flow between walls half-way below z = 0 and above
+    z = nz - 1 moving at -U and +U: u_x(z) = U (2 (z + 1/2)/nz - 1), exact
+    for half-way bounce-back (Eq. LBMMovWall applied to a wall)."""
+    nz, U = 32, 0.005
+    s = O.Sim(4, 4, nz, tau=0.8, wall_u=U)
+    s.step(30000)
+    _, u, _, _ = s.fields()
+    z = np.arange(nz)
+    exact = U * (2 * (z + 0.5) / nz - 1)
+    assert np.abs(u[0, :, 0, 0] - exact).max() < 1e-10 * U / U
+    assert np.abs(u[1:]).max() < 1e-12
+
+
+# ---------------------------------------------------------------- P8 Poiseuille
+def test_poiseuille_closed_form_trt_magic():
+    """Body-force driven channel flow: u_x = g (z+1/2)(nz-z-1/2) / (2 nu),
+    nu = (tau - 1/2)/3 (Eq. kinVisc).  With the TRT magic value the parabola
+    is reproduced exactly with the walls half-way (Sec. 4.1)."""
+    nz, g, tau = 32, 1e-6, 0.8
+    nu = (tau - 0.5) / 3
+    s = O.Sim(4, 4, nz, tau=tau, g=(g, 0, 0))
+    s.step(40000)
+    _, u, _, _ = s.fields()
+    z = np.arange(nz)
+    exact = g * (z + 0.5) * (nz - z - 0.5) / (2 * nu)
+    assert np.abs(u[0, :, 0, 0] - exact).max() / exact.max() < 1e-10
+
+
+def test_poiseuille_srt_wall_error_is_second_order():
+    """With SRT the wall location depends on tau (Sec. 4.1), so the parabola
+    carries an error that falls like nz^-2."""
+    tau = 0.8
+    nu = (tau - 0.5) / 3
+    errs = []
+    for nz in (8, 16):
+        g = 1e-6 * (32.0 / nz) ** 2
+        s = O.Sim(2, 2, nz, tau=tau, g=(g, 0, 0), srt=True)
+        s.step(int(12 * nz * nz / nu))
+        _, u, _, _ = s.fields()
+        z = np.arange(nz)
+        exact = g * (z + 0.5) * (nz - z - 0.5) / (2 * nu)
+        errs.append(np.abs(u[0, :, 0, 0] - exact).max() / exact.max())
+    assert errs[0] > 1e-4
+    assert 3.3 < errs[0] / errs[1] < 4.7
+
+
+# ---------------------------------------------------------------- P9 viscosity
+def test_shear_wave_decay_rate():
+    """A periodic shear wave u_x = A sin(kz) decays like exp(-nu k^2 t) with
+    nu = (tau - 1/2) c_s^2 (Eq. kinVisc)."""
+    nz, A, tau = 64, 1e-4, 0.8
+    nu, k = (tau - 0.5) / 3, 2 * np.pi / 64
+    s = O.Sim(2, 2, nz, tau=tau, z_periodic=True)
+    f = np.zeros((19, nz, 2, 2))
+    for z in range(nz):
+        f[:, z] = O.feq(1.0, 1.0, (A * np.sin(k * z), 0, 0))[:, None, None]
+    s.set_populations(f)
+    s.step(500)
+
+    def amp():
+        _, u, _, _ = s.fields()
+        return (u[0, :, 0, 0] * np.sin(k * np.arange(nz))).sum() * 2 / nz
+
+    a0 = amp()
+    s.step(1000)
+    a1 = amp()
+    rate = -np.log(a1 / a0) / 1000
+    assert abs(rate / (nu * k * k) - 1) < 1e-3
+
+
+# ---------------------------------------------------------------- P14 mapping
+def test_mapping_hand_counted():
+    """Sec. 4.2: a cell is an obstacle cell when its centre lies inside the
+    particle.  Cylinder along x, centre on a cell centre, L = 6, r = 1.5:
+    7 cells along the axis (|a| <= 3) times the 9 cells with dy^2+dz^2 <= 2.25."""
+    pid, ov = O.map_fibers((16, 12, 12), [[8, 6, 6]], [1, 0, 0, 0], [6.0], [1.5])
+    assert ov == 0 and (pid == 0).sum() == 63
+    zz, yy, xx = np.nonzero(pid == 0)
+    assert set(xx) == set(range(5, 12))
+    # along z (rotation by +90 deg about y maps e_x to -e_z): same count
+    q = [np.cos(np.pi / 4), 0, np.sin(np.pi / 4), 0]
+    np.testing.assert_allclose(O.fiber_axis(q), [0, 0, -1], atol=1e-15)
+    pid, _ = O.map_fibers((12, 12, 16), [[6, 6, 8]], q, [6.0], [1.5])
+    assert (pid == 0).sum() == 63
+    # radius just below 1: only the axis row
+    pid, _ = O.map_fibers((16, 12, 12), [[8, 6, 6]], [1, 0, 0, 0], [6.0], [0.99])
+    assert (pid == 0).sum() == 7
+
+
+def test_mapping_volume_converges():
+    """Obstacle cell count approaches the cylinder volume pi r^2 L as the
+    resolution grows (staircase approximation, Sec. 4.2)."""
+    t = np.array([0.6, 0.48, 0.64])
+    ax = np.cross([1.0, 0, 0], t)
+    ang = np.arccos(t[0])
+    ax /= np.linalg.norm(ax)
+    q = np.r_[np.cos(ang / 2), np.sin(ang / 2) * ax]
+    np.testing.assert_allclose(O.fiber_axis(q), t, atol=1e-14)
+    errs = []
+    for scale in (2, 4, 8):
+        L, r = 6.0 * scale, 1.0 * scale
+        n = int(L + 4 * r + 8)
+        pid, _ = O.map_fibers((n, n, n), [[n / 2 + 0.3, n / 2 - 0.2, n / 2 + 0.1]], q, [L], [r])
+        errs.append(abs((pid == 0).sum() / (np.pi * r * r * L) - 1))
+    assert errs[-1] < 0.02 and errs[-1] < errs[0]
+
+
+def test_mapping_periodic_translation():
+    """Minimum image in x and y: a fiber straddling the periodic boundary maps
+    to the same cell set as the unwrapped one, shifted."""
+    q = np.array([0.9, 0.1, -0.3, 0.2])
+    q /= np.linalg.norm(q)
+    pid_a, _ = O.map_fibers((24, 20, 20), [[12.3, 10.2, 9.7]], q, [14.0], [2.0])
+    pid_b, _ = O.map_fibers((24, 20, 20), [[0.3, 0.2, 9.7]], q, [14.0], [2.0])
+    assert np.array_equal(np.roll(np.roll(pid_a, -12, axis=2), -10, axis=1), pid_b)
+
+
+def test_mapping_overlap_lowest_id_wins():
+    """Two crossing fibers: shared cells go to the lowest id and are counted."""
+    pid, ov = O.map_fibers((20, 20, 20), [[10, 10, 10], [10, 10, 10]],
+                           [1, 0, 0, 0, np.cos(np.pi / 4), 0, 0, np.sin(np.pi / 4)],
+                           [8.0, 8.0], [1.5, 1.5])
+    assert ov > 0 and pid[10, 10, 10] == 0
+    assert (pid == 0).sum() == 81 and (pid == 1).sum() + ov == 81  # 9 x 9 cells each
+
+
+# ---------------------------------------------------------------- P13 rigid body
+def test_quaternion_update_constant_rotation():
+    """Rigid update (Sec. 4.3; integrator is this project's reading): with no
+    force and torque and W perpendicular to the axis, W stays constant and
+    the orientation after n steps is the rotation by n|W| about W."""
+    W = np.array([0.0, 0.013, 0.0])
+    st = np.zeros(16)
+    st[3] = 1.0
+    m, ipar, iperp = 10.0, 2.0, 30.0
+    st[10:13] = W
+    st[13:16] = iperp * W
+    for _ in range(500):
+        st = O.rigid_step(st, m, ipar, iperp, np.zeros(3), np.zeros(3))
+    th = 500 * 0.013
+    np.testing.assert_allclose(st[3:7], [np.cos(th / 2), 0, np.sin(th / 2), 0], atol=1e-13)
+    np.testing.assert_allclose(np.linalg.norm(st[3:7]), 1.0, atol=1e-15)
+    np.testing.assert_allclose(O.fiber_axis(st[3:7]), [np.cos(th), 0, -np.sin(th)], atol=1e-13)
+    np.testing.assert_allclose(st[10:13], W, atol=1e-17)
+
+
+def test_rigid_translation_and_wrap():
+    """V' = V + F/m, X' = X + V' and the periodic wrap in x and y."""
+    st = np.zeros(16)
+    st[3] = 1.0
+    st[0:3] = [9.95, 0.02, 5.0]
+    st[7:10] = [0.04, -0.05, 0.0]
+    out = O.rigid_step(st, 4.0, 1.0, 1.0, np.array([0.04, 0.0, 0.08]), np.zeros(3),
+                       shape=(10, 10, 10), z_periodic=False)
+    np.testing.assert_allclose(out[7:10], [0.05, -0.05, 0.02], atol=1e-17)
+    np.testing.assert_allclose(out[0:3], [0.0, 9.97, 5.02], atol=1e-14)
+
+
+def test_free_precession_conserves_angular_momentum():
+    """Torque-free rotation of an axisymmetric body: the world angular
+    momentum L stays fixed and the symmetry axis precesses about L at the
+    rate |L|/I_perp (closed form of Euler's equations).  The step is first
+    order, so the axis agrees to O(|W|^2) per step."""
+    ipar, iperp = 1.0, 5.0
+
+    def run(scale, nsteps):
+        st = np.zeros(16)
+        st[3] = 1.0
+        W = scale * np.array([0.02, 0.01, 0.0])  # along the axis e_x and across it
+        st[10:13] = W
+        st[13:16] = [ipar * W[0], iperp * W[1], 0.0]
+        Lang = st[13:16].copy()
+        for _ in range(nsteps):
+            st = O.rigid_step(st, 1.0, ipar, iperp, np.zeros(3), np.zeros(3))
+        np.testing.assert_allclose(st[13:16], Lang, atol=1e-16)
+        # exact: t(n) = rotation of e_x about L by n |L| / I_perp
+        Lh = Lang / np.linalg.norm(Lang)
+        ang = nsteps * np.linalg.norm(Lang) / iperp
+        t0 = np.array([1.0, 0, 0])
+        ex = (t0 * np.cos(ang) + np.cross(Lh, t0) * np.sin(ang)
+              + Lh * (Lh @ t0) * (1 - np.cos(ang)))
+        return np.linalg.norm(O.fiber_axis(st[3:7]) - ex)
+
+    e1 = run(1.0, 300)
+    e2 = run(0.5, 600)     # same physical time, half the angle per step
+    assert e1 < 3e-2
+    assert 1.7 < e1 / e2 < 2.3
+
+
+# ---------------------------------------------------------------- momentum exchange
+def test_drag_balance_fixed_fiber():
+    """Momentum exchange (Eq. LBMhydrodynForce): a fiber held at rest in a
+    fully periodic box of fluid driven by a body force g.  In the steady
+    state all momentum injected into the fluid, rho0 g per fluid cell per
+    step, leaves through the fiber's links, so F = rho0 g N_fluid exactly."""
+    n = 12
+    g = np.array([2e-6, 0.0, -1e-6])
+    s = O.Sim(n, n, n, tau=0.8, z_periodic=True, g=g)
+    q = np.array([0.95, 0.1, 0.25, -0.1])
+    q /= np.linalg.norm(q)
+    s.add_fiber((5.7, 6.2, 5.9), q, 8.0, 1.6, 1.0)
+    s.set_kinematics(0, np.tile(np.r_[5.7, 6.2, 5.9, q, np.zeros(6)], (6000, 1)))
+    s.step(6000)
+    _, _, flags, _ = s.fields()
+    nfluid = (flags == 0).sum()
+    h = s.history()
+    Fmean = 0.5 * (h[-1, 0, 0:3] + h[-2, 0, 0:3])
+    np.testing.assert_allclose(Fmean, g * nfluid, rtol=1e-10, atol=1e-14)
+
+
+def test_force_and_torque_signs():
+    """A body moved through fluid at rest feels a force against its velocity;
+    a body spun in fluid at rest feels a torque against its rotation (this
+    fixes the order of the cross product in the torque)."""
+    n = 16
+    q = np.array([1.0, 0, 0, 0])
+    V = np.array([2e-4, -1e-4, 5e-5])
+    for kind in ("translate", "rotate"):
+        s = O.Sim(n, n, n, tau=0.8, z_periodic=True)
+        Wv = np.array([1e-4, 3e-4, -2e-4]) if kind == "rotate" else np.zeros(3)
+        Vv = V if kind == "translate" else np.zeros(3)
+        s.add_fiber((8, 8, 8), q, 8.0, 2.0, 1.0, V=Vv, W=Wv)
+        traj = np.tile(np.r_[8, 8, 8, q, Vv, Wv], (5, 1))
+        s.set_kinematics(0, traj)
+        s.step(5)
+        h = s.history()
+        for i in range(5):
+            F, M = h[i, 0, 0:3], h[i, 0, 3:6]
+            if kind == "translate":
+                assert F @ V < 0
+            else:
+                assert M @ Wv < 0
+
+
+def test_centrosymmetric_fiber_in_couette_flow():
+    """A fiber centred in the Couette cell with its axis in the x-z plane:
+    the mapped cell set and the flow are point-symmetric about the centre,
+    so the net force and the torque components out of the shear plane vanish."""
+    n, U = 32, 0.005
+    s = O.Sim(n, n, n, tau=0.8, wall_u=U, init_couette=True)
+    th = 0.4
+    q = np.array([np.cos(th / 2), 0, np.sin(th / 2), 0])
+    X = np.array([15.5, 15.5, 15.5])
+    s.add_fiber(X, q, 16.0, 2.0, 1.0)
+    s.set_kinematics(0, np.tile(np.r_[X, q, np.zeros(6)], (20, 1)))
+    s.step(20)
+    h = s.history()
+    for i in range(20):
+        F, M = h[i, 0, 0:3], h[i, 0, 3:6]
+        assert np.abs(F).max() < 1e-12
+        assert abs(M[0]) < 1e-12 and abs(M[2]) < 1e-12
+        assert M[1] != 0.0
+
+
+def test_uncovered_cells_are_refilled_with_equilibrium():
+    """Sec. 4.2: a cell uncovered by a moving particle is refilled with
+    f_eq(rho0, u_s) of the particle's previous-step motion at that cell."""
+    n = 16
+    s = O.Sim(n, n, n, tau=0.8, z_periodic=True)
+    q = np.array([1.0, 0, 0, 0])
+    V = np.array([0.3, 0.0, 0.0])
+    X0 = np.array([8.0, 8.0, 8.0])
+    s.add_fiber(X0, q, 6.0, 1.5, 1.0, V=V)
+    _, _, fl0, _ = s.fields()
+    s.set_kinematics(0, np.r_[X0 + V, q, V, np.zeros(3)][None, :])
+    s.step(1)
+    _, _, fl1, _ = s.fields()
+    unc = (fl0 == 1) & (fl1 == 0)
+    assert unc.sum() == 9      # the trailing face x = 5 (|a| = 3.3 > 3)
+    f = s.populations()
+    fe = O.feq(1.0, 1.0, V)
+    for z, y, x in zip(*np.nonzero(unc)):
+        np.testing.assert_array_equal(f[:, z, y, x], fe)
