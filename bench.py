@@ -1,0 +1,188 @@
+"""Benchmark: coupled D3Q19 LBM + rigid-fiber time steps on one MI355X.
+
+Workload (default): 256^3 shear cell (walls at the z ends moving at -/+0.01),
+64 rigid cylinder fibers, lengths U[24, 40], diameters U[4, 6], uniform
+non-overlapping positions, orientations uniform on the sphere (seed 0),
+TRT tau = 0.8 with Lambda = 3/16, FP32 deviation storage.  A step is the
+whole hot path: fused AA stream-collide with wall and fiber bounce-back,
+momentum exchange, rigid-body update, remap with refill, boundary-list
+rebuild.  Inputs are synthetic and resident in HBM before timing starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line: MLUPS (all cells x steps / s), the roofline of the
+dominant kernel (the bulk stream-collide sweep, timed live with HIP events
+on the stream it runs on), and the FP64 oracle's rate on a bounded sample of
+the same workload on the host cores.  The FP16/BF16 deviation-storage forms
+of the same workload are timed too and reported under "forms".
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "D3Q19 MLUPS & %HBM peak; FP32 vs FP16-storage vs learned-coarse at fixed error"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per lattice update of the bulk sweep: 19 loads + 19
+# stores of the population type + the 1-byte cell flag
+BYTES_PER_LUP = {"f32": 19 * 4 * 2 + 1, "f16": 19 * 2 * 2 + 1, "bf16": 19 * 2 * 2 + 1,
+                 "f64": 19 * 8 * 2 + 1}
+
+
+def build_context(sc, storage, stream):
+    from paper_1503_06869_amd import lbm
+    g = lbm.Context(sc.nx, sc.ny, sc.nz, tau=sc.tau, magic=sc.magic, wall_u=sc.wall_u,
+                    init_couette=True, storage=storage, stream=stream)
+    for f in sc.fibers:
+        g.add_fiber(f.X, f.q, f.length, f.radius, f.density_ratio, f.V, f.W)
+    return g
+
+
+def time_form(sc, storage, steps, warmup, torch):
+    """Whole-step throughput and the bulk sweep's live event timing."""
+    stream = torch.cuda.Stream()          # default priority; the context runs on it
+    g = build_context(sc, storage, stream.cuda_stream)
+    g.step(warmup)
+    g.sync()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    g.step(steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    g.sync()
+    ms = t0.elapsed_time(t1)
+    # dominant kernel: bulk sweep, bracketed by events on the context stream
+    nsw = max(20, min(steps, 200))
+    g.enable_sweep_timing(True)
+    g.step(nsw)
+    sweep_ms, n = g.sweep_time()
+    g.enable_sweep_timing(False)
+    info = g.info()
+    _, _, flags, _ = g.fields()
+    n_solid = int(flags.sum())
+    g.close()
+    ncell = sc.ncell
+    n_bulk = ncell - n_solid - int(info["boundary_cells"])
+    bytes_launch = n_bulk * (BYTES_PER_LUP[storage] - 1) + ncell * 1
+    avg = sweep_ms / n
+    return {
+        "ms_per_step": ms / steps,
+        "mlups": ncell * steps / (ms * 1e-3) / 1e6,
+        "sweep_ms": avg,
+        "sweep_gbs": bytes_launch / (avg * 1e-3) / 1e9,
+        "sweep_bytes": bytes_launch,
+        "bulk_cells": n_bulk,
+        "boundary_cells": int(info["boundary_cells"]),
+        "solid_cells": n_solid,
+    }
+
+
+def cpu_baseline(sc, nsteps=2):
+    """FP64 oracle on the host cores: the same 256^3 workload for nsteps steps."""
+    from oracle import pyoracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    s = O.Sim(sc.nx, sc.ny, sc.nz, tau=sc.tau, magic=sc.magic, wall_u=sc.wall_u,
+              init_couette=True)
+    for f in sc.fibers:
+        s.add_fiber(f.X, f.q, f.length, f.radius, f.density_ratio, f.V, f.W)
+    t = time.perf_counter()
+    s.step(nsteps)
+    dt = time.perf_counter() - t
+    return {"value": sc.ncell * nsteps / dt / 1e6, "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d steps of the 256^3 64-fiber shear cell (FP64, %d OpenMP threads, %.1f s)"
+                      % (nsteps, threads, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--forms", default="f16,bf16", help="extra storage forms to time")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run the plain copy kernel (traffic-counter calibration)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the slab decomposition over xGMI is a design, not code)", file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("run with one process per node: --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1503_06869_amd import lbm, scenarios
+    lbm.load()
+    torch.cuda.set_device(0)
+    if a.copy_calib:
+        nbytes = 1 << 30
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        st = torch.cuda.Stream()
+        for _ in range(3):
+            lbm.copy_bytes(dst.data_ptr(), src.data_ptr(), nbytes, st.cuda_stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(10):
+            lbm.copy_bytes(dst.data_ptr(), src.data_ptr(), nbytes, st.cuda_stream)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        print(json.dumps({"copy_bytes_per_launch": 2 * nbytes, "copy_ms": ms,
+                          "copy_gbs": 2 * nbytes / (ms * 1e-3) / 1e9}))
+        return
+    sc = scenarios.many_fibers(seed=0)
+    main_form = time_form(sc, "f32", a.steps, a.warmup, torch)
+    forms = {"f32": {"mlups": round(main_form["mlups"], 1),
+                     "sweep_hbm_frac": round(main_form["sweep_gbs"] / HBM_PEAK_GBS, 4)}}
+    for st in [s for s in a.forms.split(",") if s]:
+        r = time_form(sc, st, max(100, a.steps // 2), a.warmup, torch)
+        forms[st] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                     "sweep_gbs": round(r["sweep_gbs"], 1),
+                     "sweep_hbm_frac": round(r["sweep_gbs"] / HBM_PEAK_GBS, 4)}
+    cpu = None
+    if not a.no_cpu:
+        cpu = cpu_baseline(sc)
+    out = {
+        "metric": METRIC,
+        "value": round(main_form["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(main_form["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "256^3 shear cell, 64 rigid cylinder fibers (L 24-40, d 4-6), "
+                               "TRT tau 0.8, U 0.01, FP32 deviation storage, seed 0",
+                   "cells": sc.ncell, "fibers": len(sc.fibers),
+                   "bulk_cells": main_form["bulk_cells"],
+                   "boundary_cells": main_form["boundary_cells"],
+                   "solid_cells": main_form["solid_cells"]},
+        "roofline": {"bound": "hbm", "achieved": round(main_form["sweep_gbs"], 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(main_form["sweep_gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": None,
+                     "kernel": "k_sweep_bulk (even/odd AA)",
+                     "kernel_ms": round(main_form["sweep_ms"], 5),
+                     "algorithmic_bytes_per_launch": main_form["sweep_bytes"]},
+        "forms": forms,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,820 @@
+// api.hip -- host side of the library: context, device buffers, the step
+// scheduler (direct launches or a captured two-step HIP graph) and the C ABI
+// declared in include/lbm.h.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_dev.h"
+
+using namespace lbm;
+
+struct lbm_ctx {
+    lbm_params p{};
+    std::string err;
+    hipStream_t st = nullptr;
+    int sk = 0;
+    size_t esz = 4;
+    Geo g{};
+    Phys<double> ph{};
+    double scale = 1.0;
+    // lattice
+    void *f = nullptr;
+    uint8_t *flags = nullptr;
+    int32_t *pid = nullptr;
+    uint64_t *nref = nullptr;
+    // particles
+    int np = 0;
+    std::vector<lbm_fiber> fib;
+    std::vector<PConst> pch;
+    std::vector<std::vector<double>> traj_h;
+    PState *ps[2] = {nullptr, nullptr};
+    PConst *pc = nullptr;
+    Box *box_cur = nullptr, *box_remap = nullptr;
+    double *partial = nullptr;
+    uint32_t *seg_off = nullptr, *seg_cap = nullptr, *seg_cnt = nullptr;
+    int nslab = 4, bpf = 1;
+    int32_t *nbr = nullptr, *nbr_n = nullptr;
+    double *traj = nullptr;
+    int64_t *traj_pos = nullptr;
+    double *ft = nullptr, *hist = nullptr;
+    uint32_t *list_cell = nullptr, *list_mask = nullptr;
+    void *linkval = nullptr;
+    uint32_t list_cap = 0;
+    DevCounters *ctr = nullptr;
+    uint32_t remap_grid = 0, bnd_grid = 0;
+    int64_t steps = 0;
+    int64_t device_bytes = 0;
+    // graph of one even + one odd step
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    // sweep timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    bool own_stream = false;
+    size_t ev_used = 0;
+    int64_t timed_sweeps = 0;
+    double timed_ms = 0.0;
+};
+
+static lbm_status fail(lbm_ctx *c, lbm_status s, const std::string &m)
+{
+    if (c) c->err = m;
+    return s;
+}
+
+#define HIPCHK(c, call)                                                                      \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((c), e_ == hipErrorOutOfMemory ? LBM_E_NOMEM : LBM_E_HIP,             \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                  \
+    } while (0)
+
+template <typename T>
+static hipError_t dalloc(lbm_ctx *c, T **ptr, size_t n)
+{
+    *ptr = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void **)ptr, n * sizeof(T));
+    if (e == hipSuccess) c->device_bytes += int64_t(n * sizeof(T));
+    return e;
+}
+template <typename T>
+static void dfree(T *&p)
+{
+    if (p) hipFree((void *)p);
+    p = nullptr;
+}
+
+static void free_particles(lbm_ctx *c)
+{
+    dfree(c->ps[0]);
+    dfree(c->ps[1]);
+    dfree(c->pc);
+    dfree(c->box_cur);
+    dfree(c->box_remap);
+    dfree(c->partial);
+    dfree(c->seg_off);
+    dfree(c->seg_cap);
+    dfree(c->seg_cnt);
+    dfree(c->nbr);
+    dfree(c->nbr_n);
+    dfree(c->traj);
+    dfree(c->traj_pos);
+    dfree(c->ft);
+    dfree(c->hist);
+    dfree(c->list_cell);
+    dfree(c->list_mask);
+    dfree(c->linkval);
+}
+
+static void drop_graph(lbm_ctx *c)
+{
+    if (c->gexec) hipGraphExecDestroy(c->gexec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+}
+
+// axis t = R(q) e_x, same expression order as the device
+static void host_axis(const double q[4], double t[3])
+{
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    t[0] = 1.0 - 2.0 * (y * y + z * z);
+    t[1] = 2.0 * (x * y + w * z);
+    t[2] = 2.0 * (x * z - w * y);
+}
+
+static PState make_state(const lbm_fiber &f, const PConst &c)
+{
+    PState s{};
+    const double qn = std::sqrt(f.quat[0] * f.quat[0] + f.quat[1] * f.quat[1] + f.quat[2] * f.quat[2] +
+                                f.quat[3] * f.quat[3]);
+    for (int k = 0; k < 3; ++k) s.X[k] = f.center[k];
+    for (int k = 0; k < 4; ++k) s.q[k] = f.quat[k] / qn;
+    for (int k = 0; k < 3; ++k) s.V[k] = f.vel[k];
+    for (int k = 0; k < 3; ++k) s.W[k] = f.omega[k];
+    host_axis(s.q, s.t);
+    const double tw = s.t[0] * s.W[0] + s.t[1] * s.W[1] + s.t[2] * s.W[2];
+    for (int k = 0; k < 3; ++k) s.L[k] = c.i_perp * s.W[k] + (c.i_par - c.i_perp) * tw * s.t[k];
+    return s;
+}
+
+static PartData part_data(lbm_ctx *c, PState *cur, PState *next)
+{
+    PartData pd{};
+    pd.np = c->np;
+    pd.pc = c->pc;
+    pd.ps_cur = cur;
+    pd.ps_next = next;
+    pd.box_cur = c->box_cur;
+    pd.box_remap = c->box_remap;
+    pd.partial = c->partial;
+    pd.seg_off = c->seg_off;
+    pd.seg_cap = c->seg_cap;
+    pd.seg_cnt = c->seg_cnt;
+    pd.nslab = c->nslab;
+    pd.nbr = c->nbr;
+    pd.nbr_n = c->nbr_n;
+    pd.traj = c->traj;
+    pd.traj_pos = c->traj_pos;
+    pd.ft_out = c->ft;
+    pd.hist = c->hist;
+    pd.hist_cap = c->p.history_capacity;
+    pd.implicit = c->p.coupling == LBM_COUPLING_IMPLICIT;
+    pd.rho0 = c->p.rho0;
+    pd.ctr = c->ctr;
+    pd.list_cap = c->list_cap;
+    return pd;
+}
+
+static uint32_t grid_cap(uint64_t work, uint32_t lo, uint32_t hi)
+{
+    uint64_t b = (work + 255) / 256;
+    if (b < lo) b = lo;
+    if (b > hi) b = hi;
+    return uint32_t(b);
+}
+
+// (re)allocate the per-fiber buffers for c->np fibers and upload states
+static lbm_status upload_particles(lbm_ctx *c)
+{
+    drop_graph(c);
+    free_particles(c);
+    const int np = c->np;
+    if (np == 0) return LBM_OK;
+    HIPCHK(c, dalloc(c, &c->ps[0], np));
+    HIPCHK(c, dalloc(c, &c->ps[1], np));
+    HIPCHK(c, dalloc(c, &c->pc, np));
+    HIPCHK(c, dalloc(c, &c->box_cur, np));
+    HIPCHK(c, dalloc(c, &c->box_remap, np));
+    // blocks per fiber for the momentum exchange, remap and list kernels
+    c->nslab = std::max(4, std::min(32, 2048 / np));
+    HIPCHK(c, dalloc(c, &c->partial, size_t(np) * c->nslab * 27));
+    HIPCHK(c, dalloc(c, &c->seg_off, np));
+    HIPCHK(c, dalloc(c, &c->seg_cap, np));
+    HIPCHK(c, dalloc(c, &c->seg_cnt, np));
+    HIPCHK(c, hipMemsetAsync(c->seg_cnt, 0, np * sizeof(uint32_t), c->st));
+    HIPCHK(c, dalloc(c, &c->nbr, size_t(np) * NBR_CAP));
+    HIPCHK(c, dalloc(c, &c->nbr_n, np));
+    HIPCHK(c, dalloc(c, &c->traj_pos, np));
+    HIPCHK(c, dalloc(c, &c->ft, size_t(np) * 6));
+    HIPCHK(c, dalloc(c, &c->hist, size_t(c->p.history_capacity) * np * 19));
+    // boundary-list segments, one per fiber: fluid cells next to a fiber lie
+    // within sqrt(2) of its cylinder; bound them by the cylinder widened by 2.5
+    std::vector<uint32_t> soff(np), scap(np);
+    double total = 0.0, maxcap = 0.0;
+    for (int i = 0; i < np; ++i) {
+        const double r = c->fib[i].radius + 2.5, L = c->fib[i].length + 5.0;
+        const double cap = 1.25 * (M_PI * r * r * L + 4.0 * M_PI * r * r) + 256.0;
+        soff[i] = uint32_t(total);
+        scap[i] = uint32_t(cap);
+        total += double(scap[i]);
+        maxcap = std::max(maxcap, double(scap[i]));
+    }
+    if (total >= 4294967295.0) return fail(c, LBM_E_ARG, "boundary list too large");
+    c->list_cap = uint32_t(total);
+    HIPCHK(c, dalloc(c, &c->list_cell, c->list_cap));
+    HIPCHK(c, dalloc(c, &c->list_mask, c->list_cap));
+    HIPCHK(c, hipMalloc(&c->linkval, size_t(c->list_cap) * Q * (c->sk == S_F64 ? 8 : 4)));
+    c->device_bytes += int64_t(size_t(c->list_cap) * Q * (c->sk == S_F64 ? 8 : 4));
+    HIPCHK(c, hipMemcpyAsync(c->seg_off, soff.data(), np * sizeof(uint32_t), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->seg_cap, scap.data(), np * sizeof(uint32_t), hipMemcpyHostToDevice, c->st));
+    // boundary sweep: blocks per fiber segment, about four entries per thread
+    c->bpf = std::max(1, std::min(16, int(maxcap / 1.25 / 1024.0) + 1));
+    c->remap_grid = uint32_t(np * c->nslab);
+    c->bnd_grid = uint32_t(np * c->bpf);
+    std::vector<PState> hs(np);
+    int64_t off = 0;
+    std::vector<double> alltraj;
+    for (int i = 0; i < np; ++i) {
+        PConst &pc = c->pch[i];
+        if (!c->traj_h[i].empty()) {
+            pc.traj_off = off;
+            pc.traj_n = int64_t(c->traj_h[i].size() / 13);
+            alltraj.insert(alltraj.end(), c->traj_h[i].begin(), c->traj_h[i].end());
+            off += pc.traj_n;
+        } else {
+            pc.traj_off = -1;
+            pc.traj_n = 0;
+        }
+        hs[i] = make_state(c->fib[i], pc);
+    }
+    HIPCHK(c, dalloc(c, &c->traj, alltraj.size() + 13));
+    if (!alltraj.empty())
+        HIPCHK(c, hipMemcpyAsync(c->traj, alltraj.data(), alltraj.size() * sizeof(double),
+                                 hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->pc, c->pch.data(), np * sizeof(PConst), hipMemcpyHostToDevice, c->st));
+    const int cur = int(c->steps & 1);
+    HIPCHK(c, hipMemcpyAsync(c->ps[cur], hs.data(), np * sizeof(PState), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemsetAsync(c->traj_pos, 0, np * sizeof(int64_t), c->st));
+    HIPCHK(c, hipMemsetAsync(c->box_cur, 0, np * sizeof(Box), c->st));
+    HIPCHK(c, hipMemsetAsync(c->ft, 0, np * 6 * sizeof(double), c->st));
+    return LBM_OK;
+}
+
+// map all fibers from their current states (cells of the old boxes included)
+static lbm_status setup_mapping(lbm_ctx *c, PState *old_states)
+{
+    if (c->np == 0) return LBM_OK;
+    PState *cur = c->ps[c->steps & 1];
+    PartData pd = part_data(c, old_states ? old_states : cur, cur);
+    HIPCHK(c, launch_setup_boxes(pd, c->g, c->st));
+    HIPCHK(c, launch_remap(c->sk, (c->steps & 1) != 0, c->f, c->pid, pd, c->g, c->p.rho0, c->scale,
+                           c->st));
+    HIPCHK(c, launch_near(c->flags, c->pid, c->list_cell, c->list_mask, c->nref, pd, c->g, c->st));
+    return LBM_OK;
+}
+
+static lbm_status check_device_errors(lbm_ctx *c)
+{
+    DevCounters h;
+    HIPCHK(c, hipMemcpyAsync(&h, c->ctr, sizeof h, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (h.err_unstable) return fail(c, LBM_E_UNSTABLE, "non-finite force or torque on the device");
+    if (h.err_capacity)
+        return fail(c, LBM_E_STATE,
+                    std::string("internal capacity exceeded (") +
+                        ((h.err_capacity & 2) ? "boundary list" : "neighbour list") + ")");
+    return LBM_OK;
+}
+
+static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hipEvent_t e0,
+                            hipEvent_t e1, hipError_t *err)
+{
+    const bool odd = (step_index & 1) != 0;
+    PState *cur = c->ps[step_index & 1], *next = c->ps[(step_index + 1) & 1];
+    BndData b{};
+    b.cell = c->list_cell;
+    b.mask = c->list_mask;
+    b.seg_off = c->seg_off;
+    b.seg_cnt = c->seg_cnt;
+    b.seg_cap = c->seg_cap;
+    b.np = c->np;
+    b.bpf = c->bpf;
+    b.pid = c->pid;
+    b.ps = cur;
+    b.linkval = c->linkval;
+    hipError_t e = launch_sweep(c->sk, odd, c->f, c->flags, c->g, c->ph, b, c->np ? c->bnd_grid : 0,
+                                c->st, with_events ? e0 : nullptr, with_events ? e1 : nullptr);
+    if (e == hipSuccess && c->np) {
+        PartData pd = part_data(c, cur, next);
+        e = launch_particles(pd, c->g, c->pid, c->nref, c->linkval, c->sk == S_F64, c->st);
+        if (e == hipSuccess)
+            e = launch_remap(c->sk, !odd, c->f, c->pid, pd, c->g, c->p.rho0, c->scale, c->st);
+        if (e == hipSuccess)
+            e = launch_near(c->flags, c->pid, c->list_cell, c->list_mask, c->nref, pd, c->g, c->st);
+    }
+    if (e != hipSuccess && *err == hipSuccess) *err = e;
+}
+
+static lbm_status build_graph(lbm_ctx *c)
+{
+    hipError_t e = hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(c, LBM_E_HIP, std::string("capture: ") + hipGetErrorString(e));
+    hipError_t le = hipSuccess;
+    launch_one_step(c, 0, false, nullptr, nullptr, &le);
+    launch_one_step(c, 1, false, nullptr, nullptr, &le);
+    e = hipStreamEndCapture(c->st, &c->graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        drop_graph(c);
+        return fail(c, LBM_E_HIP, std::string("capture failed: ") +
+                                      hipGetErrorString(le != hipSuccess ? le : e));
+    }
+    e = hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        drop_graph(c);
+        return fail(c, LBM_E_HIP, std::string("instantiate: ") + hipGetErrorString(e));
+    }
+    return LBM_OK;
+}
+
+// ====================================================================== ABI
+extern "C" {
+
+lbm_status lbm_params_default(lbm_params *p)
+{
+    if (!p) return LBM_E_ARG;
+    std::memset(p, 0, sizeof *p);
+    p->nx = p->ny = p->nz = 32;
+    p->collision = LBM_TRT;
+    p->tau = 0.8;
+    p->magic = 3.0 / 16.0;
+    p->rho0 = 1.0;
+    p->storage = LBM_F32;
+    p->init_profile = LBM_INIT_REST;
+    p->coupling = LBM_COUPLING_IMPLICIT;
+    p->fp16_scale_log2 = 14;
+    p->history_capacity = 4096;
+    return LBM_OK;
+}
+
+lbm_status lbm_lattice(int32_t *c, double *w)
+{
+    for (int q = 0; q < Q; ++q) {
+        if (c) {
+            c[3 * q] = CX[q];
+            c[3 * q + 1] = CY[q];
+            c[3 * q + 2] = CZ[q];
+        }
+        if (w) w[q] = wq(q);
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_params *p, lbm_ctx **out)
+{
+    if (!p || !out) return LBM_E_ARG;
+    *out = nullptr;
+    if (p->nx < 3 || p->ny < 3 || p->nz < 3) return LBM_E_ARG;
+    const double ncell = double(p->nx) * p->ny * p->nz;
+    if ((double(p->nz) + 2.0) * p->nx * p->ny >= 4294967295.0) return LBM_E_ARG;
+    if (!(p->tau > 0.5) || !(std::fabs(p->wall_u) < 0.1) || !(p->rho0 > 0.0)) return LBM_E_ARG;
+    if (p->collision != LBM_TRT && p->collision != LBM_SRT) return LBM_E_ARG;
+    if (p->collision == LBM_TRT && !(p->magic > 0.0)) return LBM_E_ARG;
+    if (p->storage < 0 || p->storage > 3 || p->history_capacity < 1) return LBM_E_ARG;
+    if (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 20) return LBM_E_ARG;
+    if (p->coupling != LBM_COUPLING_IMPLICIT && p->coupling != LBM_COUPLING_EXPLICIT) return LBM_E_ARG;
+    lbm_ctx *c = new (std::nothrow) lbm_ctx;
+    if (!c) return LBM_E_NOMEM;
+    c->p = *p;
+    c->st = (hipStream_t)p->stream;
+    if (!c->st) {
+        // graph capture needs a real stream: make a private one (default priority)
+        if (hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return LBM_E_HIP;
+        }
+        c->own_stream = true;
+    }
+    c->sk = p->storage;
+    c->esz = c->sk == S_F64 ? 8 : (c->sk == S_F32 ? 4 : 2);
+    c->scale = c->sk == S_F16 ? std::ldexp(1.0, p->fp16_scale_log2) : 1.0;
+    Geo &g = c->g;
+    g.nx = p->nx;
+    g.ny = p->ny;
+    g.nz = p->nz;
+    g.nxy = uint32_t(p->nx) * uint32_t(p->ny);
+    g.ncell = uint32_t(ncell);
+    g.qstride = uint64_t(p->nz + 2) * g.nxy;
+    g.dnx = make_fastdiv(g.nx);
+    g.dnxy = make_fastdiv(g.nxy);
+    g.zper = p->z_periodic ? 1 : 0;
+    Phys<double> &ph = c->ph;
+    ph.rho0 = p->rho0;
+    ph.omega_e = 1.0 / p->tau;
+    ph.omega_o = p->collision == LBM_SRT ? 1.0 / p->tau : 1.0 / (0.5 + p->magic / (p->tau - 0.5));
+    ph.wall_u = p->z_periodic ? 0.0 : p->wall_u;
+    for (int k = 0; k < 3; ++k) ph.g[k] = p->body_force[k];
+    ph.has_g = (p->body_force[0] != 0.0 || p->body_force[1] != 0.0 || p->body_force[2] != 0.0);
+    ph.scale = c->scale;
+    ph.inv_scale = 1.0 / c->scale;
+    lbm_status s = LBM_OK;
+    auto bail = [&](lbm_status st, const char *m) {
+        lbm_destroy(c);
+        (void)m;
+        return st;
+    };
+    if (hipMalloc(&c->f, size_t(Q) * g.qstride * c->esz) != hipSuccess) return bail(LBM_E_NOMEM, "f");
+    c->device_bytes += int64_t(size_t(Q) * g.qstride * c->esz);
+    if (dalloc(c, &c->flags, g.ncell) != hipSuccess || dalloc(c, &c->pid, g.ncell) != hipSuccess ||
+        dalloc(c, &c->nref, g.ncell) != hipSuccess || dalloc(c, &c->ctr, 1) != hipSuccess)
+        return bail(LBM_E_NOMEM, "fields");
+    if (hipMemsetAsync(c->flags, 0, g.ncell, c->st) != hipSuccess ||
+        hipMemsetAsync(c->nref, 0, size_t(g.ncell) * 8, c->st) != hipSuccess ||
+        hipMemsetAsync(c->pid, 0xFF, size_t(g.ncell) * 4, c->st) != hipSuccess ||
+        hipMemsetAsync(c->ctr, 0, sizeof(DevCounters), c->st) != hipSuccess)
+        return bail(LBM_E_HIP, "memset");
+    if (launch_init(c->sk, c->f, g, p->rho0, ph.wall_u, p->init_profile == LBM_INIT_COUETTE, c->scale,
+                    c->st) != hipSuccess)
+        return bail(LBM_E_HIP, "init");
+    if (hipStreamSynchronize(c->st) != hipSuccess) return bail(LBM_E_HIP, "sync");
+    (void)s;
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status lbm_destroy(lbm_ctx *c)
+{
+    if (!c) return LBM_E_ARG;
+    hipStreamSynchronize(c->st);
+    drop_graph(c);
+    for (hipEvent_t e : c->ev) hipEventDestroy(e);
+    free_particles(c);
+    dfree(c->f);
+    dfree(c->flags);
+    dfree(c->pid);
+    dfree(c->nref);
+    dfree(c->ctr);
+    if (c->own_stream) hipStreamDestroy(c->st);
+    delete c;
+    return LBM_OK;
+}
+
+const char *lbm_last_error(const lbm_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+lbm_status lbm_add_fiber(lbm_ctx *c, const lbm_fiber *f, int32_t *id)
+{
+    if (!c || !f) return fail(c, LBM_E_ARG, "null argument");
+    if (c->steps != 0) return fail(c, LBM_E_STATE, "fibers can only be added before the first step");
+    if (!(f->length > 0.0) || !(f->radius > 0.0) || !(f->density_ratio > 0.0))
+        return fail(c, LBM_E_ARG, "length, radius and density_ratio must be positive");
+    const double qn = std::sqrt(f->quat[0] * f->quat[0] + f->quat[1] * f->quat[1] +
+                                f->quat[2] * f->quat[2] + f->quat[3] * f->quat[3]);
+    if (!(qn > 0.0)) return fail(c, LBM_E_ARG, "zero quaternion");
+    const int n[3] = {c->p.nx, c->p.ny, c->p.nz};
+    double q[4], t[3];
+    for (int k = 0; k < 4; ++k) q[k] = f->quat[k] / qn;
+    host_axis(q, t);
+    for (int k = 0; k < 3; ++k) {
+        if (!(f->center[k] >= 0.0 && f->center[k] < n[k]))
+            return fail(c, LBM_E_GEOM, "centre outside the domain");
+        const double ext = 0.5 * f->length * std::fabs(t[k]) + f->radius * std::sqrt(std::fmax(0.0, 1.0 - t[k] * t[k]));
+        const bool per = k < 2 || c->p.z_periodic;
+        if (per && !(f->length * 0.5 + f->radius < 0.5 * n[k] - 1.0))
+            return fail(c, LBM_E_GEOM, "fiber longer than half the periodic domain");
+        if (!per && (f->center[k] - ext < 1.0 || f->center[k] + ext > n[k] - 2.0))
+            return fail(c, LBM_E_GEOM, "fiber within one cell of a wall");
+    }
+    if ((c->np + 1) * 27 * 8 > 65536) return fail(c, LBM_E_ARG, "at most 303 fibers per context");
+    PConst pc{};
+    pc.length = f->length;
+    pc.radius = f->radius;
+    pc.mass = f->density_ratio * c->p.rho0 * M_PI * f->radius * f->radius * f->length;
+    pc.i_par = 0.5 * pc.mass * f->radius * f->radius;
+    pc.i_perp = pc.mass * (3.0 * f->radius * f->radius + f->length * f->length) / 12.0;
+    pc.traj_off = -1;
+    c->fib.push_back(*f);
+    c->pch.push_back(pc);
+    c->traj_h.emplace_back();
+    c->np++;
+    lbm_status s = upload_particles(c);
+    if (s == LBM_OK) s = setup_mapping(c, nullptr);
+    unsigned long long ov_before = 0;
+    DevCounters h{};
+    if (s == LBM_OK) {
+        hipError_t e = hipMemcpyAsync(&h, c->ctr, sizeof h, hipMemcpyDeviceToHost, c->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+        if (e != hipSuccess) s = fail(c, LBM_E_HIP, hipGetErrorString(e));
+    }
+    if (s == LBM_OK && (h.overlaps > ov_before || h.err_capacity)) {
+        // reject: remove the fiber and re-map the others from scratch
+        c->fib.pop_back();
+        c->pch.pop_back();
+        c->traj_h.pop_back();
+        c->np--;
+        hipMemsetAsync(c->flags, 0, c->g.ncell, c->st);
+        hipMemsetAsync(c->pid, 0xFF, size_t(c->g.ncell) * 4, c->st);
+        hipMemsetAsync(c->nref, 0, size_t(c->g.ncell) * 8, c->st);
+        hipMemsetAsync(c->ctr, 0, sizeof(DevCounters), c->st);
+        lbm_status s2 = upload_particles(c);
+        if (s2 == LBM_OK) s2 = setup_mapping(c, nullptr);
+        if (s2 != LBM_OK) return s2;
+        hipStreamSynchronize(c->st);
+        return fail(c, LBM_E_GEOM, h.err_capacity ? "internal capacity exceeded while mapping"
+                                                 : "fiber overlaps another fiber");
+    }
+    if (s != LBM_OK) return s;
+    if (id) *id = c->np - 1;
+    c->err.clear();
+    return LBM_OK;
+}
+
+lbm_status lbm_set_fiber_kinematics(lbm_ctx *c, int32_t id, const double *traj, int64_t nsteps)
+{
+    if (!c || id < 0 || id >= c->np || nsteps < 0 || (nsteps > 0 && !traj))
+        return fail(c, LBM_E_ARG, "bad fiber id or trajectory");
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    // fetch the current states so that the re-upload keeps them
+    std::vector<PState> hs(c->np);
+    HIPCHK(c, hipMemcpy(hs.data(), c->ps[c->steps & 1], c->np * sizeof(PState), hipMemcpyDeviceToHost));
+    std::vector<int64_t> pos(c->np);
+    HIPCHK(c, hipMemcpy(pos.data(), c->traj_pos, c->np * sizeof(int64_t), hipMemcpyDeviceToHost));
+    // keep only the unconsumed part of the other trajectories
+    for (int i = 0; i < c->np; ++i) {
+        if (i == id) continue;
+        auto &t = c->traj_h[i];
+        const size_t used = size_t(std::min<int64_t>(pos[i], int64_t(t.size() / 13))) * 13;
+        t.erase(t.begin(), t.begin() + used);
+    }
+    c->traj_h[id].assign(traj, traj + nsteps * 13);
+    std::vector<Box> boxes(c->np);
+    HIPCHK(c, hipMemcpy(boxes.data(), c->box_cur, c->np * sizeof(Box), hipMemcpyDeviceToHost));
+    lbm_status s = upload_particles(c);
+    if (s != LBM_OK) return s;
+    HIPCHK(c, hipMemcpyAsync(c->ps[c->steps & 1], hs.data(), c->np * sizeof(PState),
+                             hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->box_cur, boxes.data(), c->np * sizeof(Box), hipMemcpyHostToDevice, c->st));
+    // rebuild the remap work and list for the unchanged poses
+    s = setup_mapping(c, nullptr);
+    if (s != LBM_OK) return s;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx *c, int64_t n)
+{
+    if (!c) return LBM_E_ARG;
+    if (n < 0) return fail(c, LBM_E_ARG, "negative step count");
+    hipError_t err = hipSuccess;
+    auto direct = [&](void) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->timing) {
+            while (c->ev.size() < c->ev_used + 2) {
+                hipEvent_t e;
+                hipEventCreate(&e);
+                c->ev.push_back(e);
+            }
+            e0 = c->ev[c->ev_used];
+            e1 = c->ev[c->ev_used + 1];
+            c->ev_used += 2;
+        }
+        launch_one_step(c, c->steps, c->timing, e0, e1, &err);
+        c->steps++;
+    };
+    int64_t left = n;
+    if (!c->timing && left >= 4) {
+        if (c->steps & 1) {
+            direct();
+            --left;
+        }
+        if (!c->gexec) {
+            lbm_status s = build_graph(c);
+            if (s != LBM_OK) return s;
+        }
+        while (left >= 2 && err == hipSuccess) {
+            err = hipGraphLaunch(c->gexec, c->st);
+            c->steps += 2;
+            left -= 2;
+        }
+    }
+    while (left > 0 && err == hipSuccess) {
+        direct();
+        --left;
+    }
+    if (err != hipSuccess) return fail(c, LBM_E_HIP, std::string("launch: ") + hipGetErrorString(err));
+    return LBM_OK;
+}
+
+lbm_status lbm_sync(lbm_ctx *c)
+{
+    if (!c) return LBM_E_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    return check_device_errors(c);
+}
+
+lbm_status lbm_get_force_torque(lbm_ctx *c, double *F, double *M)
+{
+    if (!c) return LBM_E_ARG;
+    lbm_status s = check_device_errors(c);
+    if (s != LBM_OK) return s;
+    if (c->np == 0) return LBM_OK;
+    std::vector<double> h(size_t(c->np) * 6);
+    HIPCHK(c, hipMemcpy(h.data(), c->ft, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int i = 0; i < c->np; ++i)
+        for (int k = 0; k < 3; ++k) {
+            if (F) F[3 * i + k] = h[6 * i + k];
+            if (M) M[3 * i + k] = h[6 * i + 3 + k];
+        }
+    return LBM_OK;
+}
+
+lbm_status lbm_get_fields(lbm_ctx *c, void *rho, void *u, uint8_t *flags, int32_t *pid,
+                          int32_t dst_is_device)
+{
+    if (!c) return LBM_E_ARG;
+    lbm_status s = check_device_errors(c);
+    if (s != LBM_OK) return s;
+    const size_t n = c->g.ncell, rsz = c->sk == S_F64 ? 8 : 4;
+    void *drho = nullptr, *du = nullptr;
+    if (rho) {
+        if (dst_is_device) drho = rho;
+        else HIPCHK(c, hipMalloc(&drho, n * rsz));
+    }
+    if (u) {
+        if (dst_is_device) du = u;
+        else HIPCHK(c, hipMalloc(&du, 3 * n * rsz));
+    }
+    PState *cur = c->np ? c->ps[c->steps & 1] : nullptr;
+    if (rho || u)
+        HIPCHK(c, launch_decode(c->sk, (c->steps & 1) != 0, c->f, c->flags, c->pid, cur, c->g, c->ph,
+                                drho, du, nullptr, c->st));
+    const hipMemcpyKind k = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (rho && !dst_is_device) HIPCHK(c, hipMemcpyAsync(rho, drho, n * rsz, k, c->st));
+    if (u && !dst_is_device) HIPCHK(c, hipMemcpyAsync(u, du, 3 * n * rsz, k, c->st));
+    if (flags) {
+        // logical flags: 0 fluid, 1 fiber (the near-boundary bit is internal)
+        std::vector<uint8_t> hf(n);
+        HIPCHK(c, hipMemcpyAsync(hf.data(), c->flags, n, hipMemcpyDeviceToHost, c->st));
+        HIPCHK(c, hipStreamSynchronize(c->st));
+        for (auto &v : hf) v &= F_SOLID;
+        HIPCHK(c, hipMemcpyAsync(flags, hf.data(), n, dst_is_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost, c->st));
+        HIPCHK(c, hipStreamSynchronize(c->st));
+    }
+    if (pid) HIPCHK(c, hipMemcpyAsync(pid, c->pid, n * 4, k, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (rho && !dst_is_device) hipFree(drho);
+    if (u && !dst_is_device) hipFree(du);
+    return LBM_OK;
+}
+
+lbm_status lbm_get_fiber_state(lbm_ctx *c, double *X, double *q, double *V, double *W)
+{
+    if (!c) return LBM_E_ARG;
+    lbm_status s = check_device_errors(c);
+    if (s != LBM_OK) return s;
+    if (c->np == 0) return LBM_OK;
+    std::vector<PState> h(c->np);
+    HIPCHK(c, hipMemcpy(h.data(), c->ps[c->steps & 1], c->np * sizeof(PState), hipMemcpyDeviceToHost));
+    for (int i = 0; i < c->np; ++i) {
+        for (int k = 0; k < 3; ++k) {
+            if (X) X[3 * i + k] = h[i].X[k];
+            if (V) V[3 * i + k] = h[i].V[k];
+            if (W) W[3 * i + k] = h[i].W[k];
+        }
+        if (q)
+            for (int k = 0; k < 4; ++k) q[4 * i + k] = h[i].q[k];
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_set_fiber_state(lbm_ctx *c, int32_t id, const double X[3], const double q[4],
+                               const double V[3], const double W[3])
+{
+    if (!c || id < 0 || id >= c->np || !X || !q || !V || !W) return fail(c, LBM_E_ARG, "bad argument");
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    PState *cur = c->ps[c->steps & 1], *other = c->ps[(c->steps + 1) & 1];
+    std::vector<PState> h(c->np);
+    HIPCHK(c, hipMemcpy(h.data(), cur, c->np * sizeof(PState), hipMemcpyDeviceToHost));
+    // keep the old states for the refill of uncovered cells
+    HIPCHK(c, hipMemcpy(other, h.data(), c->np * sizeof(PState), hipMemcpyHostToDevice));
+    lbm_fiber f = c->fib[id];
+    for (int k = 0; k < 3; ++k) {
+        f.center[k] = X[k];
+        f.vel[k] = V[k];
+        f.omega[k] = W[k];
+    }
+    for (int k = 0; k < 4; ++k) f.quat[k] = q[k];
+    h[id] = make_state(f, c->pch[id]);
+    HIPCHK(c, hipMemcpy(cur, h.data(), c->np * sizeof(PState), hipMemcpyHostToDevice));
+    lbm_status s = setup_mapping(c, other);
+    if (s != LBM_OK) return s;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    return check_device_errors(c);
+}
+
+lbm_status lbm_get_history(lbm_ctx *c, int64_t first, int64_t count, double *out)
+{
+    if (!c || !out || count < 0) return fail(c, LBM_E_ARG, "bad argument");
+    lbm_status s = check_device_errors(c);
+    if (s != LBM_OK) return s;
+    const int64_t cap = c->p.history_capacity;
+    if (first < 0 || first + count > c->steps || first < c->steps - cap)
+        return fail(c, LBM_E_ARG, "history window not available");
+    if (c->np == 0 || count == 0) return LBM_OK;
+    const size_t rec = size_t(c->np) * 19;
+    for (int64_t i = 0; i < count;) {
+        const int64_t slot = (first + i) % cap;
+        const int64_t run = std::min<int64_t>(count - i, cap - slot);
+        HIPCHK(c, hipMemcpy(out + i * rec, c->hist + slot * rec, size_t(run) * rec * sizeof(double),
+                            hipMemcpyDeviceToHost));
+        i += run;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_get_populations(lbm_ctx *c, double *f)
+{
+    if (!c || !f) return LBM_E_ARG;
+    lbm_status s = check_device_errors(c);
+    if (s != LBM_OK) return s;
+    double *d = nullptr;
+    const size_t n = size_t(Q) * c->g.ncell;
+    HIPCHK(c, hipMalloc(&d, n * sizeof(double)));
+    PState *cur = c->np ? c->ps[c->steps & 1] : nullptr;
+    hipError_t e = launch_decode(c->sk, (c->steps & 1) != 0, c->f, c->flags, c->pid, cur, c->g, c->ph,
+                                 nullptr, nullptr, d, c->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(f, d, n * sizeof(double), hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    hipFree(d);
+    if (e != hipSuccess) return fail(c, LBM_E_HIP, hipGetErrorString(e));
+    return LBM_OK;
+}
+
+lbm_status lbm_set_populations(lbm_ctx *c, const double *f)
+{
+    if (!c || !f) return LBM_E_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    double *d = nullptr;
+    const size_t n = size_t(Q) * c->g.ncell;
+    HIPCHK(c, hipMalloc(&d, n * sizeof(double)));
+    hipError_t e = hipMemcpyAsync(d, f, n * sizeof(double), hipMemcpyHostToDevice, c->st);
+    if (e == hipSuccess) e = launch_encode(c->sk, (c->steps & 1) != 0, c->f, c->g, c->p.rho0, c->scale, d, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    hipFree(d);
+    if (e != hipSuccess) return fail(c, LBM_E_HIP, hipGetErrorString(e));
+    return LBM_OK;
+}
+
+lbm_status lbm_get_info(lbm_ctx *c, lbm_info *info)
+{
+    if (!c || !info) return LBM_E_ARG;
+    DevCounters h{};
+    HIPCHK(c, hipMemcpyAsync(&h, c->ctr, sizeof h, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    info->steps_done = c->steps;
+    info->nfibers = c->np;
+    info->parity = int32_t(c->steps & 1);
+    int64_t nb = 0;
+    if (c->np) {
+        std::vector<uint32_t> cnt(c->np);
+        HIPCHK(c, hipMemcpy(cnt.data(), c->seg_cnt, c->np * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        for (uint32_t v : cnt) nb += v;
+    }
+    info->boundary_cells = nb;
+    info->overlap_events = int64_t(h.overlaps);
+    info->device_bytes = c->device_bytes;
+    info->population_bytes = int64_t(size_t(Q) * c->g.qstride * c->esz);
+    return LBM_OK;
+}
+
+lbm_status lbm_enable_sweep_timing(lbm_ctx *c, int32_t on)
+{
+    if (!c) return LBM_E_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    c->timing = on != 0;
+    c->ev_used = 0;
+    c->timed_ms = 0.0;
+    c->timed_sweeps = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_sweep_time(lbm_ctx *c, double *total_ms, int64_t *nsweeps)
+{
+    if (!c) return LBM_E_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+        c->timed_ms += ms;
+        c->timed_sweeps++;
+    }
+    c->ev_used = 0;
+    if (total_ms) *total_ms = c->timed_ms;
+    if (nsweeps) *nsweeps = c->timed_sweeps;
+    return LBM_OK;
+}
+
+lbm_status lbm_copy_bytes(void *dst, const void *src, size_t nbytes, void *stream)
+{
+    if (!dst || !src || (nbytes % 16) != 0) return LBM_E_ARG;
+    if (launch_copy(dst, src, nbytes, (hipStream_t)stream) != hipSuccess) return LBM_E_HIP;
+    return LBM_OK;
+}
+
+}  // extern "C"

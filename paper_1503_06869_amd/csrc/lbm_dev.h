@@ -1,0 +1,171 @@
+// lbm_dev.h -- device-side data structures, lattice tables and the launch
+// interface shared by the HIP translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// D3Q19 velocity set (Sec. 4.1: weights 1/3, 1/18, 1/36).  Order used on the
+// device and at the ABI: 0 = rest, 1..9 one of each opposite pair, q+9 the
+// opposite of q.  Keeping opposites nine apart lets the TRT pairs and the
+// AA slot swap be written as q <-> q+9.
+// ---------------------------------------------------------------------------
+constexpr int Q = 19;
+constexpr int CX[Q] = {0, 1, 0, 0, 1, 1, 1, 1, 0, 0, -1, 0, 0, -1, -1, -1, -1, 0, 0};
+constexpr int CY[Q] = {0, 0, 1, 0, 1, -1, 0, 0, 1, 1, 0, -1, 0, -1, 1, 0, 0, -1, -1};
+constexpr int CZ[Q] = {0, 0, 0, 1, 0, 0, 1, -1, 1, -1, 0, 0, -1, 0, 0, -1, 1, -1, 1};
+__host__ __device__ constexpr int opp(int q) { return q == 0 ? 0 : (q <= 9 ? q + 9 : q - 9); }
+__host__ __device__ constexpr double wq(int q)
+{
+    return q == 0 ? 1.0 / 3.0 : ((q <= 3 || (q >= 10 && q <= 12)) ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// cell flags
+constexpr uint8_t F_SOLID = 1;   // cell centre inside a fiber
+constexpr uint8_t F_NEAR = 2;    // fluid cell with at least one fiber neighbour
+
+// uint32 division by a runtime constant (round-up multiply-shift method)
+struct FastDiv {
+    uint32_t m, s;
+};
+inline FastDiv make_fastdiv(uint32_t d)
+{
+    if ((d & (d - 1)) == 0) {
+        uint32_t s = 0;
+        while ((1u << s) < d) ++s;
+        return {0u, s};
+    }
+    uint32_t l = 32 - __builtin_clz(d - 1);
+    uint64_t m = ((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1;
+    return {uint32_t(m), l};
+}
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f)
+{
+    if (f.m == 0) return n >> f.s;
+    uint32_t t = __umulhi(n, f.m);
+    return (t + ((n - t) >> 1)) >> (f.s - 1);
+}
+
+// ---------------------------------------------------------------------------
+// Particle data (FP64 throughout)
+// ---------------------------------------------------------------------------
+struct PState {            // one fiber, state at a time level
+    double X[3];           // centre of mass
+    double q[4];           // orientation (w, x, y, z)
+    double V[3];           // velocity
+    double W[3];           // angular velocity (world frame)
+    double L[3];           // angular momentum (world frame)
+    double t[3];           // axis R(q) e_x
+    double pad;
+};
+struct PConst {
+    double length, radius, mass, i_par, i_perp;
+    int64_t traj_off;      // offset (rows) into the trajectory array, or -1
+    int64_t traj_n;        // rows prescribed
+};
+struct Box {               // cells lo[k] .. lo[k]+len[k]-1 (wrapped where periodic)
+    int32_t lo[3];
+    int32_t len[3];
+};
+constexpr int NBR_CAP = 128;   // neighbours per fiber whose boxes may intersect
+
+// per-fiber accumulators of the momentum exchange (FP64):
+// F0[3] M0[3] A[6] (sym xx xy xz yy yz zz) B[9] C[6]
+constexpr int NACC = 30;
+
+// device-side counters and error flags
+struct DevCounters {
+    uint32_t block_ticket;     // "last block" ticket of the particle kernel
+    uint32_t list_count;       // boundary-cell list length
+    uint32_t err_unstable;     // non-finite F/M seen
+    uint32_t err_capacity;     // list or neighbour capacity exceeded
+    unsigned long long overlaps;
+    uint32_t pad0;
+    uint32_t pad;
+    unsigned long long step;   // steps completed by the particle kernel (history index)
+};
+
+// ---------------------------------------------------------------------------
+// Kernel argument bundles
+// ---------------------------------------------------------------------------
+struct Geo {
+    uint32_t nx, ny, nz, nxy;
+    uint32_t ncell;
+    uint64_t qstride;          // elements per direction array: (nz+2) * nxy
+    FastDiv dnx, dnxy;
+    int32_t zper;
+};
+
+template <typename R>
+struct Phys {
+    R rho0, omega_e, omega_o, wall_u;
+    R g[3];
+    int32_t has_g;
+    R scale, inv_scale;        // storage scaling of the deviation
+};
+
+struct BndData {               // boundary-cell list and particle access for the sweep
+    const uint32_t *cell;
+    const uint32_t *mask;      // bit q (1..18) set: neighbour x + c_q is a fiber cell
+    const uint32_t *seg_off;   // [np] start of each fiber's list segment
+    const uint32_t *seg_cnt;   // [np] entries in each segment
+    const uint32_t *seg_cap;   // [np] capacity of each segment
+    int32_t np;
+    int32_t bpf;               // blocks per fiber segment
+    const int32_t *pid;
+    const PState *ps;          // state at the time level of the sweep
+    void *linkval;             // [entry][Q] post-collision deviation (compute type)
+};
+
+struct PartData {
+    int32_t np;
+    const PConst *pc;
+    PState *ps_cur, *ps_next;
+    Box *box_cur;              // box of the current pose (read by the MEA, rewritten by the last block)
+    Box *box_remap;            // old-and-new union boxes for the remap
+    int32_t *nbr;              // [np][NBR_CAP]
+    int32_t *nbr_n;            // [np]
+    const double *traj;        // prescribed rows [.][13]
+    int64_t *traj_pos;         // [np] rows consumed
+    double *ft_out;            // [np][6] F, M of the step
+    double *hist;              // ring [cap][np][19]
+    int64_t hist_cap;
+    int32_t implicit;
+    double rho0;
+    DevCounters *ctr;
+    uint32_t list_cap;
+    int32_t nslab;             // blocks per fiber (z-planes of a box dealt round robin)
+    double *partial;           // [np][nslab][27] per-block momentum-exchange sums
+    const uint32_t *seg_off;   // [np] list segment of each fiber: start
+    const uint32_t *seg_cap;   // [np] capacity
+    uint32_t *seg_cnt;         // [np] entries
+};
+
+// ---------------------------------------------------------------------------
+// Launch wrappers (defined in sweep.hip / particles.hip)
+// ---------------------------------------------------------------------------
+enum StorageKind { S_F32 = 0, S_F16 = 1, S_BF16 = 2, S_F64 = 3 };
+
+hipError_t launch_init(int sk, void *f, const Geo &g, double rho0, double wall_u, int couette,
+                       double scale, hipStream_t st);
+hipError_t launch_sweep(int sk, bool odd, void *f, const uint8_t *flags, const Geo &g,
+                        const Phys<double> &ph, const BndData &b, uint32_t bnd_grid,
+                        hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_decode(int sk, bool swapped, const void *f, const uint8_t *flags,
+                         const int32_t *pid, const PState *ps, const Geo &g, const Phys<double> &ph,
+                         void *rho, void *u, double *fout, hipStream_t st);
+hipError_t launch_encode(int sk, bool swapped, void *f, const Geo &g, double rho0, double scale,
+                         const double *fin, hipStream_t st);
+hipError_t launch_particles(const PartData &pd, const Geo &g, const int32_t *pid, const uint64_t *nref,
+                            const void *linkval, int linkval_is_double, hipStream_t st);
+hipError_t launch_setup_boxes(const PartData &pd, const Geo &g, hipStream_t st);
+hipError_t launch_remap(int sk, bool next_odd, void *f, int32_t *pid, const PartData &pd, const Geo &g,
+                        double rho0, double scale, hipStream_t st);
+hipError_t launch_near(uint8_t *flags, const int32_t *pid, uint32_t *list_cell, uint32_t *list_mask,
+                       uint64_t *nref, const PartData &pd, const Geo &g, hipStream_t st);
+hipError_t launch_copy(void *dst, const void *src, size_t nbytes, hipStream_t st);
+
+}  // namespace lbm

@@ -1,0 +1,250 @@
+"""Thin ctypes binding of the C ABI in include/lbm.h (argument marshalling only).
+
+The functions keep the C names (``lbm_create``, ``lbm_step``, ...).  The
+``Context`` class wraps one context with numpy in/out arrays.  Every step of
+the method runs in the HIP kernels of ``liblbmfib.so``; if that library is
+missing this module raises on import of the library (there is no fallback).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbmfib.so")
+
+LBM_OK, LBM_E_ARG, LBM_E_NOMEM, LBM_E_HIP, LBM_E_GEOM, LBM_E_UNSTABLE, LBM_E_STATE = range(7)
+LBM_TRT, LBM_SRT = 0, 1
+LBM_F32, LBM_F16DEV, LBM_BF16DEV, LBM_F64 = 0, 1, 2, 3
+LBM_INIT_REST, LBM_INIT_COUETTE = 0, 1
+LBM_COUPLING_IMPLICIT, LBM_COUPLING_EXPLICIT = 0, 1
+
+STORAGE = {"f32": LBM_F32, "f16": LBM_F16DEV, "bf16": LBM_BF16DEV, "f64": LBM_F64}
+
+EXPORTED = [
+    "lbm_params_default", "lbm_create", "lbm_destroy", "lbm_last_error", "lbm_lattice",
+    "lbm_add_fiber", "lbm_set_fiber_kinematics", "lbm_step", "lbm_sync",
+    "lbm_get_force_torque", "lbm_get_fields", "lbm_get_fiber_state", "lbm_set_fiber_state",
+    "lbm_get_history", "lbm_get_populations", "lbm_set_populations", "lbm_get_info",
+    "lbm_enable_sweep_timing", "lbm_get_sweep_time", "lbm_copy_bytes",
+]
+
+
+class lbm_params(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("z_periodic", C.c_int32), ("collision", C.c_int32),
+                ("tau", C.c_double), ("magic", C.c_double), ("wall_u", C.c_double),
+                ("rho0", C.c_double), ("body_force", C.c_double * 3),
+                ("storage", C.c_int32), ("init_profile", C.c_int32), ("coupling", C.c_int32),
+                ("fp16_scale_log2", C.c_int32), ("history_capacity", C.c_int64),
+                ("stream", C.c_void_p)]
+
+
+class lbm_fiber(C.Structure):
+    _fields_ = [("center", C.c_double * 3), ("quat", C.c_double * 4), ("length", C.c_double),
+                ("radius", C.c_double), ("density_ratio", C.c_double),
+                ("vel", C.c_double * 3), ("omega", C.c_double * 3)]
+
+
+class lbm_info(C.Structure):
+    _fields_ = [("steps_done", C.c_int64), ("nfibers", C.c_int32), ("parity", C.c_int32),
+                ("boundary_cells", C.c_int64), ("overlap_events", C.c_int64),
+                ("device_bytes", C.c_int64), ("population_bytes", C.c_int64)]
+
+
+_dp = C.POINTER(C.c_double)
+_lib = None
+
+
+def load():
+    """Load liblbmfib.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("liblbmfib.so not built: run paper_1503_06869_amd.build.build()")
+    L = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    sig = {
+        "lbm_params_default": ([C.POINTER(lbm_params)], C.c_int),
+        "lbm_create": ([C.POINTER(lbm_params), C.POINTER(vp)], C.c_int),
+        "lbm_destroy": ([vp], C.c_int),
+        "lbm_last_error": ([vp], C.c_char_p),
+        "lbm_lattice": ([C.POINTER(C.c_int32), _dp], C.c_int),
+        "lbm_add_fiber": ([vp, C.POINTER(lbm_fiber), C.POINTER(C.c_int32)], C.c_int),
+        "lbm_set_fiber_kinematics": ([vp, C.c_int32, _dp, C.c_int64], C.c_int),
+        "lbm_step": ([vp, C.c_int64], C.c_int),
+        "lbm_sync": ([vp], C.c_int),
+        "lbm_get_force_torque": ([vp, _dp, _dp], C.c_int),
+        "lbm_get_fields": ([vp, vp, vp, vp, vp, C.c_int32], C.c_int),
+        "lbm_get_fiber_state": ([vp, _dp, _dp, _dp, _dp], C.c_int),
+        "lbm_set_fiber_state": ([vp, C.c_int32, _dp, _dp, _dp, _dp], C.c_int),
+        "lbm_get_history": ([vp, C.c_int64, C.c_int64, _dp], C.c_int),
+        "lbm_get_populations": ([vp, _dp], C.c_int),
+        "lbm_set_populations": ([vp, _dp], C.c_int),
+        "lbm_get_info": ([vp, C.POINTER(lbm_info)], C.c_int),
+        "lbm_enable_sweep_timing": ([vp, C.c_int32], C.c_int),
+        "lbm_get_sweep_time": ([vp, _dp, C.POINTER(C.c_int64)], C.c_int),
+        "lbm_copy_bytes": ([vp, vp, C.c_size_t, vp], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+class LBMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("lbm error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(x, n=None):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    if n is not None and a.size != n:
+        raise ValueError("expected %d values, got %d" % (n, a.size))
+    return a
+
+
+def lattice():
+    """(c[19][3], w[19]) in the library's population order."""
+    c = np.zeros(57, np.int32)
+    w = np.zeros(19)
+    load().lbm_lattice(c.ctypes.data_as(C.POINTER(C.c_int32)), _d(w))
+    return c.reshape(19, 3), w
+
+
+def copy_bytes(dst_ptr, src_ptr, nbytes, stream=None):
+    r = load().lbm_copy_bytes(C.c_void_p(dst_ptr), C.c_void_p(src_ptr), nbytes, C.c_void_p(stream or 0))
+    if r != LBM_OK:
+        raise LBMError(r, "copy failed")
+
+
+class Context:
+    """One lattice with its fibers (owns an lbm_ctx)."""
+
+    def __init__(self, nx, ny, nz, tau=0.8, magic=3.0 / 16.0, wall_u=0.0, rho0=1.0,
+                 z_periodic=False, collision="trt", storage="f32", init_couette=False,
+                 coupling="implicit", body_force=(0.0, 0.0, 0.0), fp16_scale_log2=14,
+                 history_capacity=4096, stream=None):
+        L = load()
+        p = lbm_params()
+        L.lbm_params_default(C.byref(p))
+        p.nx, p.ny, p.nz = nx, ny, nz
+        p.z_periodic = int(bool(z_periodic))
+        p.collision = LBM_SRT if collision == "srt" else LBM_TRT
+        p.tau, p.magic, p.wall_u, p.rho0 = tau, magic, wall_u, rho0
+        p.body_force = (C.c_double * 3)(*body_force)
+        p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        p.init_profile = LBM_INIT_COUETTE if init_couette else LBM_INIT_REST
+        p.coupling = LBM_COUPLING_EXPLICIT if coupling == "explicit" else LBM_COUPLING_IMPLICIT
+        p.fp16_scale_log2 = fp16_scale_log2
+        p.history_capacity = history_capacity
+        p.stream = stream
+        h = C.c_void_p()
+        r = L.lbm_create(C.byref(p), C.byref(h))
+        if r != LBM_OK:
+            raise LBMError(r, "lbm_create failed")
+        self._h = h
+        self.shape = (nx, ny, nz)
+        self.ncell = nx * ny * nz
+        self.storage = p.storage
+        self.nfibers = 0
+
+    def _chk(self, r):
+        if r != LBM_OK:
+            raise LBMError(r, load().lbm_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lbm_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def add_fiber(self, X, q, length, radius, density_ratio=1.0, V=(0, 0, 0), W=(0, 0, 0)):
+        f = lbm_fiber()
+        f.center = (C.c_double * 3)(*_f64(X, 3))
+        f.quat = (C.c_double * 4)(*_f64(q, 4))
+        f.length, f.radius, f.density_ratio = float(length), float(radius), float(density_ratio)
+        f.vel = (C.c_double * 3)(*_f64(V, 3))
+        f.omega = (C.c_double * 3)(*_f64(W, 3))
+        i = C.c_int32()
+        self._chk(load().lbm_add_fiber(self._h, C.byref(f), C.byref(i)))
+        self.nfibers += 1
+        return i.value
+
+    def set_kinematics(self, fid, traj):
+        t = _f64(traj).reshape(-1, 13)
+        self._chk(load().lbm_set_fiber_kinematics(self._h, fid, _d(t), t.shape[0]))
+
+    def step(self, n=1):
+        self._chk(load().lbm_step(self._h, int(n)))
+
+    def sync(self):
+        self._chk(load().lbm_sync(self._h))
+
+    def force_torque(self):
+        F, M = np.zeros((self.nfibers, 3)), np.zeros((self.nfibers, 3))
+        self._chk(load().lbm_get_force_torque(self._h, _d(F), _d(M)))
+        return F, M
+
+    def fields(self):
+        nx, ny, nz = self.shape
+        dt = np.float64 if self.storage == LBM_F64 else np.float32
+        rho = np.zeros((nz, ny, nx), dt)
+        u = np.zeros((3, nz, ny, nx), dt)
+        flags = np.zeros((nz, ny, nx), np.uint8)
+        pid = np.zeros((nz, ny, nx), np.int32)
+        self._chk(load().lbm_get_fields(self._h, rho.ctypes.data, u.ctypes.data, flags.ctypes.data,
+                                        pid.ctypes.data, 0))
+        return rho, u, flags, pid
+
+    def fields_to_device(self, rho_ptr, u_ptr):
+        """Write rho and u into device buffers (e.g. torch tensors' data_ptr())."""
+        self._chk(load().lbm_get_fields(self._h, C.c_void_p(rho_ptr), C.c_void_p(u_ptr), None,
+                                        None, 1))
+
+    def fiber_state(self):
+        n = self.nfibers
+        X, q, V, W = np.zeros((n, 3)), np.zeros((n, 4)), np.zeros((n, 3)), np.zeros((n, 3))
+        self._chk(load().lbm_get_fiber_state(self._h, _d(X), _d(q), _d(V), _d(W)))
+        return X, q, V, W
+
+    def set_fiber_state(self, fid, X, q, V=(0, 0, 0), W=(0, 0, 0)):
+        self._chk(load().lbm_set_fiber_state(self._h, fid, _d(_f64(X, 3)), _d(_f64(q, 4)),
+                                             _d(_f64(V, 3)), _d(_f64(W, 3))))
+
+    def history(self, first, count):
+        out = np.zeros((count, self.nfibers, 19))
+        self._chk(load().lbm_get_history(self._h, first, count, _d(out)))
+        return out
+
+    def populations(self):
+        nx, ny, nz = self.shape
+        f = np.zeros((19, nz, ny, nx))
+        self._chk(load().lbm_get_populations(self._h, _d(f)))
+        return f
+
+    def set_populations(self, f):
+        self._chk(load().lbm_set_populations(self._h, _d(_f64(f, 19 * self.ncell))))
+
+    def info(self):
+        i = lbm_info()
+        self._chk(load().lbm_get_info(self._h, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in lbm_info._fields_}
+
+    def enable_sweep_timing(self, on=True):
+        self._chk(load().lbm_enable_sweep_timing(self._h, int(bool(on))))
+
+    def sweep_time(self):
+        ms = C.c_double()
+        n = C.c_int64()
+        self._chk(load().lbm_get_sweep_time(self._h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value

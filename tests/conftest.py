@@ -3,6 +3,9 @@ import sys
 
 import pytest
 
+# the oracle is OpenMP code: never spin-wait when cores are shared
+os.environ.setdefault("OMP_WAIT_POLICY", "PASSIVE")
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

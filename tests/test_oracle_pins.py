@@ -439,3 +439,30 @@ def test_uncovered_cells_are_refilled_with_equilibrium():
     fe = O.feq(1.0, 1.0, V)
     for z, y, x in zip(*np.nonzero(unc)):
         np.testing.assert_array_equal(f[:, z, y, x], fe)
+
+
+# ---------------------------------------------------------------- P15 Jeffery
+def test_oracle_tumbling_period_near_jeffery():
+    """Jeffery's closed form T = 2 pi (r + 1/r) / shear rate holds for a
+    spheroid in unbounded Stokes flow; a staircase cylinder of aspect ratio
+    4 between walls two fiber lengths apart is only expected within a broad
+    band (cylinders tumble like spheroids of somewhat smaller aspect ratio).
+    The oracle's period (computed by tests/golden/make_jeffery_golden.py
+    from the oracle alone) must lie within 15 % of the closed form."""
+    import json
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import jeffery
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "jeffery_single_fiber.json")
+    d = json.load(open(path))
+    if "U0.02/seed0" not in d:
+        pytest.skip("golden period not generated")
+    e = d["U0.02/seed0"]
+    TJ = jeffery.jeffery_period(16.0 / 4.0, e["shear_rate"])
+    assert abs(e["period"] / TJ - 1) < 0.15
+    # at U = 0.005 the fiber settles near the flow direction (no crossing
+    # after the first half turn in 190000 steps)
+    if "U0.005/seed0" in d:
+        assert len(d["U0.005/seed0"]["crossings"]) == 1
