@@ -83,7 +83,9 @@ typedef struct {
     int32_t coupling;          /* lbm_coupling */
     int32_t fp16_scale_log2;   /* k for LBM_F16DEV (0..20) */
     int64_t history_capacity;  /* steps kept in the device history ring (>= 1) */
-    void *stream;              /* hipStream_t to order work on; NULL = the null stream */
+    void *stream;              /* hipStream_t to order work on; NULL: a private stream */
+    int32_t sweep_grid;        /* workgroups of the bulk sweep (grid-stride); 0 = automatic */
+    int32_t q_pad;             /* extra elements between direction arrays; -1 = automatic */
 } lbm_params;
 
 /* A rigid circular cylinder.  The axis is t = R(q) e_x for the unit
@@ -111,7 +113,8 @@ typedef struct {
 } lbm_info;
 
 /* Fill *p with defaults: 32^3, walls, TRT, tau 0.8, Lambda 3/16, U 0,
- * rho0 1, F32, rest, implicit coupling, k = 14, history 4096, NULL stream. */
+ * rho0 1, F32, rest, implicit coupling, k = 14, history 4096, NULL stream,
+ * automatic sweep grid and padding. */
 lbm_status lbm_params_default(lbm_params *p);
 
 /* Allocate the lattice and initialise f = f_eq(rho0, u0(z)) (Eq.

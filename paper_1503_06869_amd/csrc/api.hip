@@ -46,7 +46,7 @@ struct lbm_ctx {
     void *linkval = nullptr;
     uint32_t list_cap = 0;
     DevCounters *ctr = nullptr;
-    uint32_t remap_grid = 0, bnd_grid = 0;
+    uint32_t remap_grid = 0, bnd_grid = 0, sweep_grid = 0;
     int64_t steps = 0;
     int64_t device_bytes = 0;
     // graph of one even + one odd step
@@ -300,8 +300,9 @@ static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hi
     b.pid = c->pid;
     b.ps = cur;
     b.linkval = c->linkval;
-    hipError_t e = launch_sweep(c->sk, odd, c->f, c->flags, c->g, c->ph, b, c->np ? c->bnd_grid : 0,
-                                c->st, with_events ? e0 : nullptr, with_events ? e1 : nullptr);
+    hipError_t e = launch_sweep(c->sk, odd, c->f, c->flags, c->g, c->ph, b, c->sweep_grid,
+                                c->np ? c->bnd_grid : 0, c->st, with_events ? e0 : nullptr,
+                                with_events ? e1 : nullptr);
     if (e == hipSuccess && c->np) {
         PartData pd = part_data(c, cur, next);
         e = launch_particles(pd, c->g, c->pid, c->nref, c->linkval, c->sk == S_F64, c->st);
@@ -351,6 +352,8 @@ lbm_status lbm_params_default(lbm_params *p)
     p->coupling = LBM_COUPLING_IMPLICIT;
     p->fp16_scale_log2 = 14;
     p->history_capacity = 4096;
+    p->sweep_grid = 0;
+    p->q_pad = -1;
     return LBM_OK;
 }
 
@@ -373,7 +376,8 @@ lbm_status lbm_create(const lbm_params *p, lbm_ctx **out)
     *out = nullptr;
     if (p->nx < 3 || p->ny < 3 || p->nz < 3) return LBM_E_ARG;
     const double ncell = double(p->nx) * p->ny * p->nz;
-    if ((double(p->nz) + 2.0) * p->nx * p->ny >= 4294967295.0) return LBM_E_ARG;
+    if ((double(p->nz) + 2.0) * p->nx * p->ny + 65536.0 >= 4294967295.0) return LBM_E_ARG;
+    if (p->sweep_grid < 0 || p->q_pad > (1 << 20)) return LBM_E_ARG;
     if (!(p->tau > 0.5) || !(std::fabs(p->wall_u) < 0.1) || !(p->rho0 > 0.0)) return LBM_E_ARG;
     if (p->collision != LBM_TRT && p->collision != LBM_SRT) return LBM_E_ARG;
     if (p->collision == LBM_TRT && !(p->magic > 0.0)) return LBM_E_ARG;
@@ -393,6 +397,13 @@ lbm_status lbm_create(const lbm_params *p, lbm_ctx **out)
         c->own_stream = true;
     }
     c->sk = p->storage;
+    // bulk sweep: a grid-stride loop over 256-cell chunks with a few
+    // resident workgroups per CU keeps the 38 access streams compact
+    {
+        const uint32_t nchunk = uint32_t((double(p->nx) * p->ny * p->nz + 255.0) / 256.0);
+        uint32_t gsz = p->sweep_grid > 0 ? uint32_t(p->sweep_grid) : 2048u;
+        c->sweep_grid = gsz < nchunk ? gsz : nchunk;
+    }
     c->esz = c->sk == S_F64 ? 8 : (c->sk == S_F32 ? 4 : 2);
     c->scale = c->sk == S_F16 ? std::ldexp(1.0, p->fp16_scale_log2) : 1.0;
     Geo &g = c->g;
@@ -401,7 +412,10 @@ lbm_status lbm_create(const lbm_params *p, lbm_ctx **out)
     g.nz = p->nz;
     g.nxy = uint32_t(p->nx) * uint32_t(p->ny);
     g.ncell = uint32_t(ncell);
-    g.qstride = uint64_t(p->nz + 2) * g.nxy;
+    // Direction arrays are padded apart so that the 19 streams of a sweep do
+    // not start at addresses that are equal modulo a large power of two.
+    const uint64_t pad = p->q_pad >= 0 ? uint64_t(p->q_pad) : 1088u;
+    g.qstride = uint64_t(p->nz + 2) * g.nxy + pad;
     g.dnx = make_fastdiv(g.nx);
     g.dnxy = make_fastdiv(g.nxy);
     g.zper = p->z_periodic ? 1 : 0;

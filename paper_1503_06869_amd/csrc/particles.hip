@@ -498,9 +498,13 @@ __global__ __launch_bounds__(256) void k_rigid(PartData pd, Geo g)
     for (int t = threadIdx.x; t < np * 27; t += blockDim.x) {
         const int p = t / 27, k = t % 27;
         const double *pp = pd.partial + size_t(p) * ns * 27 + k;
-        double v = 0.0;
-        for (int j = 0; j < ns; ++j) v += pp[j * 27];
-        tot[t] = v;
+        double v[32];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) v[j] = j < ns ? pp[j * 27] : 0.0;   // all loads in flight
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < 32; ++j) acc += v[j];                        // slab order
+        tot[t] = acc;
     }
     __syncthreads();
     const int64_t step = int64_t(pd.ctr->step);

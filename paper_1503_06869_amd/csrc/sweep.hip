@@ -225,15 +225,19 @@ __device__ __forceinline__ void update_cell(S *__restrict__ f, const Geo &g,
     (void)six_r0;
 }
 
+// Grid-stride over 256-cell chunks: at any time the resident workgroups work
+// on one compact band of the lattice, which keeps each of the 38 access
+// streams (19 directions read, 19 written) within a few DRAM pages.
 template <typename S, bool ODD>
 __global__ __launch_bounds__(256) void k_sweep_bulk(S *__restrict__ f, const uint8_t *__restrict__ flags,
                                                     Geo g, Phys<typename St<S>::R> ph)
 {
-    const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
-    const uint32_t cell = b * 256u + threadIdx.x;
-    if (cell >= g.ncell) return;
-    if (flags[cell]) return;   // fiber cells idle; boundary cells go to k_sweep_bnd
-    update_cell<S, ODD, false>(f, g, ph, cell, 0u, 0u, BndData{});
+    const uint32_t nchunk = (g.ncell + 255u) >> 8;
+    for (uint32_t ch = xcd_block(blockIdx.x, gridDim.x); ch < nchunk; ch += gridDim.x) {
+        const uint32_t cell = (ch << 8) + threadIdx.x;
+        if (cell < g.ncell && !flags[cell])   // fiber cells idle; boundary cells: k_sweep_bnd
+            update_cell<S, ODD, false>(f, g, ph, cell, 0u, 0u, BndData{});
+    }
 }
 
 template <typename S, bool ODD>
@@ -372,12 +376,12 @@ static Phys<R> cast_phys(const Phys<double> &p)
 
 template <typename S>
 static hipError_t sweep_t(bool odd, void *f, const uint8_t *flags, const Geo &g,
-                          const Phys<double> &ph, const BndData &b, uint32_t bnd_grid,
-                          hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
+                          const Phys<double> &ph, const BndData &b, uint32_t sweep_grid,
+                          uint32_t bnd_grid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     using R = typename St<S>::R;
     const Phys<R> p = cast_phys<R>(ph);
-    const uint32_t nb = (g.ncell + 255u) / 256u;
+    const uint32_t nb = sweep_grid;
     if (ev0) hipEventRecord(ev0, st);
     if (odd)
         hipLaunchKernelGGL((k_sweep_bulk<S, true>), dim3(nb), dim3(256), 0, st, (S *)f, flags, g, p);
@@ -395,14 +399,14 @@ static hipError_t sweep_t(bool odd, void *f, const uint8_t *flags, const Geo &g,
 }
 
 hipError_t launch_sweep(int sk, bool odd, void *f, const uint8_t *flags, const Geo &g,
-                        const Phys<double> &ph, const BndData &b, uint32_t bnd_grid,
-                        hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
+                        const Phys<double> &ph, const BndData &b, uint32_t sweep_grid,
+                        uint32_t bnd_grid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     switch (sk) {
-    case S_F32: return sweep_t<float>(odd, f, flags, g, ph, b, bnd_grid, st, ev0, ev1);
-    case S_F16: return sweep_t<_Float16>(odd, f, flags, g, ph, b, bnd_grid, st, ev0, ev1);
-    case S_BF16: return sweep_t<bf16s>(odd, f, flags, g, ph, b, bnd_grid, st, ev0, ev1);
-    default: return sweep_t<double>(odd, f, flags, g, ph, b, bnd_grid, st, ev0, ev1);
+    case S_F32: return sweep_t<float>(odd, f, flags, g, ph, b, sweep_grid, bnd_grid, st, ev0, ev1);
+    case S_F16: return sweep_t<_Float16>(odd, f, flags, g, ph, b, sweep_grid, bnd_grid, st, ev0, ev1);
+    case S_BF16: return sweep_t<bf16s>(odd, f, flags, g, ph, b, sweep_grid, bnd_grid, st, ev0, ev1);
+    default: return sweep_t<double>(odd, f, flags, g, ph, b, sweep_grid, bnd_grid, st, ev0, ev1);
     }
 }
 

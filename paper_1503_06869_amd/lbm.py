@@ -37,7 +37,7 @@ class lbm_params(C.Structure):
                 ("rho0", C.c_double), ("body_force", C.c_double * 3),
                 ("storage", C.c_int32), ("init_profile", C.c_int32), ("coupling", C.c_int32),
                 ("fp16_scale_log2", C.c_int32), ("history_capacity", C.c_int64),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("sweep_grid", C.c_int32), ("q_pad", C.c_int32)]
 
 
 class lbm_fiber(C.Structure):
@@ -132,7 +132,7 @@ class Context:
     def __init__(self, nx, ny, nz, tau=0.8, magic=3.0 / 16.0, wall_u=0.0, rho0=1.0,
                  z_periodic=False, collision="trt", storage="f32", init_couette=False,
                  coupling="implicit", body_force=(0.0, 0.0, 0.0), fp16_scale_log2=14,
-                 history_capacity=4096, stream=None):
+                 history_capacity=4096, stream=None, sweep_grid=0, q_pad=-1):
         L = load()
         p = lbm_params()
         L.lbm_params_default(C.byref(p))
@@ -147,6 +147,8 @@ class Context:
         p.fp16_scale_log2 = fp16_scale_log2
         p.history_capacity = history_capacity
         p.stream = stream
+        p.sweep_grid = sweep_grid
+        p.q_pad = q_pad
         h = C.c_void_p()
         r = L.lbm_create(C.byref(p), C.byref(h))
         if r != LBM_OK:

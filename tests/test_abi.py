@@ -46,8 +46,8 @@ def test_lattice_table_needs_no_gpu():
 
 
 def test_struct_layout_matches_header():
-    # lbm_params: 5 int32, 4 doubles, 3 doubles, 4 int32, int64, pointer
-    assert C.sizeof(lbm.lbm_params) == 5 * 4 + 4 + 4 * 8 + 3 * 8 + 4 * 4 + 8 + 8
+    # lbm_params: 5 int32 (+4 pad), 4 doubles, 3 doubles, 4 int32, int64, pointer, 2 int32
+    assert C.sizeof(lbm.lbm_params) == 5 * 4 + 4 + 4 * 8 + 3 * 8 + 4 * 4 + 8 + 8 + 2 * 4
     assert C.sizeof(lbm.lbm_fiber) == (3 + 4 + 3 + 3 + 3) * 8
     assert C.sizeof(lbm.lbm_info) == 8 + 4 + 4 + 8 * 4
 
