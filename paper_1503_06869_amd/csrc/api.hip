@@ -56,6 +56,9 @@ struct lbm_ctx {
     bool timing = false;
     std::vector<hipEvent_t> ev;
     bool own_stream = false;
+    // second stream: boundary sweep and the particle chain run beside the bulk sweep
+    hipStream_t st2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     size_t ev_used = 0;
     int64_t timed_sweeps = 0;
     double timed_ms = 0.0;
@@ -284,6 +287,14 @@ static lbm_status check_device_errors(lbm_ctx *c)
     return LBM_OK;
 }
 
+// One time step as a two-branch graph of kernels:
+//   st : bulk sweep ----------------------------------------+--> near/list
+//   st2: boundary sweep -> momentum exchange -> rigid -> remap
+// The bulk sweep touches only slots of bulk cells; the boundary sweep, the
+// refill of the remap and the momentum exchange touch only slots and data
+// of cells next to fibers, so the branches are independent.  The flag and
+// list rebuild reads and writes the flags the bulk sweep reads, so it waits
+// for both branches.
 static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hipEvent_t e0,
                             hipEvent_t e1, hipError_t *err)
 {
@@ -300,17 +311,25 @@ static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hi
     b.pid = c->pid;
     b.ps = cur;
     b.linkval = c->linkval;
-    hipError_t e = launch_sweep(c->sk, odd, c->f, c->flags, c->g, c->ph, b, c->sweep_grid,
-                                c->np ? c->bnd_grid : 0, c->st, with_events ? e0 : nullptr,
-                                with_events ? e1 : nullptr);
-    if (e == hipSuccess && c->np) {
-        PartData pd = part_data(c, cur, next);
-        e = launch_particles(pd, c->g, c->pid, c->nref, c->linkval, c->sk == S_F64, c->st);
-        if (e == hipSuccess)
-            e = launch_remap(c->sk, !odd, c->f, c->pid, pd, c->g, c->p.rho0, c->scale, c->st);
-        if (e == hipSuccess)
-            e = launch_near(c->flags, c->pid, c->list_cell, c->list_mask, c->nref, pd, c->g, c->st);
+    hipError_t e = hipSuccess;
+    if (!c->np) {
+        e = launch_sweep(c->sk, odd, c->f, c->flags, c->g, c->ph, b, c->sweep_grid, 0, c->st, c->st,
+                         with_events ? e0 : nullptr, with_events ? e1 : nullptr);
+        if (e != hipSuccess && *err == hipSuccess) *err = e;
+        return;
     }
+    e = hipEventRecord(c->ev_fork, c->st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->st2, c->ev_fork, 0);
+    if (e == hipSuccess)
+        e = launch_sweep(c->sk, odd, c->f, c->flags, c->g, c->ph, b, c->sweep_grid, c->bnd_grid, c->st,
+                         c->st2, with_events ? e0 : nullptr, with_events ? e1 : nullptr);
+    PartData pd = part_data(c, cur, next);
+    if (e == hipSuccess) e = launch_particles(pd, c->g, c->pid, c->nref, c->linkval, c->sk == S_F64, c->st2);
+    if (e == hipSuccess) e = launch_remap(c->sk, !odd, c->f, c->pid, pd, c->g, c->p.rho0, c->scale, c->st2);
+    if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->st2);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->st, c->ev_join, 0);
+    if (e == hipSuccess)
+        e = launch_near(c->flags, c->pid, c->list_cell, c->list_mask, c->nref, pd, c->g, c->st);
     if (e != hipSuccess && *err == hipSuccess) *err = e;
 }
 
@@ -396,12 +415,21 @@ lbm_status lbm_create(const lbm_params *p, lbm_ctx **out)
         }
         c->own_stream = true;
     }
+    if (hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        lbm_destroy(c);
+        return LBM_E_HIP;
+    }
     c->sk = p->storage;
     // bulk sweep: a grid-stride loop over 256-cell chunks with a few
     // resident workgroups per CU keeps the 38 access streams compact
     {
         const uint32_t nchunk = uint32_t((double(p->nx) * p->ny * p->nz + 255.0) / 256.0);
-        uint32_t gsz = p->sweep_grid > 0 ? uint32_t(p->sweep_grid) : 2048u;
+        // measured on the 256^3 cell: FP32/FP64 best near 512 workgroups
+        // (leaving room for the boundary branch), 16-bit storage near 4096
+        const uint32_t dflt = (p->storage == LBM_F16DEV || p->storage == LBM_BF16DEV) ? 4096u : 512u;
+        uint32_t gsz = p->sweep_grid > 0 ? uint32_t(p->sweep_grid) : dflt;
         c->sweep_grid = gsz < nchunk ? gsz : nchunk;
     }
     c->esz = c->sk == S_F64 ? 8 : (c->sk == S_F32 ? 4 : 2);
@@ -465,6 +493,9 @@ lbm_status lbm_destroy(lbm_ctx *c)
     dfree(c->pid);
     dfree(c->nref);
     dfree(c->ctr);
+    if (c->st2) hipStreamDestroy(c->st2);
+    if (c->ev_fork) hipEventDestroy(c->ev_fork);
+    if (c->ev_join) hipEventDestroy(c->ev_join);
     if (c->own_stream) hipStreamDestroy(c->st);
     delete c;
     return LBM_OK;

@@ -151,9 +151,12 @@ enum StorageKind { S_F32 = 0, S_F16 = 1, S_BF16 = 2, S_F64 = 3 };
 
 hipError_t launch_init(int sk, void *f, const Geo &g, double rho0, double wall_u, int couette,
                        double scale, hipStream_t st);
+// bulk sweep on st (bracketed by ev0/ev1 if given), boundary sweep on st_bnd;
+// either part is skipped when its grid is 0
 hipError_t launch_sweep(int sk, bool odd, void *f, const uint8_t *flags, const Geo &g,
                         const Phys<double> &ph, const BndData &b, uint32_t sweep_grid,
-                        uint32_t bnd_grid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
+                        uint32_t bnd_grid, hipStream_t st, hipStream_t st_bnd, hipEvent_t ev0,
+                        hipEvent_t ev1);
 hipError_t launch_decode(int sk, bool swapped, const void *f, const uint8_t *flags,
                          const int32_t *pid, const PState *ps, const Geo &g, const Phys<double> &ph,
                          void *rho, void *u, double *fout, hipStream_t st);

@@ -118,6 +118,91 @@ __device__ __forceinline__ bool boxes_meet(const Box &a, const Box &b, const Geo
     return true;
 }
 
+// ------------------------------------------------------------------ per-plane rectangles
+// Within a box, plane z is crossed by the capsule of radius r + RECT_MARGIN
+// around the fiber axis segment only in an x/y rectangle; every cell that a
+// fiber can own, or border (fluid neighbours lie within sqrt(2) of owned
+// cell centres), is inside it.  Rectangles are in the unwrapped frame of
+// the box; for boxes narrower than the domain they are clipped to the box.
+constexpr double RECT_MARGIN = 2.5;
+
+struct Rect {
+    int32_t x0, x1, y0, y1;   // inclusive; empty when x0 > x1
+};
+
+__device__ __forceinline__ Rect plane_rect(const PState &s, const PConst &c, int32_t z, const Box &b,
+                                           const Geo &g)
+{
+    Rect r{1, 0, 1, 0};
+    const double R = c.radius + RECT_MARGIN, hl = 0.5 * c.length;
+    const double dz = mi_d(double(z) - s.X[2], g.nz, g.zper != 0);
+    const double tz = s.t[2];
+    double slo, shi;
+    if (fabs(tz) < 1e-12) {
+        if (fabs(dz) > R) return r;
+        slo = -hl;
+        shi = hl;
+    } else {
+        const double a = (dz - R) / tz, bb = (dz + R) / tz;
+        slo = fmax(fmin(a, bb), -hl);
+        shi = fmin(fmax(a, bb), hl);
+        if (slo > shi) return r;
+    }
+    const double mx = double(b.lo[0]) + 0.5 * double(b.len[0]);
+    const double my = double(b.lo[1]) + 0.5 * double(b.len[1]);
+    const double cx = mx + mi_d(s.X[0] - mx, g.nx, true), cy = my + mi_d(s.X[1] - my, g.ny, true);
+    const double xa = slo * s.t[0], xb = shi * s.t[0], ya = slo * s.t[1], yb = shi * s.t[1];
+    r.x0 = int32_t(floor(cx + fmin(xa, xb) - R));
+    r.x1 = int32_t(ceil(cx + fmax(xa, xb) + R));
+    r.y0 = int32_t(floor(cy + fmin(ya, yb) - R));
+    r.y1 = int32_t(ceil(cy + fmax(ya, yb) + R));
+    if (b.len[0] < int32_t(g.nx)) {
+        r.x0 = max(r.x0, b.lo[0]);
+        r.x1 = min(r.x1, b.lo[0] + b.len[0] - 1);
+    } else if (r.x1 - r.x0 + 1 > int32_t(g.nx)) {
+        r.x1 = r.x0 + int32_t(g.nx) - 1;
+    }
+    if (b.len[1] < int32_t(g.ny)) {
+        r.y0 = max(r.y0, b.lo[1]);
+        r.y1 = min(r.y1, b.lo[1] + b.len[1] - 1);
+    } else if (r.y1 - r.y0 + 1 > int32_t(g.ny)) {
+        r.y1 = r.y0 + int32_t(g.ny) - 1;
+    }
+    return r;
+}
+
+__device__ __forceinline__ Rect rect_union(Rect a, Rect b, const Geo &g)
+{
+    if (a.x0 > a.x1 || a.y0 > a.y1) return b;
+    if (b.x0 > b.x1 || b.y0 > b.y1) return a;
+    Rect r{min(a.x0, b.x0), max(a.x1, b.x1), min(a.y0, b.y0), max(a.y1, b.y1)};
+    if (r.x1 - r.x0 + 1 > int32_t(g.nx)) r.x1 = r.x0 + int32_t(g.nx) - 1;
+    if (r.y1 - r.y0 + 1 > int32_t(g.ny)) r.y1 = r.y0 + int32_t(g.ny) - 1;
+    return r;
+}
+
+__device__ __forceinline__ bool in_rect(const Rect &r, int32_t x, int32_t y, const Geo &g)
+{
+    if (r.x0 > r.x1 || r.y0 > r.y1) return false;
+    return wrapi(x - r.x0, g.nx) <= r.x1 - r.x0 && wrapi(y - r.y0, g.ny) <= r.y1 - r.y0;
+}
+
+// is plane z (domain coordinate) inside the z-range of box b?
+__device__ __forceinline__ bool in_zrange(const Box &b, int32_t z, const Geo &g)
+{
+    int32_t d = z - b.lo[2];
+    if (g.zper) d = wrapi(d, g.nz);
+    return d >= 0 && d < b.len[2];
+}
+
+// plane rectangle of fiber o's remap region: both poses of the step
+__device__ __forceinline__ Rect remap_rect(const PartData &pd, int o, int32_t z, const Geo &g)
+{
+    const Box b = pd.box_remap[o];
+    const PConst c = pd.pc[o];
+    return rect_union(plane_rect(pd.ps_cur[o], c, z, b, g), plane_rect(pd.ps_next[o], c, z, b, g), g);
+}
+
 // ------------------------------------------------------------------ boxes of the remap
 // Runs in one block: union of the box of the old pose (box_cur) and the new
 // pose (ps_next) per fiber, their cell-count prefix, and for every fiber the
@@ -405,7 +490,7 @@ __device__ __forceinline__ void add_link(double *acc, int q, double ft, double r
     acc[24] += k6 * rc1 * rc1; acc[25] += k6 * rc1 * rc2; acc[26] += k6 * rc2 * rc2;
 }
 
-constexpr int PF = 8;   // box cells per thread whose near-cell records are fetched together
+constexpr int PF = 4;   // cells per thread whose near-cell records are fetched together
 
 template <typename LV>
 __global__ __launch_bounds__(256) void k_particles(PartData pd, Geo g, const int32_t *__restrict__ pid,
@@ -421,11 +506,14 @@ __global__ __launch_bounds__(256) void k_particles(PartData pd, Geo g, const int
     for (int k = 0; k < 27; ++k) acc[k] = 0.0;
     const double r0 = pd.rho0;
     const int32_t nx = g.nx, ny = g.ny, nz = g.nz;
-    const int area = bx.len[0] * bx.len[1];
+    const PConst pc = pd.pc[p];
     for (int iz = sl; iz < bx.len[2]; iz += ns) {
         int32_t cz = bx.lo[2] + iz;
         if (g.zper) cz = wrapc(cz, nz);
         else if (cz < 0 || cz >= nz) continue;
+        const Rect rc = plane_rect(s, pc, cz, bx, g);
+        if (rc.x0 > rc.x1 || rc.y0 > rc.y1) continue;
+        const int wx = rc.x1 - rc.x0 + 1, area = wx * (rc.y1 - rc.y0 + 1);
         for (int base = 0; base < area; base += 256 * PF) {
             uint64_t rec[PF];
             int32_t cxv[PF], cyv[PF];
@@ -435,9 +523,9 @@ __global__ __launch_bounds__(256) void k_particles(PartData pd, Geo g, const int
                 rec[k] = 0;
                 cxv[k] = cyv[k] = 0;
                 if (i < area) {
-                    const int iy = i / bx.len[0], ix = i - iy * bx.len[0];
-                    cxv[k] = wrapc(bx.lo[0] + ix, nx);
-                    cyv[k] = wrapc(bx.lo[1] + iy, ny);
+                    const int iy = i / wx, ix = i - iy * wx;
+                    cxv[k] = wrapi(rc.x0 + ix, nx);
+                    cyv[k] = wrapi(rc.y0 + iy, ny);
                     rec[k] = nref[(uint32_t(cz) * g.ny + uint32_t(cyv[k])) * g.nx + uint32_t(cxv[k])];
                 }
             }
@@ -548,7 +636,9 @@ __global__ __launch_bounds__(256) void k_rigid(PartData pd, Geo g)
 struct NbrStage {
     int32_t id[NBR_CAP];
     Box box[NBR_CAP];
-    int32_t n;
+    Rect rect[NBR_CAP];   // plane rectangle of each lower-indexed neighbour (current plane)
+    uint8_t zin[NBR_CAP]; // current plane inside the neighbour's box
+    int32_t n, nlow;
 };
 
 __device__ __forceinline__ void stage_nbrs(const PartData &pd, int p, NbrStage &sh)
@@ -559,17 +649,32 @@ __device__ __forceinline__ void stage_nbrs(const PartData &pd, int p, NbrStage &
         sh.id[k] = o;
         sh.box[k] = pd.box_remap[o];
     }
-    if (threadIdx.x == 0) sh.n = nn;
+    if (threadIdx.x == 0) {
+        int nl = 0;
+        while (nl < nn && pd.nbr[p * NBR_CAP + nl] < p) ++nl;   // ascending ids
+        sh.n = nn;
+        sh.nlow = nl;
+    }
     __syncthreads();
 }
 
-__device__ __forceinline__ bool owned_here(const NbrStage &sh, int p, int32_t x, int32_t y, int32_t z,
-                                           const Geo &g)
+// rectangles of the lower-indexed neighbours for plane z (block-uniform call)
+__device__ __forceinline__ void stage_plane(const PartData &pd, NbrStage &sh, int32_t z, const Geo &g)
 {
-    for (int k = 0; k < sh.n; ++k) {
-        if (sh.id[k] >= p) break;   // ascending ids
-        if (in_box(sh.box[k], x, y, z, g)) return false;
+    __syncthreads();
+    for (int k = threadIdx.x; k < sh.nlow; k += blockDim.x) {
+        const int o = sh.id[k];
+        sh.zin[k] = in_zrange(sh.box[k], z, g);
+        if (sh.zin[k]) sh.rect[k] = remap_rect(pd, o, z, g);
     }
+    __syncthreads();
+}
+
+// a cell is handled by the lowest-indexed fiber whose remap region holds it
+__device__ __forceinline__ bool owned_here(const NbrStage &sh, int32_t x, int32_t y, const Geo &g)
+{
+    for (int k = 0; k < sh.nlow; ++k)
+        if (sh.zin[k] && in_rect(sh.rect[k], x, y, g)) return false;
     return true;
 }
 
@@ -605,24 +710,27 @@ __global__ __launch_bounds__(256) void k_remap(S *__restrict__ f, int32_t *__res
     const PState sp = pd.ps_next[p];
     const PConst cp = pd.pc[p];
     const int32_t nx = g.nx, ny = g.ny, nz = g.nz;
-    const int area = b.len[0] * b.len[1];
-    for (int iz = sl; iz < b.len[2]; iz += ns) {
+    for (int iz = sl; iz < b.len[2]; iz += ns) {   // block-uniform
         int32_t z = b.lo[2] + iz;
         if (g.zper) z = wrapc(z, nz);
         else if (z < 0 || z >= nz) continue;
+        stage_plane(pd, sh, z, g);
+        const Rect rc = remap_rect(pd, p, z, g);
+        if (rc.x0 > rc.x1 || rc.y0 > rc.y1) continue;
+        const int wx = rc.x1 - rc.x0 + 1, area = wx * (rc.y1 - rc.y0 + 1);
         for (int i = threadIdx.x; i < area; i += blockDim.x) {
-            const int iy = i / b.len[0], ix = i - iy * b.len[0];
-            const int32_t x = wrapc(b.lo[0] + ix, nx), y = wrapc(b.lo[1] + iy, ny);
-            if (!owned_here(sh, p, x, y, z, g)) continue;
+            const int iy = i / wx, ix = i - iy * wx;
+            const int32_t x = wrapi(rc.x0 + ix, nx), y = wrapi(rc.y0 + iy, ny);
+            if (!owned_here(sh, x, y, g)) continue;
             const double cx = x, cy = y, cz = z;
             int owner = -1, claims = 0;
             if (inside(sp, cp, cx, cy, cz, g)) {
                 owner = p;
                 claims = 1;
             }
-            for (int k = 0; k < sh.n; ++k) {
+            for (int k = sh.nlow; k < sh.n; ++k) {
                 const int o = sh.id[k];
-                if (o < p || !in_box(sh.box[k], x, y, z, g)) continue;
+                if (!in_box(sh.box[k], x, y, z, g)) continue;
                 if (inside(pd.ps_next[o], pd.pc[o], cx, cy, cz, g)) {
                     if (owner < 0) owner = o;
                     ++claims;
@@ -686,15 +794,18 @@ __global__ __launch_bounds__(256) void k_near(uint8_t *__restrict__ flags, const
     const Box b = pd.box_remap[p];
     const uint32_t off = pd.seg_off[p], cap = pd.seg_cap[p];
     const int32_t nx = g.nx, ny = g.ny, nz = g.nz;
-    const int area = b.len[0] * b.len[1];
     for (int iz = sl; iz < b.len[2]; iz += ns) {   // block-uniform
         int32_t z = b.lo[2] + iz;
         if (g.zper) z = wrapc(z, nz);
         else if (z < 0 || z >= nz) continue;
+        stage_plane(pd, sh, z, g);
+        const Rect rc = remap_rect(pd, p, z, g);
+        const int wx = rc.x1 - rc.x0 + 1;
+        const int area = (rc.x0 > rc.x1 || rc.y0 > rc.y1) ? 0 : wx * (rc.y1 - rc.y0 + 1);
         for (int i = threadIdx.x; i < area; i += blockDim.x) {
-            const int iy = i / b.len[0], ix = i - iy * b.len[0];
-            const int32_t x = wrapc(b.lo[0] + ix, nx), y = wrapc(b.lo[1] + iy, ny);
-            if (!owned_here(sh, p, x, y, z, g)) continue;
+            const int iy = i / wx, ix = i - iy * wx;
+            const int32_t x = wrapi(rc.x0 + ix, nx), y = wrapi(rc.y0 + iy, ny);
+            if (!owned_here(sh, x, y, g)) continue;
             const uint32_t cell = (uint32_t(z) * g.ny + uint32_t(y)) * g.nx + uint32_t(x);
             if (pid[cell] >= 0) {
                 flags[cell] = F_SOLID;

@@ -377,36 +377,39 @@ static Phys<R> cast_phys(const Phys<double> &p)
 template <typename S>
 static hipError_t sweep_t(bool odd, void *f, const uint8_t *flags, const Geo &g,
                           const Phys<double> &ph, const BndData &b, uint32_t sweep_grid,
-                          uint32_t bnd_grid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
+                          uint32_t bnd_grid, hipStream_t st, hipStream_t st_bnd, hipEvent_t ev0,
+                          hipEvent_t ev1)
 {
     using R = typename St<S>::R;
     const Phys<R> p = cast_phys<R>(ph);
-    const uint32_t nb = sweep_grid;
-    if (ev0) hipEventRecord(ev0, st);
-    if (odd)
-        hipLaunchKernelGGL((k_sweep_bulk<S, true>), dim3(nb), dim3(256), 0, st, (S *)f, flags, g, p);
-    else
-        hipLaunchKernelGGL((k_sweep_bulk<S, false>), dim3(nb), dim3(256), 0, st, (S *)f, flags, g, p);
-    if (ev1) hipEventRecord(ev1, st);
+    if (sweep_grid) {
+        if (ev0) hipEventRecord(ev0, st);
+        if (odd)
+            hipLaunchKernelGGL((k_sweep_bulk<S, true>), dim3(sweep_grid), dim3(256), 0, st, (S *)f, flags, g, p);
+        else
+            hipLaunchKernelGGL((k_sweep_bulk<S, false>), dim3(sweep_grid), dim3(256), 0, st, (S *)f, flags, g, p);
+        if (ev1) hipEventRecord(ev1, st);
+    }
     if (bnd_grid) {
         bnd_grid = uint32_t(b.np * b.bpf);
         if (odd)
-            hipLaunchKernelGGL((k_sweep_bnd<S, true>), dim3(bnd_grid), dim3(256), 0, st, (S *)f, g, p, b);
+            hipLaunchKernelGGL((k_sweep_bnd<S, true>), dim3(bnd_grid), dim3(256), 0, st_bnd, (S *)f, g, p, b);
         else
-            hipLaunchKernelGGL((k_sweep_bnd<S, false>), dim3(bnd_grid), dim3(256), 0, st, (S *)f, g, p, b);
+            hipLaunchKernelGGL((k_sweep_bnd<S, false>), dim3(bnd_grid), dim3(256), 0, st_bnd, (S *)f, g, p, b);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_sweep(int sk, bool odd, void *f, const uint8_t *flags, const Geo &g,
                         const Phys<double> &ph, const BndData &b, uint32_t sweep_grid,
-                        uint32_t bnd_grid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
+                        uint32_t bnd_grid, hipStream_t st, hipStream_t st_bnd, hipEvent_t ev0,
+                        hipEvent_t ev1)
 {
     switch (sk) {
-    case S_F32: return sweep_t<float>(odd, f, flags, g, ph, b, sweep_grid, bnd_grid, st, ev0, ev1);
-    case S_F16: return sweep_t<_Float16>(odd, f, flags, g, ph, b, sweep_grid, bnd_grid, st, ev0, ev1);
-    case S_BF16: return sweep_t<bf16s>(odd, f, flags, g, ph, b, sweep_grid, bnd_grid, st, ev0, ev1);
-    default: return sweep_t<double>(odd, f, flags, g, ph, b, sweep_grid, bnd_grid, st, ev0, ev1);
+    case S_F32: return sweep_t<float>(odd, f, flags, g, ph, b, sweep_grid, bnd_grid, st, st_bnd, ev0, ev1);
+    case S_F16: return sweep_t<_Float16>(odd, f, flags, g, ph, b, sweep_grid, bnd_grid, st, st_bnd, ev0, ev1);
+    case S_BF16: return sweep_t<bf16s>(odd, f, flags, g, ph, b, sweep_grid, bnd_grid, st, st_bnd, ev0, ev1);
+    default: return sweep_t<double>(odd, f, flags, g, ph, b, sweep_grid, bnd_grid, st, st_bnd, ev0, ev1);
     }
 }
 

@@ -5,7 +5,11 @@ The period of a Jeffery orbit is measured from the fiber axis history: the
 x component of the axis changes sign each time the fiber passes through the
 gradient direction, twice per period.  Crossing times are located by linear
 interpolation; the first crossing is discarded (start-up transient) and the
-period is twice the mean interval between the remaining crossings."""
+period is twice the mean interval between the following crossings, up to the
+fourth crossing.  (The coarse staircase fibers used here eventually settle
+next to the flow direction after a few turns: a fiber of diameter 4 cells
+is held where its end cells change; which turn that happens on depends on
+rounding, so only the regular turns before it are used.)"""
 import numpy as np
 
 
@@ -26,12 +30,12 @@ def crossings(tx, step0=1):
     return np.array(t)
 
 
-def period(tx, step0=1, min_crossings=3):
+def period(tx, step0=1, min_crossings=3, max_crossings=4):
     """Returns (period, crossing times) or (nan, crossings) if too few."""
     c = crossings(tx, step0)
     if len(c) < min_crossings:
         return float("nan"), c
-    return 2.0 * float(np.mean(np.diff(c[1:]))), c
+    return 2.0 * float(np.mean(np.diff(c[1:max_crossings]))), c
 
 
 def jeffery_period(aspect_ratio, shear_rate):
