@@ -26,7 +26,6 @@ struct lbm_ctx {
     void *f = nullptr;
     uint8_t *flags = nullptr;
     int32_t *pid = nullptr;
-    uint64_t *nref = nullptr;
     // particles
     int np = 0;
     std::vector<lbm_fiber> fib;
@@ -35,7 +34,7 @@ struct lbm_ctx {
     PState *ps[2] = {nullptr, nullptr};
     PConst *pc = nullptr;
     Box *box_cur = nullptr, *box_remap = nullptr;
-    double *partial = nullptr;
+    long long *mea = nullptr;
     uint32_t *seg_off = nullptr, *seg_cap = nullptr, *seg_cnt = nullptr;
     int nslab = 4, bpf = 1;
     int32_t *nbr = nullptr, *nbr_n = nullptr;
@@ -43,7 +42,6 @@ struct lbm_ctx {
     int64_t *traj_pos = nullptr;
     double *ft = nullptr, *hist = nullptr;
     uint32_t *list_cell = nullptr, *list_mask = nullptr;
-    void *linkval = nullptr;
     uint32_t list_cap = 0;
     DevCounters *ctr = nullptr;
     uint32_t remap_grid = 0, bnd_grid = 0, sweep_grid = 0;
@@ -101,7 +99,7 @@ static void free_particles(lbm_ctx *c)
     dfree(c->pc);
     dfree(c->box_cur);
     dfree(c->box_remap);
-    dfree(c->partial);
+    dfree(c->mea);
     dfree(c->seg_off);
     dfree(c->seg_cap);
     dfree(c->seg_cnt);
@@ -113,7 +111,6 @@ static void free_particles(lbm_ctx *c)
     dfree(c->hist);
     dfree(c->list_cell);
     dfree(c->list_mask);
-    dfree(c->linkval);
 }
 
 static void drop_graph(lbm_ctx *c)
@@ -157,7 +154,7 @@ static PartData part_data(lbm_ctx *c, PState *cur, PState *next)
     pd.ps_next = next;
     pd.box_cur = c->box_cur;
     pd.box_remap = c->box_remap;
-    pd.partial = c->partial;
+    pd.mea = c->mea;
     pd.seg_off = c->seg_off;
     pd.seg_cap = c->seg_cap;
     pd.seg_cnt = c->seg_cnt;
@@ -198,7 +195,8 @@ static lbm_status upload_particles(lbm_ctx *c)
     HIPCHK(c, dalloc(c, &c->box_remap, np));
     // blocks per fiber for the momentum exchange, remap and list kernels
     c->nslab = std::max(4, std::min(32, 2048 / np));
-    HIPCHK(c, dalloc(c, &c->partial, size_t(np) * c->nslab * 27));
+    HIPCHK(c, dalloc(c, &c->mea, size_t(np) * NACC));
+    HIPCHK(c, hipMemsetAsync(c->mea, 0, size_t(np) * NACC * sizeof(long long), c->st));
     HIPCHK(c, dalloc(c, &c->seg_off, np));
     HIPCHK(c, dalloc(c, &c->seg_cap, np));
     HIPCHK(c, dalloc(c, &c->seg_cnt, np));
@@ -224,8 +222,6 @@ static lbm_status upload_particles(lbm_ctx *c)
     c->list_cap = uint32_t(total);
     HIPCHK(c, dalloc(c, &c->list_cell, c->list_cap));
     HIPCHK(c, dalloc(c, &c->list_mask, c->list_cap));
-    HIPCHK(c, hipMalloc(&c->linkval, size_t(c->list_cap) * Q * (c->sk == S_F64 ? 8 : 4)));
-    c->device_bytes += int64_t(size_t(c->list_cap) * Q * (c->sk == S_F64 ? 8 : 4));
     HIPCHK(c, hipMemcpyAsync(c->seg_off, soff.data(), np * sizeof(uint32_t), hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipMemcpyAsync(c->seg_cap, scap.data(), np * sizeof(uint32_t), hipMemcpyHostToDevice, c->st));
     // boundary sweep: blocks per fiber segment, about four entries per thread
@@ -270,7 +266,7 @@ static lbm_status setup_mapping(lbm_ctx *c, PState *old_states)
     HIPCHK(c, launch_setup_boxes(pd, c->g, c->st));
     HIPCHK(c, launch_remap(c->sk, (c->steps & 1) != 0, c->f, c->pid, pd, c->g, c->p.rho0, c->scale,
                            c->st));
-    HIPCHK(c, launch_near(c->flags, c->pid, c->list_cell, c->list_mask, c->nref, pd, c->g, c->st));
+    HIPCHK(c, launch_near(c->flags, c->pid, c->list_cell, c->list_mask, pd, c->g, c->st));
     return LBM_OK;
 }
 
@@ -310,7 +306,8 @@ static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hi
     b.bpf = c->bpf;
     b.pid = c->pid;
     b.ps = cur;
-    b.linkval = c->linkval;
+    b.mea = c->mea;
+    b.ctr = c->ctr;
     hipError_t e = hipSuccess;
     if (!c->np) {
         e = launch_sweep(c->sk, odd, c->f, c->flags, c->g, c->ph, b, c->sweep_grid, 0, c->st, c->st,
@@ -324,12 +321,12 @@ static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hi
         e = launch_sweep(c->sk, odd, c->f, c->flags, c->g, c->ph, b, c->sweep_grid, c->bnd_grid, c->st,
                          c->st2, with_events ? e0 : nullptr, with_events ? e1 : nullptr);
     PartData pd = part_data(c, cur, next);
-    if (e == hipSuccess) e = launch_particles(pd, c->g, c->pid, c->nref, c->linkval, c->sk == S_F64, c->st2);
+    if (e == hipSuccess) e = launch_rigid(pd, c->g, c->st2);
     if (e == hipSuccess) e = launch_remap(c->sk, !odd, c->f, c->pid, pd, c->g, c->p.rho0, c->scale, c->st2);
     if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->st2);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->st, c->ev_join, 0);
     if (e == hipSuccess)
-        e = launch_near(c->flags, c->pid, c->list_cell, c->list_mask, c->nref, pd, c->g, c->st);
+        e = launch_near(c->flags, c->pid, c->list_cell, c->list_mask, pd, c->g, c->st);
     if (e != hipSuccess && *err == hipSuccess) *err = e;
 }
 
@@ -465,10 +462,9 @@ lbm_status lbm_create(const lbm_params *p, lbm_ctx **out)
     if (hipMalloc(&c->f, size_t(Q) * g.qstride * c->esz) != hipSuccess) return bail(LBM_E_NOMEM, "f");
     c->device_bytes += int64_t(size_t(Q) * g.qstride * c->esz);
     if (dalloc(c, &c->flags, g.ncell) != hipSuccess || dalloc(c, &c->pid, g.ncell) != hipSuccess ||
-        dalloc(c, &c->nref, g.ncell) != hipSuccess || dalloc(c, &c->ctr, 1) != hipSuccess)
+        dalloc(c, &c->ctr, 1) != hipSuccess)
         return bail(LBM_E_NOMEM, "fields");
     if (hipMemsetAsync(c->flags, 0, g.ncell, c->st) != hipSuccess ||
-        hipMemsetAsync(c->nref, 0, size_t(g.ncell) * 8, c->st) != hipSuccess ||
         hipMemsetAsync(c->pid, 0xFF, size_t(g.ncell) * 4, c->st) != hipSuccess ||
         hipMemsetAsync(c->ctr, 0, sizeof(DevCounters), c->st) != hipSuccess)
         return bail(LBM_E_HIP, "memset");
@@ -491,7 +487,6 @@ lbm_status lbm_destroy(lbm_ctx *c)
     dfree(c->f);
     dfree(c->flags);
     dfree(c->pid);
-    dfree(c->nref);
     dfree(c->ctr);
     if (c->st2) hipStreamDestroy(c->st2);
     if (c->ev_fork) hipEventDestroy(c->ev_fork);
@@ -526,7 +521,7 @@ lbm_status lbm_add_fiber(lbm_ctx *c, const lbm_fiber *f, int32_t *id)
         if (!per && (f->center[k] - ext < 1.0 || f->center[k] + ext > n[k] - 2.0))
             return fail(c, LBM_E_GEOM, "fiber within one cell of a wall");
     }
-    if ((c->np + 1) * 27 * 8 > 65536) return fail(c, LBM_E_ARG, "at most 303 fibers per context");
+    if ((c->np + 1) * NACC * 8 > 65536) return fail(c, LBM_E_ARG, "at most 302 fibers per context");
     PConst pc{};
     pc.length = f->length;
     pc.radius = f->radius;
@@ -555,7 +550,6 @@ lbm_status lbm_add_fiber(lbm_ctx *c, const lbm_fiber *f, int32_t *id)
         c->np--;
         hipMemsetAsync(c->flags, 0, c->g.ncell, c->st);
         hipMemsetAsync(c->pid, 0xFF, size_t(c->g.ncell) * 4, c->st);
-        hipMemsetAsync(c->nref, 0, size_t(c->g.ncell) * 8, c->st);
         hipMemsetAsync(c->ctr, 0, sizeof(DevCounters), c->st);
         lbm_status s2 = upload_particles(c);
         if (s2 == LBM_OK) s2 = setup_mapping(c, nullptr);

@@ -72,9 +72,17 @@ struct Box {               // cells lo[k] .. lo[k]+len[k]-1 (wrapped where perio
 };
 constexpr int NBR_CAP = 128;   // neighbours per fiber whose boxes may intersect
 
-// per-fiber accumulators of the momentum exchange (FP64):
-// F0[3] M0[3] A[6] (sym xx xy xz yy yz zz) B[9] C[6]
-constexpr int NACC = 30;
+// Per-fiber sums of the momentum exchange: F0[3] M0[3] A[6] (symmetric:
+// xx xy xz yy yz zz) B[9] C[6].  They are accumulated as int64 fixed point
+// (each link's FP64 term scaled by 2^FX_k and rounded), so that the sums are
+// exact and do not depend on the order in which links are added; FP64 is
+// restored once per step.  Scales leave ample range for fibers of
+// thousands of links: |F0| < 2^11, |M0| < 2^17, |A|,|B| < 2^23, |C| < 2^37.
+constexpr int NACC = 27;
+__host__ __device__ constexpr int fx_shift(int k)
+{
+    return k < 3 ? 52 : (k < 6 ? 46 : (k < 21 ? 40 : 26));
+}
 
 // device-side counters and error flags
 struct DevCounters {
@@ -117,7 +125,8 @@ struct BndData {               // boundary-cell list and particle access for the
     int32_t bpf;               // blocks per fiber segment
     const int32_t *pid;
     const PState *ps;          // state at the time level of the sweep
-    void *linkval;             // [entry][Q] post-collision deviation (compute type)
+    long long *mea;            // [np][NACC] fixed-point momentum-exchange sums
+    DevCounters *ctr;          // error flags
 };
 
 struct PartData {
@@ -138,7 +147,7 @@ struct PartData {
     DevCounters *ctr;
     uint32_t list_cap;
     int32_t nslab;             // blocks per fiber (z-planes of a box dealt round robin)
-    double *partial;           // [np][nslab][27] per-block momentum-exchange sums
+    long long *mea;            // [np][NACC] fixed-point momentum-exchange sums
     const uint32_t *seg_off;   // [np] list segment of each fiber: start
     const uint32_t *seg_cap;   // [np] capacity
     uint32_t *seg_cnt;         // [np] entries
@@ -162,13 +171,12 @@ hipError_t launch_decode(int sk, bool swapped, const void *f, const uint8_t *fla
                          void *rho, void *u, double *fout, hipStream_t st);
 hipError_t launch_encode(int sk, bool swapped, void *f, const Geo &g, double rho0, double scale,
                          const double *fin, hipStream_t st);
-hipError_t launch_particles(const PartData &pd, const Geo &g, const int32_t *pid, const uint64_t *nref,
-                            const void *linkval, int linkval_is_double, hipStream_t st);
+hipError_t launch_rigid(const PartData &pd, const Geo &g, hipStream_t st);
 hipError_t launch_setup_boxes(const PartData &pd, const Geo &g, hipStream_t st);
 hipError_t launch_remap(int sk, bool next_odd, void *f, int32_t *pid, const PartData &pd, const Geo &g,
                         double rho0, double scale, hipStream_t st);
 hipError_t launch_near(uint8_t *flags, const int32_t *pid, uint32_t *list_cell, uint32_t *list_mask,
-                       uint64_t *nref, const PartData &pd, const Geo &g, hipStream_t st);
+                       const PartData &pd, const Geo &g, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, size_t nbytes, hipStream_t st);
 
 }  // namespace lbm

@@ -453,153 +453,29 @@ __device__ __forceinline__ void rigid_update(const PState &s, const PConst &c, c
     o.pad = 0.0;
 }
 
-// ------------------------------------------------------------------ momentum exchange
-// Links of fiber p: fluid cell x next to fiber cell y = x + c_q with
-// pid(y) = p.  The sweep stored the post-collision deviation f~'_q(x) of
-// every such link; here (Eq. LBMhydrodynForce, dx^3/dt = 1)
-//   dF = (2 f~_q - 6 w_q rho0 c_q.u_s) c_q,  dM = (y - X) x dF,
-// split into the velocity-free part (F0, M0) and the matrices A, B, C of
-// the part linear in u_s = V + W x (y - X).
-//
-// k_particles: np * nslab blocks of 256 threads.  Block (p, s) scans the
-// z-planes s, s + nslab, ... of fiber p's box and writes its 27 sums
-// (butterfly within each wavefront, wavefronts added in order).
-// k_rigid (one block) adds the nslab partial sums of each fiber in slab
-// order, advances every fiber and prepares the next remap: a fixed
-// assignment and fixed order throughout, so the result is reproducible.
+// ------------------------------------------------------------------ rigid update kernel
 __device__ __forceinline__ int32_t wrapc(int32_t v, int32_t n)
 {
     return v < 0 ? v + n : (v >= n ? v - n : v);
 }
 
-__device__ __forceinline__ void add_link(double *acc, int q, double ft, double rx, double ry,
-                                         double rz, double r0)
-{
-    const double m2 = 2.0 * (ft + wq(q) * r0);
-    const double c0 = CX[q], c1 = CY[q], c2 = CZ[q];
-    const double rc0 = ry * c2 - rz * c1, rc1 = rz * c0 - rx * c2, rc2 = rx * c1 - ry * c0;
-    const double k6 = 6.0 * wq(q) * r0;
-    acc[0] += m2 * c0; acc[1] += m2 * c1; acc[2] += m2 * c2;
-    acc[3] += m2 * rc0; acc[4] += m2 * rc1; acc[5] += m2 * rc2;
-    acc[6] += k6 * c0 * c0; acc[7] += k6 * c0 * c1; acc[8] += k6 * c0 * c2;
-    acc[9] += k6 * c1 * c1; acc[10] += k6 * c1 * c2; acc[11] += k6 * c2 * c2;
-    acc[12] += k6 * c0 * rc0; acc[13] += k6 * c0 * rc1; acc[14] += k6 * c0 * rc2;
-    acc[15] += k6 * c1 * rc0; acc[16] += k6 * c1 * rc1; acc[17] += k6 * c1 * rc2;
-    acc[18] += k6 * c2 * rc0; acc[19] += k6 * c2 * rc1; acc[20] += k6 * c2 * rc2;
-    acc[21] += k6 * rc0 * rc0; acc[22] += k6 * rc0 * rc1; acc[23] += k6 * rc0 * rc2;
-    acc[24] += k6 * rc1 * rc1; acc[25] += k6 * rc1 * rc2; acc[26] += k6 * rc2 * rc2;
-}
-
-constexpr int PF = 4;   // cells per thread whose near-cell records are fetched together
-
-template <typename LV>
-__global__ __launch_bounds__(256) void k_particles(PartData pd, Geo g, const int32_t *__restrict__ pid,
-                                                   const uint64_t *__restrict__ nref,
-                                                   const LV *__restrict__ linkval)
-{
-    const int ns = pd.nslab;
-    const int p = blockIdx.x / ns, sl = blockIdx.x % ns;
-    const PState s = pd.ps_cur[p];
-    const Box bx = pd.box_cur[p];
-    double acc[27];
-#pragma unroll
-    for (int k = 0; k < 27; ++k) acc[k] = 0.0;
-    const double r0 = pd.rho0;
-    const int32_t nx = g.nx, ny = g.ny, nz = g.nz;
-    const PConst pc = pd.pc[p];
-    for (int iz = sl; iz < bx.len[2]; iz += ns) {
-        int32_t cz = bx.lo[2] + iz;
-        if (g.zper) cz = wrapc(cz, nz);
-        else if (cz < 0 || cz >= nz) continue;
-        const Rect rc = plane_rect(s, pc, cz, bx, g);
-        if (rc.x0 > rc.x1 || rc.y0 > rc.y1) continue;
-        const int wx = rc.x1 - rc.x0 + 1, area = wx * (rc.y1 - rc.y0 + 1);
-        for (int base = 0; base < area; base += 256 * PF) {
-            uint64_t rec[PF];
-            int32_t cxv[PF], cyv[PF];
-#pragma unroll
-            for (int k = 0; k < PF; ++k) {
-                const int i = base + k * 256 + int(threadIdx.x);
-                rec[k] = 0;
-                cxv[k] = cyv[k] = 0;
-                if (i < area) {
-                    const int iy = i / wx, ix = i - iy * wx;
-                    cxv[k] = wrapi(rc.x0 + ix, nx);
-                    cyv[k] = wrapi(rc.y0 + iy, ny);
-                    rec[k] = nref[(uint32_t(cz) * g.ny + uint32_t(cyv[k])) * g.nx + uint32_t(cxv[k])];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < PF; ++k) {
-                const uint32_t m = uint32_t(rec[k]);
-                if (!m) continue;
-                const uint32_t e = uint32_t(rec[k] >> 32);
-                const int32_t cx = cxv[k], cy = cyv[k];
-                int32_t pv[Q];
-                double lv[Q];
-#pragma unroll
-                for (int q = 1; q < Q; ++q) {
-                    pv[q] = -1;
-                    lv[q] = 0.0;
-                    if ((m >> q) & 1u) {
-                        const int32_t yx = wrapc(cx + CX[q], nx), yy = wrapc(cy + CY[q], ny);
-                        int32_t yz = cz + CZ[q];
-                        if (g.zper) yz = wrapc(yz, nz);
-                        pv[q] = pid[(uint32_t(yz) * g.ny + uint32_t(yy)) * g.nx + uint32_t(yx)];
-                        lv[q] = double(linkval[uint64_t(e) * Q + q]);
-                    }
-                }
-#pragma unroll
-                for (int q = 1; q < Q; ++q) {
-                    if (pv[q] != p) continue;
-                    const int32_t yx = wrapc(cx + CX[q], nx), yy = wrapc(cy + CY[q], ny);
-                    int32_t yz = cz + CZ[q];
-                    if (g.zper) yz = wrapc(yz, nz);
-                    add_link(acc, q, lv[q], mi_d(double(yx) - s.X[0], g.nx, true),
-                             mi_d(double(yy) - s.X[1], g.ny, true),
-                             mi_d(double(yz) - s.X[2], g.nz, g.zper != 0), r0);
-                }
-            }
-        }
-    }
-    __shared__ double wsum[4][27];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < 27; ++k) {
-        double v = acc[k];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane == 0) wsum[wid][k] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < 27) {
-        const int k = threadIdx.x;
-        pd.partial[(size_t(p) * ns + sl) * 27 + k] = ((wsum[0][k] + wsum[1][k]) + wsum[2][k]) + wsum[3][k];
-    }
-}
-
-// One block: per-fiber totals (slab order), rigid-body update, outputs,
+// One block: the momentum-exchange sums of every fiber (accumulated in fixed
+// point by the boundary sweep) back to FP64, the rigid-body update, outputs,
 // then the boxes and neighbour lists of the remap and the list reset.
 __global__ __launch_bounds__(256) void k_rigid(PartData pd, Geo g)
 {
-    extern __shared__ double tot[];   // [np][27]
-    const int np = pd.np, ns = pd.nslab;
-    for (int t = threadIdx.x; t < np * 27; t += blockDim.x) {
-        const int p = t / 27, k = t % 27;
-        const double *pp = pd.partial + size_t(p) * ns * 27 + k;
-        double v[32];
-#pragma unroll
-        for (int j = 0; j < 32; ++j) v[j] = j < ns ? pp[j * 27] : 0.0;   // all loads in flight
-        double acc = 0.0;
-#pragma unroll
-        for (int j = 0; j < 32; ++j) acc += v[j];                        // slab order
-        tot[t] = acc;
+    extern __shared__ double tot[];   // [np][NACC]
+    const int np = pd.np;
+    for (int t = threadIdx.x; t < np * NACC; t += blockDim.x) {
+        const int k = t % NACC;
+        tot[t] = ldexp(double(pd.mea[t]), -fx_shift(k));
+        pd.mea[t] = 0;   // cleared for the next step's boundary sweep
     }
     __syncthreads();
     const int64_t step = int64_t(pd.ctr->step);
     for (int p = threadIdx.x; p < np; p += blockDim.x) {
         double ac[NACC];
-        for (int k = 0; k < 27; ++k) ac[k] = tot[p * 27 + k];
-        for (int k = 27; k < NACC; ++k) ac[k] = 0.0;
+        for (int k = 0; k < NACC; ++k) ac[k] = tot[p * NACC + k];
         const PConst c = pd.pc[p];
         const PState s = pd.ps_cur[p];
         const double *row = nullptr;
@@ -771,17 +647,15 @@ __global__ __launch_bounds__(256) void k_remap(S *__restrict__ f, int32_t *__res
     }
 }
 
-// Flags of the cells in the remap boxes and the boundary-cell list.  The
+// Flags of the cells in the remap regions and the boundary-cell list.  The
 // list is cut into one segment per fiber; a block stages the boundary cells
 // it finds in LDS and reserves a range of its fiber's segment with a single
-// atomic.  The dense record nref[cell] = (list index << 32) | mask lets the
-// momentum exchange find a cell's links without searching the list.
+// atomic.
 constexpr int LSTAGE = 2048;
 
 __global__ __launch_bounds__(256) void k_near(uint8_t *__restrict__ flags, const int32_t *__restrict__ pid,
                                               uint32_t *__restrict__ list_cell,
-                                              uint32_t *__restrict__ list_mask,
-                                              uint64_t *__restrict__ nref, PartData pd, Geo g)
+                                              uint32_t *__restrict__ list_mask, PartData pd, Geo g)
 {
     const int ns = pd.nslab;
     const int p = blockIdx.x / ns, sl = blockIdx.x % ns;
@@ -809,7 +683,6 @@ __global__ __launch_bounds__(256) void k_near(uint8_t *__restrict__ flags, const
             const uint32_t cell = (uint32_t(z) * g.ny + uint32_t(y)) * g.nx + uint32_t(x);
             if (pid[cell] >= 0) {
                 flags[cell] = F_SOLID;
-                nref[cell] = 0ull;
                 continue;
             }
             uint32_t mask = 0;
@@ -823,7 +696,6 @@ __global__ __launch_bounds__(256) void k_near(uint8_t *__restrict__ flags, const
             }
             if (!mask) {
                 flags[cell] = 0;
-                nref[cell] = 0ull;
                 continue;
             }
             const uint32_t k = atomicAdd(&s_n, 1u);
@@ -837,12 +709,10 @@ __global__ __launch_bounds__(256) void k_near(uint8_t *__restrict__ flags, const
                     const uint32_t e = off + r;
                     list_cell[e] = cell;
                     list_mask[e] = mask;
-                    nref[cell] = (uint64_t(e) << 32) | mask;
                     flags[cell] = F_NEAR;
                 } else {
                     flags[cell] = 0;
-                    nref[cell] = 0ull;
-                    atomicOr(&pd.ctr->err_capacity, 2u);
+                        atomicOr(&pd.ctr->err_capacity, 2u);
                 }
             }
         }
@@ -856,11 +726,9 @@ __global__ __launch_bounds__(256) void k_near(uint8_t *__restrict__ flags, const
                 const uint32_t e = off + r;
                 list_cell[e] = cell;
                 list_mask[e] = s_mask[k];
-                nref[cell] = (uint64_t(e) << 32) | s_mask[k];
                 flags[cell] = F_NEAR;
             } else {
                 flags[cell] = 0;
-                nref[cell] = 0ull;
                 atomicOr(&pd.ctr->err_capacity, 2u);
             }
         }
@@ -871,16 +739,9 @@ __global__ __launch_bounds__(256) void k_near(uint8_t *__restrict__ flags, const
 }
 
 // ------------------------------------------------------------------ launchers
-hipError_t launch_particles(const PartData &pd, const Geo &g, const int32_t *pid, const uint64_t *nref,
-                            const void *linkval, int linkval_is_double, hipStream_t st)
+hipError_t launch_rigid(const PartData &pd, const Geo &g, hipStream_t st)
 {
-    const dim3 gr(pd.np * pd.nslab), bl(256);
-    if (linkval_is_double)
-        hipLaunchKernelGGL(k_particles<double>, gr, bl, 0, st, pd, g, pid, nref, (const double *)linkval);
-    else
-        hipLaunchKernelGGL(k_particles<float>, gr, bl, 0, st, pd, g, pid, nref, (const float *)linkval);
-    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
-    hipLaunchKernelGGL(k_rigid, dim3(1), dim3(256), size_t(pd.np) * 27 * sizeof(double), st, pd, g);
+    hipLaunchKernelGGL(k_rigid, dim3(1), dim3(256), size_t(pd.np) * NACC * sizeof(double), st, pd, g);
     return hipGetLastError();
 }
 
@@ -905,10 +766,10 @@ hipError_t launch_remap(int sk, bool next_odd, void *f, int32_t *pid, const Part
 }
 
 hipError_t launch_near(uint8_t *flags, const int32_t *pid, uint32_t *list_cell, uint32_t *list_mask,
-                       uint64_t *nref, const PartData &pd, const Geo &g, hipStream_t st)
+                       const PartData &pd, const Geo &g, hipStream_t st)
 {
     hipLaunchKernelGGL(k_near, dim3(pd.np * pd.nslab), dim3(256), 0, st, flags, pid, list_cell, list_mask,
-                       nref, pd, g);
+                       pd, g);
     return hipGetLastError();
 }
 

@@ -146,10 +146,52 @@ __device__ __forceinline__ void surf_vel(const PState &s, double cx, double cy, 
 }
 
 // ------------------------------------------------------------------ one cell
+// compile-time loop: f(std::integral_constant<int, I>) for I in [B, E)
+template <int I>
+struct IntC {
+    static constexpr int value = I;
+};
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&fn)
+{
+    if constexpr (B < E) {
+        fn(IntC<B>{});
+        static_for<B + 1, E>(fn);
+    }
+}
+
+// fixed-point term of the momentum-exchange sums (see fx_shift)
+__device__ __forceinline__ long long fx(double v, int k) { return __double2ll_rn(ldexp(v, fx_shift(k))); }
+
+// Momentum exchange of one link x -> y = x + c_q into fiber-local sums
+// (Eq. LBMhydrodynForce and the torque after it): with r = y - X,
+//   dF = 2 (f~_q + w_q rho0) c_q - 6 w_q rho0 (c_q.u_s) c_q,  dM = r x dF,
+// split into the velocity-free part F0, M0 and the matrices of the part
+// linear in u_s = V + W x r: A = k c c^T, B = k c (r x c)^T, C = k (r x c)(r x c)^T,
+// k = 6 w_q rho0, so that F = F0 - A V - B W and M = M0 - B^T V - C W.
+template <int q>
+__device__ __forceinline__ void link_terms(long long *acc, double ft, double rx, double ry, double rz,
+                                           double r0)
+{
+    const double m2 = 2.0 * (ft + wq(q) * r0);
+    const double c0 = CX[q], c1 = CY[q], c2 = CZ[q];
+    const double rc0 = ry * c2 - rz * c1, rc1 = rz * c0 - rx * c2, rc2 = rx * c1 - ry * c0;
+    const double k6 = 6.0 * wq(q) * r0;
+    const double t[NACC] = {m2 * c0, m2 * c1, m2 * c2, m2 * rc0, m2 * rc1, m2 * rc2,
+                            k6 * c0 * c0, k6 * c0 * c1, k6 * c0 * c2, k6 * c1 * c1, k6 * c1 * c2, k6 * c2 * c2,
+                            k6 * c0 * rc0, k6 * c0 * rc1, k6 * c0 * rc2,
+                            k6 * c1 * rc0, k6 * c1 * rc1, k6 * c1 * rc2,
+                            k6 * c2 * rc0, k6 * c2 * rc1, k6 * c2 * rc2,
+                            k6 * rc0 * rc0, k6 * rc0 * rc1, k6 * rc0 * rc2,
+                            k6 * rc1 * rc1, k6 * rc1 * rc2, k6 * rc2 * rc2};
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) acc[k] += fx(t[k], k);
+}
+
 template <typename S, bool ODD, bool BND>
 __device__ __forceinline__ void update_cell(S *__restrict__ f, const Geo &g,
                                             const Phys<typename St<S>::R> &ph, uint32_t cell,
-                                            uint32_t mask, uint32_t entry, const BndData &b)
+                                            uint32_t mask, int home, long long *acc, const BndData &b)
 {
     using R = typename St<S>::R;
     const uint32_t z = fdiv(cell, g.dnxy);
@@ -189,8 +231,8 @@ __device__ __forceinline__ void update_cell(S *__restrict__ f, const Geo &g,
     const R six_r0 = R(6) * ph.rho0;
     const PState *ps = nullptr;
     if (BND) ps = b.ps;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
+    static_for<0, Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
         const uint32_t nb = zo[1 + CZ[q]] + yo[1 + CY[q]] + xo[1 + CX[q]];
         const bool to_wall = (CZ[q] < 0 && wall_lo) || (CZ[q] > 0 && wall_hi);
         bool to_part = false;
@@ -201,17 +243,35 @@ __device__ __forceinline__ void update_cell(S *__restrict__ f, const Geo &g,
             out -= six_r0 * R(wq(q)) * R(CX[q]) * uw;
         }
         if (BND && to_part) {
-            // moving-obstacle bounce-back (Eq. LBMMovWall); keep the
-            // post-collision value for the momentum exchange
+            // moving-obstacle bounce-back (Eq. LBMMovWall) and the link's
+            // momentum exchange, from the post-collision value in registers
             const int32_t p = b.pid[nb - g.nxy];
             const uint32_t yx = xo[1 + CX[q]], yy = (y + g.ny + CY[q]) % g.ny;
             const int32_t yzi = int32_t(z) + CZ[q];
             const uint32_t yz = g.zper ? uint32_t((yzi + int32_t(g.nz)) % int32_t(g.nz)) : uint32_t(yzi);
-            double us[3];
-            surf_vel(ps[p], double(yx), double(yy), double(yz), g, us);
-            const double cu = double(CX[q]) * us[0] + double(CY[q]) * us[1] + double(CZ[q]) * us[2];
+            const PState &sp = ps[p];
+            const double rx = mi(double(yx) - sp.X[0], g.nx, true);
+            const double ry = mi(double(yy) - sp.X[1], g.ny, true);
+            const double rz = mi(double(yz) - sp.X[2], g.nz, g.zper != 0);
+            const double us0 = sp.V[0] + (sp.W[1] * rz - sp.W[2] * ry);
+            const double us1 = sp.V[1] + (sp.W[2] * rx - sp.W[0] * rz);
+            const double us2 = sp.V[2] + (sp.W[0] * ry - sp.W[1] * rx);
+            const double cu = double(CX[q]) * us0 + double(CY[q]) * us1 + double(CZ[q]) * us2;
             out -= R(6.0 * wq(q) * double(ph.rho0) * cu);
-            reinterpret_cast<R *>(b.linkval)[uint64_t(entry) * Q + q] = fv[q];
+            if (!isfinite(double(fv[q]))) atomicOr(&b.ctr->err_unstable, 1u);
+            if (p == home) {
+                link_terms<q>(acc, double(fv[q]), rx, ry, rz, double(ph.rho0));
+            } else {
+                // link to another fiber (fibers closer than the region margin)
+                long long tmp[NACC];
+#pragma unroll
+                for (int k = 0; k < NACC; ++k) tmp[k] = 0;
+                link_terms<q>(tmp, double(fv[q]), rx, ry, rz, double(ph.rho0));
+#pragma unroll
+                for (int k = 0; k < NACC; ++k)
+                    atomicAdd(reinterpret_cast<unsigned long long *>(b.mea + size_t(p) * NACC + k),
+                              (unsigned long long)tmp[k]);
+            }
         }
         const bool bounce = to_wall || to_part;
         if (!ODD) {
@@ -221,8 +281,10 @@ __device__ __forceinline__ void update_cell(S *__restrict__ f, const Geo &g,
             if (bounce) St<S>::st(f, uint64_t(opp(q)) * qs + own, out, sc);
             else St<S>::st(f, uint64_t(q) * qs + nb, out, sc);
         }
-    }
+    });
     (void)six_r0;
+    (void)home;
+    (void)acc;
 }
 
 // Grid-stride over 256-cell chunks: at any time the resident workgroups work
@@ -236,7 +298,7 @@ __global__ __launch_bounds__(256) void k_sweep_bulk(S *__restrict__ f, const uin
     for (uint32_t ch = xcd_block(blockIdx.x, gridDim.x); ch < nchunk; ch += gridDim.x) {
         const uint32_t cell = (ch << 8) + threadIdx.x;
         if (cell < g.ncell && !flags[cell])   // fiber cells idle; boundary cells: k_sweep_bnd
-            update_cell<S, ODD, false>(f, g, ph, cell, 0u, 0u, BndData{});
+            update_cell<S, ODD, false>(f, g, ph, cell, 0u, -1, nullptr, BndData{});
     }
 }
 
@@ -248,9 +310,28 @@ __global__ __launch_bounds__(256) void k_sweep_bnd(S *__restrict__ f, Geo g,
     const int p = blockIdx.x / b.bpf, j = blockIdx.x % b.bpf;
     const uint32_t cnt = b.seg_cnt[p], cap = b.seg_cap[p];
     const uint32_t n = cnt < cap ? cnt : cap, off = b.seg_off[p];
+    long long acc[NACC];
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) acc[k] = 0;
     for (uint32_t r = j * 256u + threadIdx.x; r < n; r += b.bpf * 256u) {
         const uint32_t e = off + r;
-        update_cell<S, ODD, true>(f, g, ph, b.cell[e], b.mask[e], e, b);
+        update_cell<S, ODD, true>(f, g, ph, b.cell[e], b.mask[e], p, acc, b);
+    }
+    // integer sums: exact, so the reduction order does not matter
+    __shared__ long long red[4][NACC];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) {
+        long long v = acc[k];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) red[wid][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NACC) {
+        const int k = threadIdx.x;
+        const long long v = red[0][k] + red[1][k] + red[2][k] + red[3][k];
+        if (v) atomicAdd(reinterpret_cast<unsigned long long *>(b.mea + size_t(p) * NACC + k),
+                         (unsigned long long)v);
     }
 }
 
