@@ -29,6 +29,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "D3Q19 MLUPS & %HBM peak; FP32 vs FP16-storage vs learned-coarse at fixed error"
 HBM_PEAK_GBS = 8000.0
+# HBM traffic of the FP32 bulk sweep on this workload, from rocprofv3
+# FETCH_SIZE / WRITE_SIZE passes (profiles/sweep_bulk_256cube_64fibers_traffic.md),
+# scaled by the counters' readings for a plain copy of known size.  Valid only
+# for the sweep source it was measured on (SHA-1 below); otherwise reported null.
+SWEEP_TRAFFIC = {"sweep_sha1": "50ca00fc2c72ce3d4061bed684ad46c9a8f7b3a1",
+                 "bytes_per_launch": 2.5725e9}
 # algorithmic bytes per lattice update of the bulk sweep: 19 loads + 19
 # stores of the population type + the 1-byte cell flag
 BYTES_PER_LUP = {"f32": 19 * 4 * 2 + 1, "f16": 19 * 2 * 2 + 1, "bf16": 19 * 2 * 2 + 1,
@@ -83,6 +89,13 @@ def time_form(sc, storage, steps, warmup, torch):
         "boundary_cells": int(info["boundary_cells"]),
         "solid_cells": n_solid,
     }
+
+
+def sweep_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1503_06869_amd", "csrc", "sweep.hip")
+    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    return SWEEP_TRAFFIC["bytes_per_launch"] if sha == SWEEP_TRAFFIC["sweep_sha1"] else None
 
 
 def cpu_baseline(sc, nsteps=2):
@@ -174,7 +187,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(main_form["sweep_gbs"], 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(main_form["sweep_gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": None,
+                     "traffic": sweep_traffic(),
                      "kernel": "k_sweep_bulk (even/odd AA)",
                      "kernel_ms": round(main_form["sweep_ms"], 5),
                      "algorithmic_bytes_per_launch": main_form["sweep_bytes"]},
