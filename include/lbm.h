@@ -59,13 +59,23 @@ typedef enum { LBM_F32 = 0, LBM_F16DEV = 1, LBM_BF16DEV = 2, LBM_F64 = 3 } lbm_s
 
 typedef enum { LBM_INIT_REST = 0, LBM_INIT_COUETTE = 1 } lbm_init;
 
-/* How the part of the momentum-exchange force that is linear in the
- * particle surface velocity enters the rigid-body update:
- *   LBM_COUPLING_IMPLICIT  at the new velocities (solid-particle scheme of
- *                          Nguyen and Ladd, cited in Sec. 4.2); stable at
- *                          density ratio 1
- *   LBM_COUPLING_EXPLICIT  every term at the old velocities */
-typedef enum { LBM_COUPLING_IMPLICIT = 0, LBM_COUPLING_EXPLICIT = 1 } lbm_coupling;
+/* How the momentum-exchange force enters the rigid-body update (Sec. 4.3
+ * leaves the time integration open):
+ *   LBM_COUPLING_IMPLICIT        the part linear in the particle surface
+ *                                velocity taken at the new velocities
+ *                                (solid-particle scheme of Nguyen and Ladd,
+ *                                cited in Sec. 4.2), the velocity-free part
+ *                                averaged over this and the previous step;
+ *                                stable at density ratio 1 down to tau 0.55
+ *   LBM_COUPLING_EXPLICIT        every term at the old velocities
+ *   LBM_COUPLING_IMPLICIT_PLAIN  as IMPLICIT without the two-step average
+ *                                (grows a period-two torque oscillation at
+ *                                density ratio 1 for tau below about 0.7) */
+typedef enum {
+    LBM_COUPLING_IMPLICIT = 0,
+    LBM_COUPLING_EXPLICIT = 1,
+    LBM_COUPLING_IMPLICIT_PLAIN = 2
+} lbm_coupling;
 
 typedef struct lbm_ctx lbm_ctx;
 

@@ -334,6 +334,8 @@ typedef struct {
     double st[16];          /* X3 q4 V3 W3 Lang3 */
     double length, radius, mass, i_par, i_perp;
     double F[3], M[3];
+    double F0p[3], M0p[3];  /* velocity-free sums of the previous step */
+    int have_prev;
     double *traj;           /* prescribed kinematics, 13 per step, or NULL */
     int64_t traj_n, traj_pos;
 } fiber;
@@ -618,7 +620,11 @@ static void one_step(or_sim *s)
         }
     free(part);
 
-    /* 3. rigid-body update; keep the old states for the refill             */
+    /* 3. rigid-body update; keep the old states for the refill.  With      */
+    /*    coupling 0 the velocity-free sums F0, M0 enter as the mean of this   */
+    /*    step's and the previous step's values: the plain sums let the        */
+    /*    torque build a growing oscillation of period two steps at density    */
+    /*    ratio 1 and small tau, which the mean removes.                       */
     double *old = (double *)malloc((size_t)(s->nf ? s->nf : 1) * 16 * sizeof(double));
     for (int i = 0; i < s->nf; ++i) {
         fiber *f = &s->fib[i];
@@ -636,9 +642,15 @@ static void one_step(or_sim *s)
             double tw = t[0] * Wp[0] + t[1] * Wp[1] + t[2] * Wp[2];
             for (int k = 0; k < 3; ++k)
                 f->st[13 + k] = f->i_perp * Wp[k] + (f->i_par - f->i_perp) * tw * t[k];
-        } else if (p->implicit) {
+        } else if (p->coupling != 1) {
+            double F0u[3], M0u[3];
+            for (int k = 0; k < 3; ++k) {
+                const int avg = p->coupling == 0 && f->have_prev;
+                F0u[k] = avg ? 0.5 * (rd[6 + k] + f->F0p[k]) : rd[6 + k];
+                M0u[k] = avg ? 0.5 * (rd[9 + k] + f->M0p[k]) : rd[9 + k];
+            }
             double out[16];
-            or_rigid_step_implicit(f->st, f->mass, f->i_par, f->i_perp, rd + 6, rd + 9, rd + 12,
+            or_rigid_step_implicit(f->st, f->mass, f->i_par, f->i_perp, F0u, M0u, rd + 12,
                                    rd + 21, rd + 30, nx, ny, nz, p->z_periodic, out, f->F, f->M);
             memcpy(f->st, out, 16 * sizeof(double));
         } else {
@@ -649,6 +661,11 @@ static void one_step(or_sim *s)
                           p->z_periodic, out);
             memcpy(f->st, out, 16 * sizeof(double));
         }
+        for (int k = 0; k < 3; ++k) {
+            f->F0p[k] = rd[6 + k];
+            f->M0p[k] = rd[9 + k];
+        }
+        f->have_prev = 1;
     }
     free(red);
 

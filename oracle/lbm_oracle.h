@@ -45,9 +45,12 @@ typedef struct {
     double wall_u;     /* wall velocity along x: top wall +U, bottom wall -U */
     double g[3];       /* body-force acceleration (Poiseuille / drag tests only) */
     int init_couette;  /* 1: start from the linear Couette profile; 0: fluid at rest */
-    int implicit;      /* 1: velocity-dependent part of the bounce-back force taken at the
-                          new particle velocity (solid-particle scheme of Nguyen and Ladd);
-                          0: fully explicit, every term at the old velocity */
+    int coupling;      /* how the momentum-exchange force enters the rigid-body update:
+                          0: the part linear in the surface velocity at the new particle
+                             velocity (solid-particle scheme of Nguyen and Ladd), the
+                             velocity-free part averaged over this and the previous step;
+                          1: fully explicit, every term at the old velocity;
+                          2: as 0 without the two-step average */
 } or_params;
 
 /* ---- building blocks (exposed so the tests can pin them one by one) ---- */

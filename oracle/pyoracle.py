@@ -24,7 +24,7 @@ class Params(C.Structure):
                 ("z_periodic", C.c_int), ("srt", C.c_int),
                 ("tau", C.c_double), ("magic", C.c_double), ("rho0", C.c_double),
                 ("wall_u", C.c_double), ("g", C.c_double * 3), ("init_couette", C.c_int),
-                ("implicit", C.c_int)]
+                ("coupling", C.c_int)]
 
 
 def lib():
@@ -139,14 +139,18 @@ def rigid_step(state, mass, i_par, i_perp, F, M, shape=(1 << 20, 1 << 20, 1 << 2
 
 
 # ---------------------------------------------------------------- coupled simulation
+# coupling of the momentum-exchange force to the rigid-body update (or_params.coupling)
+COUPLING = {"implicit": 0, "explicit": 1, "implicit_plain": 2}
+
+
 class Sim:
     """One coupled simulation held by the oracle."""
 
     def __init__(self, nx, ny, nz, tau=0.8, magic=3.0 / 16.0, wall_u=0.0, rho0=1.0,
                  z_periodic=False, srt=False, g=(0.0, 0.0, 0.0), init_couette=False,
-                 implicit=True):
+                 coupling="implicit"):
         p = Params(nx, ny, nz, int(z_periodic), int(srt), tau, magic, rho0, wall_u,
-                   (C.c_double * 3)(*g), int(init_couette), int(implicit))
+                   (C.c_double * 3)(*g), int(init_couette), COUPLING[coupling])
         self.shape = (nx, ny, nz)
         self.ncell = nx * ny * nz
         self._h = lib().or_create(C.byref(p))

@@ -4,7 +4,8 @@
 
 Every HIP translation unit is compiled with packed-FP32 instructions
 disabled; the particle and host units also with contraction off, so that
-the FP64 cell predicate and quaternion arithmetic round exactly as written.
+the FP64 cell predicate and quaternion arithmetic round exactly as written
+(the batched unit gets the same through a pragma after its sweep code).
 """
 import concurrent.futures as cf
 import os
@@ -22,6 +23,9 @@ SOURCES = {
     "sweep.hip": [],
     "particles.hip": ["-ffp-contract=off"],
     "api.hip": ["-ffp-contract=off"],
+    # the sweep part keeps the default contraction of sweep.hip; the particle
+    # part and the host code follow a contraction-off pragma in the header
+    "batched.hip": [],
 }
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

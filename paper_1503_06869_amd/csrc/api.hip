@@ -166,7 +166,7 @@ static PartData part_data(lbm_ctx *c, PState *cur, PState *next)
     pd.ft_out = c->ft;
     pd.hist = c->hist;
     pd.hist_cap = c->p.history_capacity;
-    pd.implicit = c->p.coupling == LBM_COUPLING_IMPLICIT;
+    pd.coupling = c->p.coupling;
     pd.rho0 = c->p.rho0;
     pd.ctr = c->ctr;
     pd.list_cap = c->list_cap;
@@ -399,7 +399,7 @@ lbm_status lbm_create(const lbm_params *p, lbm_ctx **out)
     if (p->collision == LBM_TRT && !(p->magic > 0.0)) return LBM_E_ARG;
     if (p->storage < 0 || p->storage > 3 || p->history_capacity < 1) return LBM_E_ARG;
     if (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 20) return LBM_E_ARG;
-    if (p->coupling != LBM_COUPLING_IMPLICIT && p->coupling != LBM_COUPLING_EXPLICIT) return LBM_E_ARG;
+    if (p->coupling < LBM_COUPLING_IMPLICIT || p->coupling > LBM_COUPLING_IMPLICIT_PLAIN) return LBM_E_ARG;
     lbm_ctx *c = new (std::nothrow) lbm_ctx;
     if (!c) return LBM_E_NOMEM;
     c->p = *p;

@@ -59,7 +59,8 @@ struct PState {            // one fiber, state at a time level
     double W[3];           // angular velocity (world frame)
     double L[3];           // angular momentum (world frame)
     double t[3];           // axis R(q) e_x
-    double pad;
+    double have_prev;      // 1: F0p, M0p hold the previous step's sums
+    double F0p[3], M0p[3]; // velocity-free momentum-exchange sums of the step that led here
 };
 struct PConst {
     double length, radius, mass, i_par, i_perp;
@@ -142,7 +143,7 @@ struct PartData {
     double *ft_out;            // [np][6] F, M of the step
     double *hist;              // ring [cap][np][19]
     int64_t hist_cap;
-    int32_t implicit;
+    int32_t coupling;          // lbm_coupling
     double rho0;
     DevCounters *ctr;
     uint32_t list_cap;

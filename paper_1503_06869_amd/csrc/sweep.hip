@@ -18,274 +18,9 @@
 //               what the next even sweep of x reads.
 // With this, the odd gather is uniform (no flags needed) and every slot is
 // read and written by exactly one thread of a sweep.
-#include "lbm_dev.h"
+#include "lbm_sweep_dev.h"
 
 namespace lbm {
-
-// ------------------------------------------------------------------ storage
-template <typename S>
-struct St;
-template <>
-struct St<float> {
-    using R = float;
-    static __device__ __forceinline__ float ld(const float *p, uint64_t i, float) { return p[i]; }
-    static __device__ __forceinline__ void st(float *p, uint64_t i, float v, float)
-    {
-        __builtin_nontemporal_store(v, p + i);
-    }
-};
-template <>
-struct St<double> {
-    using R = double;
-    static __device__ __forceinline__ double ld(const double *p, uint64_t i, double) { return p[i]; }
-    static __device__ __forceinline__ void st(double *p, uint64_t i, double v, double)
-    {
-        __builtin_nontemporal_store(v, p + i);
-    }
-};
-template <>
-struct St<_Float16> {
-    using R = float;
-    static __device__ __forceinline__ float ld(const _Float16 *p, uint64_t i, float inv)
-    {
-        return float(p[i]) * inv;
-    }
-    static __device__ __forceinline__ void st(_Float16 *p, uint64_t i, float v, float scale)
-    {
-        __builtin_nontemporal_store(_Float16(v * scale), p + i);   // v_cvt_f16_f32: RNE
-    }
-};
-struct bf16s {
-    uint16_t b;
-};
-template <>
-struct St<bf16s> {
-    using R = float;
-    static __device__ __forceinline__ float ld(const bf16s *p, uint64_t i, float)
-    {
-        const uint16_t *u = reinterpret_cast<const uint16_t *>(p);
-        return __uint_as_float(uint32_t(u[i]) << 16);
-    }
-    static __device__ __forceinline__ void st(bf16s *p, uint64_t i, float v, float)
-    {
-        uint32_t u = __float_as_uint(v);
-        u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even
-        __builtin_nontemporal_store(uint16_t(u >> 16), reinterpret_cast<uint16_t *>(p) + i);
-    }
-};
-
-// Each XCD receives every 8th block; renumber so that each XCD works on a
-// contiguous range of cells (neighbouring blocks share partial cache lines).
-__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb)
-{
-    const uint32_t per = nb >> 3, rem = nb & 7u;
-    const uint32_t xcd = b & 7u, k = b >> 3;
-    return xcd * per + (xcd < rem ? xcd : rem) + k;
-}
-
-// ------------------------------------------------------------------ collision
-// TRT in deviation form: f' = f - w rho0, drho = sum f', j = sum c f'.
-// Even/odd equilibrium parts of Eq. EqPDF_TRT minus w rho0:
-//   feq_e' = w (drho - 3/2 rho0 u.u + 9/2 rho0 (c.u)^2),  feq_o = 3 w rho0 c.u
-// lambda_e = -omega_e, lambda_o = -omega_o (Eq. LBMCollide).  With a body
-// force the velocity carries +g/2 and the odd part gains (1 - omega_o/2) 3 w rho0 c.g.
-template <typename R>
-__device__ __forceinline__ void collide(R (&f)[Q], const Phys<R> &ph, R inv_rho0)
-{
-    R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        drho += f[q];
-        if (CX[q]) jx += CX[q] > 0 ? f[q] : -f[q];
-        if (CY[q]) jy += CY[q] > 0 ? f[q] : -f[q];
-        if (CZ[q]) jz += CZ[q] > 0 ? f[q] : -f[q];
-    }
-    R ux = jx * inv_rho0, uy = jy * inv_rho0, uz = jz * inv_rho0;
-    if (ph.has_g) {
-        ux += R(0.5) * ph.g[0];
-        uy += R(0.5) * ph.g[1];
-        uz += R(0.5) * ph.g[2];
-    }
-    const R r0 = ph.rho0, we = ph.omega_e, wo = ph.omega_o;
-    const R base = drho - R(1.5) * r0 * (ux * ux + uy * uy + uz * uz);
-    f[0] = f[0] - we * (f[0] - R(wq(0)) * base);
-#pragma unroll
-    for (int q = 1; q <= 9; ++q) {
-        const R w = R(wq(q));
-        const R cu = R(CX[q]) * ux + R(CY[q]) * uy + R(CZ[q]) * uz;
-        const R eeq = w * (base + R(4.5) * r0 * cu * cu);
-        const R oeq = R(3) * w * r0 * cu;
-        const R e = R(0.5) * (f[q] + f[q + 9]);
-        const R o = R(0.5) * (f[q] - f[q + 9]);
-        const R de = we * (e - eeq);
-        R dd = wo * (o - oeq);
-        if (ph.has_g)
-            dd -= (R(1) - R(0.5) * wo) * R(3) * w * r0 *
-                  (R(CX[q]) * ph.g[0] + R(CY[q]) * ph.g[1] + R(CZ[q]) * ph.g[2]);
-        f[q] = f[q] - de - dd;
-        f[q + 9] = f[q + 9] - de + dd;
-    }
-}
-
-// rigid-body velocity of fiber p at the centre of cell (cx, cy, cz):
-// u_s = V + W x d with d the minimum-image vector from the centre of mass.
-__device__ __forceinline__ double mi(double d, uint32_t n, bool per)
-{
-    if (!per) return d;
-    const double h = 0.5 * double(n);
-    return d > h ? d - double(n) : (d < -h ? d + double(n) : d);
-}
-__device__ __forceinline__ void surf_vel(const PState &s, double cx, double cy, double cz,
-                                         const Geo &g, double us[3])
-{
-    const double dx = mi(cx - s.X[0], g.nx, true), dy = mi(cy - s.X[1], g.ny, true),
-                 dz = mi(cz - s.X[2], g.nz, g.zper != 0);
-    us[0] = s.V[0] + (s.W[1] * dz - s.W[2] * dy);
-    us[1] = s.V[1] + (s.W[2] * dx - s.W[0] * dz);
-    us[2] = s.V[2] + (s.W[0] * dy - s.W[1] * dx);
-}
-
-// ------------------------------------------------------------------ one cell
-// compile-time loop: f(std::integral_constant<int, I>) for I in [B, E)
-template <int I>
-struct IntC {
-    static constexpr int value = I;
-};
-template <int B, int E, typename F>
-__device__ __forceinline__ void static_for(F &&fn)
-{
-    if constexpr (B < E) {
-        fn(IntC<B>{});
-        static_for<B + 1, E>(fn);
-    }
-}
-
-// fixed-point term of the momentum-exchange sums (see fx_shift)
-__device__ __forceinline__ long long fx(double v, int k) { return __double2ll_rn(ldexp(v, fx_shift(k))); }
-
-// Momentum exchange of one link x -> y = x + c_q into fiber-local sums
-// (Eq. LBMhydrodynForce and the torque after it): with r = y - X,
-//   dF = 2 (f~_q + w_q rho0) c_q - 6 w_q rho0 (c_q.u_s) c_q,  dM = r x dF,
-// split into the velocity-free part F0, M0 and the matrices of the part
-// linear in u_s = V + W x r: A = k c c^T, B = k c (r x c)^T, C = k (r x c)(r x c)^T,
-// k = 6 w_q rho0, so that F = F0 - A V - B W and M = M0 - B^T V - C W.
-template <int q>
-__device__ __forceinline__ void link_terms(long long *acc, double ft, double rx, double ry, double rz,
-                                           double r0)
-{
-    const double m2 = 2.0 * (ft + wq(q) * r0);
-    const double c0 = CX[q], c1 = CY[q], c2 = CZ[q];
-    const double rc0 = ry * c2 - rz * c1, rc1 = rz * c0 - rx * c2, rc2 = rx * c1 - ry * c0;
-    const double k6 = 6.0 * wq(q) * r0;
-    const double t[NACC] = {m2 * c0, m2 * c1, m2 * c2, m2 * rc0, m2 * rc1, m2 * rc2,
-                            k6 * c0 * c0, k6 * c0 * c1, k6 * c0 * c2, k6 * c1 * c1, k6 * c1 * c2, k6 * c2 * c2,
-                            k6 * c0 * rc0, k6 * c0 * rc1, k6 * c0 * rc2,
-                            k6 * c1 * rc0, k6 * c1 * rc1, k6 * c1 * rc2,
-                            k6 * c2 * rc0, k6 * c2 * rc1, k6 * c2 * rc2,
-                            k6 * rc0 * rc0, k6 * rc0 * rc1, k6 * rc0 * rc2,
-                            k6 * rc1 * rc1, k6 * rc1 * rc2, k6 * rc2 * rc2};
-#pragma unroll
-    for (int k = 0; k < NACC; ++k) acc[k] += fx(t[k], k);
-}
-
-template <typename S, bool ODD, bool BND>
-__device__ __forceinline__ void update_cell(S *__restrict__ f, const Geo &g,
-                                            const Phys<typename St<S>::R> &ph, uint32_t cell,
-                                            uint32_t mask, int home, long long *acc, const BndData &b)
-{
-    using R = typename St<S>::R;
-    const uint32_t z = fdiv(cell, g.dnxy);
-    const uint32_t rr = cell - z * g.nxy;
-    const uint32_t y = fdiv(rr, g.dnx);
-    const uint32_t x = rr - y * g.nx;
-    const uint32_t xo[3] = {x == 0 ? g.nx - 1 : x - 1, x, x + 1 == g.nx ? 0 : x + 1};
-    const uint32_t yo[3] = {(y == 0 ? g.ny - 1 : y - 1) * g.nx, y * g.nx,
-                            (y + 1 == g.ny ? 0 : y + 1) * g.nx};
-    uint32_t zo[3];
-    if (g.zper) {
-        zo[0] = ((z == 0 ? g.nz - 1 : z - 1) + 1) * g.nxy;
-        zo[1] = (z + 1) * g.nxy;
-        zo[2] = ((z + 1 == g.nz ? 0 : z + 1) + 1) * g.nxy;
-    } else {
-        zo[0] = z * g.nxy;
-        zo[1] = (z + 1) * g.nxy;
-        zo[2] = (z + 2) * g.nxy;
-    }
-    const uint64_t qs = g.qstride;
-    const R inv = ph.inv_scale, sc = ph.scale;
-    R fv[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        if (!ODD) {
-            fv[q] = St<S>::ld(f, uint64_t(q) * qs + zo[1] + yo[1] + xo[1], inv);
-        } else {
-            const uint32_t src = zo[1 - CZ[q]] + yo[1 - CY[q]] + xo[1 - CX[q]];
-            fv[q] = St<S>::ld(f, uint64_t(opp(q)) * qs + src, inv);
-        }
-    }
-    collide<R>(fv, ph, R(1) / ph.rho0);
-
-    const bool wall_lo = !g.zper && z == 0;
-    const bool wall_hi = !g.zper && z + 1 == g.nz;
-    const uint32_t own = zo[1] + yo[1] + xo[1];
-    const R six_r0 = R(6) * ph.rho0;
-    const PState *ps = nullptr;
-    if (BND) ps = b.ps;
-    static_for<0, Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        const uint32_t nb = zo[1 + CZ[q]] + yo[1 + CY[q]] + xo[1 + CX[q]];
-        const bool to_wall = (CZ[q] < 0 && wall_lo) || (CZ[q] > 0 && wall_hi);
-        bool to_part = false;
-        if (BND) to_part = (mask >> q) & 1u;
-        R out = fv[q];
-        if (CX[q] != 0 && to_wall) {
-            const R uw = CZ[q] < 0 ? -ph.wall_u : ph.wall_u;
-            out -= six_r0 * R(wq(q)) * R(CX[q]) * uw;
-        }
-        if (BND && to_part) {
-            // moving-obstacle bounce-back (Eq. LBMMovWall) and the link's
-            // momentum exchange, from the post-collision value in registers
-            const int32_t p = b.pid[nb - g.nxy];
-            const uint32_t yx = xo[1 + CX[q]], yy = (y + g.ny + CY[q]) % g.ny;
-            const int32_t yzi = int32_t(z) + CZ[q];
-            const uint32_t yz = g.zper ? uint32_t((yzi + int32_t(g.nz)) % int32_t(g.nz)) : uint32_t(yzi);
-            const PState &sp = ps[p];
-            const double rx = mi(double(yx) - sp.X[0], g.nx, true);
-            const double ry = mi(double(yy) - sp.X[1], g.ny, true);
-            const double rz = mi(double(yz) - sp.X[2], g.nz, g.zper != 0);
-            const double us0 = sp.V[0] + (sp.W[1] * rz - sp.W[2] * ry);
-            const double us1 = sp.V[1] + (sp.W[2] * rx - sp.W[0] * rz);
-            const double us2 = sp.V[2] + (sp.W[0] * ry - sp.W[1] * rx);
-            const double cu = double(CX[q]) * us0 + double(CY[q]) * us1 + double(CZ[q]) * us2;
-            out -= R(6.0 * wq(q) * double(ph.rho0) * cu);
-            if (!isfinite(double(fv[q]))) atomicOr(&b.ctr->err_unstable, 1u);
-            if (p == home) {
-                link_terms<q>(acc, double(fv[q]), rx, ry, rz, double(ph.rho0));
-            } else {
-                // link to another fiber (fibers closer than the region margin)
-                long long tmp[NACC];
-#pragma unroll
-                for (int k = 0; k < NACC; ++k) tmp[k] = 0;
-                link_terms<q>(tmp, double(fv[q]), rx, ry, rz, double(ph.rho0));
-#pragma unroll
-                for (int k = 0; k < NACC; ++k)
-                    atomicAdd(reinterpret_cast<unsigned long long *>(b.mea + size_t(p) * NACC + k),
-                              (unsigned long long)tmp[k]);
-            }
-        }
-        const bool bounce = to_wall || to_part;
-        if (!ODD) {
-            if (bounce) St<S>::st(f, uint64_t(q) * qs + nb, out, sc);
-            else St<S>::st(f, uint64_t(opp(q)) * qs + own, out, sc);
-        } else {
-            if (bounce) St<S>::st(f, uint64_t(opp(q)) * qs + own, out, sc);
-            else St<S>::st(f, uint64_t(q) * qs + nb, out, sc);
-        }
-    });
-    (void)six_r0;
-    (void)home;
-    (void)acc;
-}
 
 // Grid-stride over 256-cell chunks: at any time the resident workgroups work
 // on one compact band of the lattice, which keeps each of the 38 access

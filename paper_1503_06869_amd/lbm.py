@@ -1,9 +1,11 @@
-"""Thin ctypes binding of the C ABI in include/lbm.h (argument marshalling only).
+"""Thin ctypes binding of the C ABI in include/lbm.h and include/lbm_batch.h
+(argument marshalling only).
 
-The functions keep the C names (``lbm_create``, ``lbm_step``, ...).  The
-``Context`` class wraps one context with numpy in/out arrays.  Every step of
-the method runs in the HIP kernels of ``liblbmfib.so``; if that library is
-missing this module raises on import of the library (there is no fallback).
+The functions keep the C names (``lbm_create``, ``lbm_step``,
+``lbm_batch_step``, ...).  The ``Context`` class wraps one lattice, the
+``Batch`` class many independent one-fiber cases, with numpy in/out arrays.
+Every step of the method runs in the HIP kernels of ``liblbmfib.so``; if
+that library is missing, ``load()`` raises (there is no fallback).
 """
 import ctypes as C
 import os
@@ -17,7 +19,9 @@ LBM_OK, LBM_E_ARG, LBM_E_NOMEM, LBM_E_HIP, LBM_E_GEOM, LBM_E_UNSTABLE, LBM_E_STA
 LBM_TRT, LBM_SRT = 0, 1
 LBM_F32, LBM_F16DEV, LBM_BF16DEV, LBM_F64 = 0, 1, 2, 3
 LBM_INIT_REST, LBM_INIT_COUETTE = 0, 1
-LBM_COUPLING_IMPLICIT, LBM_COUPLING_EXPLICIT = 0, 1
+LBM_COUPLING_IMPLICIT, LBM_COUPLING_EXPLICIT, LBM_COUPLING_IMPLICIT_PLAIN = 0, 1, 2
+COUPLING = {"implicit": LBM_COUPLING_IMPLICIT, "explicit": LBM_COUPLING_EXPLICIT,
+            "implicit_plain": LBM_COUPLING_IMPLICIT_PLAIN}
 
 STORAGE = {"f32": LBM_F32, "f16": LBM_F16DEV, "bf16": LBM_BF16DEV, "f64": LBM_F64}
 
@@ -27,6 +31,13 @@ EXPORTED = [
     "lbm_get_force_torque", "lbm_get_fields", "lbm_get_fiber_state", "lbm_set_fiber_state",
     "lbm_get_history", "lbm_get_populations", "lbm_set_populations", "lbm_get_info",
     "lbm_enable_sweep_timing", "lbm_get_sweep_time", "lbm_copy_bytes",
+]
+EXPORTED_BATCH = [
+    "lbm_batch_params_default", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_last_error",
+    "lbm_batch_set_kinematics", "lbm_batch_autotune", "lbm_batch_set_config", "lbm_batch_step",
+    "lbm_batch_sync", "lbm_batch_get_force_torque", "lbm_batch_get_fiber_state",
+    "lbm_batch_get_history", "lbm_batch_get_fields", "lbm_batch_get_populations",
+    "lbm_batch_get_info",
 ]
 
 
@@ -49,6 +60,29 @@ class lbm_fiber(C.Structure):
 class lbm_info(C.Structure):
     _fields_ = [("steps_done", C.c_int64), ("nfibers", C.c_int32), ("parity", C.c_int32),
                 ("boundary_cells", C.c_int64), ("overlap_events", C.c_int64),
+                ("device_bytes", C.c_int64), ("population_bytes", C.c_int64)]
+
+
+class lbm_batch_case(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("tau", C.c_double),
+                ("wall_u", C.c_double), ("fiber", lbm_fiber)]
+
+
+class lbm_batch_params(C.Structure):
+    _fields_ = [("collision", C.c_int32), ("magic", C.c_double), ("rho0", C.c_double),
+                ("storage", C.c_int32), ("init_profile", C.c_int32), ("coupling", C.c_int32),
+                ("fp16_scale_log2", C.c_int32), ("history_capacity", C.c_int64),
+                ("stream", C.c_void_p), ("threads", C.c_int32), ("bins", C.c_int32)]
+
+
+class lbm_batch_tuning(C.Structure):
+    _fields_ = [("threads", C.c_int32), ("bins", C.c_int32), ("ms_per_step", C.c_double),
+                ("from_cache", C.c_int32), ("trials", C.c_int32)]
+
+
+class lbm_batch_info(C.Structure):
+    _fields_ = [("steps_done", C.c_int64), ("ncases", C.c_int32), ("bins", C.c_int32),
+                ("threads", C.c_int32), ("cells", C.c_int64), ("boundary_cells", C.c_int64),
                 ("device_bytes", C.c_int64), ("population_bytes", C.c_int64)]
 
 
@@ -86,6 +120,22 @@ def load():
         "lbm_enable_sweep_timing": ([vp, C.c_int32], C.c_int),
         "lbm_get_sweep_time": ([vp, _dp, C.POINTER(C.c_int64)], C.c_int),
         "lbm_copy_bytes": ([vp, vp, C.c_size_t, vp], C.c_int),
+        "lbm_batch_params_default": ([C.POINTER(lbm_batch_params)], C.c_int),
+        "lbm_batch_create": ([C.POINTER(lbm_batch_params), C.POINTER(lbm_batch_case), C.c_int32,
+                              C.POINTER(vp)], C.c_int),
+        "lbm_batch_destroy": ([vp], C.c_int),
+        "lbm_batch_last_error": ([vp], C.c_char_p),
+        "lbm_batch_set_kinematics": ([vp, C.c_int32, _dp, C.c_int64], C.c_int),
+        "lbm_batch_autotune": ([vp, C.c_int32, C.c_char_p, C.POINTER(lbm_batch_tuning)], C.c_int),
+        "lbm_batch_set_config": ([vp, C.c_int32, C.c_int32], C.c_int),
+        "lbm_batch_step": ([vp, C.c_int64], C.c_int),
+        "lbm_batch_sync": ([vp], C.c_int),
+        "lbm_batch_get_force_torque": ([vp, _dp, _dp], C.c_int),
+        "lbm_batch_get_fiber_state": ([vp, _dp, _dp, _dp, _dp], C.c_int),
+        "lbm_batch_get_history": ([vp, C.c_int32, C.c_int64, C.c_int64, _dp], C.c_int),
+        "lbm_batch_get_fields": ([vp, C.c_int32, vp, vp, vp, vp, C.c_int32], C.c_int),
+        "lbm_batch_get_populations": ([vp, C.c_int32, _dp], C.c_int),
+        "lbm_batch_get_info": ([vp, C.POINTER(lbm_batch_info)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -143,7 +193,7 @@ class Context:
         p.body_force = (C.c_double * 3)(*body_force)
         p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
         p.init_profile = LBM_INIT_COUETTE if init_couette else LBM_INIT_REST
-        p.coupling = LBM_COUPLING_EXPLICIT if coupling == "explicit" else LBM_COUPLING_IMPLICIT
+        p.coupling = COUPLING[coupling]
         p.fp16_scale_log2 = fp16_scale_log2
         p.history_capacity = history_capacity
         p.stream = stream
@@ -250,3 +300,117 @@ class Context:
         n = C.c_int64()
         self._chk(load().lbm_get_sweep_time(self._h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+
+def _fiber_struct(X, q, length, radius, density_ratio=1.0, V=(0, 0, 0), W=(0, 0, 0)):
+    f = lbm_fiber()
+    f.center = (C.c_double * 3)(*_f64(X, 3))
+    f.quat = (C.c_double * 4)(*_f64(q, 4))
+    f.length, f.radius, f.density_ratio = float(length), float(radius), float(density_ratio)
+    f.vel = (C.c_double * 3)(*_f64(V, 3))
+    f.omega = (C.c_double * 3)(*_f64(W, 3))
+    return f
+
+
+class Batch:
+    """Many independent one-fiber shear cells advanced by one persistent
+    launch (owns an lbm_batch).  ``cases``: objects with nx, ny, nz, tau,
+    wall_u and fibers[0] (X, q, length, radius, density_ratio, V, W)."""
+
+    def __init__(self, cases, storage="f32", collision="trt", magic=3.0 / 16.0, rho0=1.0,
+                 init_couette=True, coupling="implicit", fp16_scale_log2=14,
+                 history_capacity=4096, stream=None, threads=0, bins=0):
+        L = load()
+        p = lbm_batch_params()
+        L.lbm_batch_params_default(C.byref(p))
+        p.collision = LBM_SRT if collision == "srt" else LBM_TRT
+        p.magic, p.rho0 = magic, rho0
+        p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        p.init_profile = LBM_INIT_COUETTE if init_couette else LBM_INIT_REST
+        p.coupling = COUPLING[coupling]
+        p.fp16_scale_log2 = fp16_scale_log2
+        p.history_capacity = history_capacity
+        p.stream = stream
+        p.threads, p.bins = threads, bins
+        arr = (lbm_batch_case * len(cases))()
+        for i, sc in enumerate(cases):
+            fb = sc.fibers[0]
+            arr[i].nx, arr[i].ny, arr[i].nz = sc.nx, sc.ny, sc.nz
+            arr[i].tau, arr[i].wall_u = sc.tau, sc.wall_u
+            arr[i].fiber = _fiber_struct(fb.X, fb.q, fb.length, fb.radius, fb.density_ratio, fb.V, fb.W)
+        h = C.c_void_p()
+        r = L.lbm_batch_create(C.byref(p), arr, len(cases), C.byref(h))
+        if r != LBM_OK:
+            raise LBMError(r, L.lbm_batch_last_error(None).decode())
+        self._h = h
+        self.ncases = len(cases)
+        self.shapes = [(sc.nx, sc.ny, sc.nz) for sc in cases]
+        self.storage = p.storage
+
+    def _chk(self, r):
+        if r != LBM_OK:
+            raise LBMError(r, load().lbm_batch_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lbm_batch_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def set_kinematics(self, c, traj):
+        t = _f64(traj).reshape(-1, 13)
+        self._chk(load().lbm_batch_set_kinematics(self._h, c, _d(t), t.shape[0]))
+
+    def autotune(self, trial_steps=10, cache_path=None):
+        t = lbm_batch_tuning()
+        cp = cache_path.encode() if cache_path else None
+        self._chk(load().lbm_batch_autotune(self._h, trial_steps, cp, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in lbm_batch_tuning._fields_}
+
+    def set_config(self, threads=0, bins=0):
+        self._chk(load().lbm_batch_set_config(self._h, threads, bins))
+
+    def step(self, n=1):
+        self._chk(load().lbm_batch_step(self._h, int(n)))
+
+    def sync(self):
+        self._chk(load().lbm_batch_sync(self._h))
+
+    def force_torque(self):
+        F, M = np.zeros((self.ncases, 3)), np.zeros((self.ncases, 3))
+        self._chk(load().lbm_batch_get_force_torque(self._h, _d(F), _d(M)))
+        return F, M
+
+    def fiber_state(self):
+        n = self.ncases
+        X, q, V, W = np.zeros((n, 3)), np.zeros((n, 4)), np.zeros((n, 3)), np.zeros((n, 3))
+        self._chk(load().lbm_batch_get_fiber_state(self._h, _d(X), _d(q), _d(V), _d(W)))
+        return X, q, V, W
+
+    def history(self, c, first, count):
+        out = np.zeros((count, 19))
+        self._chk(load().lbm_batch_get_history(self._h, c, first, count, _d(out)))
+        return out
+
+    def fields(self, c):
+        nx, ny, nz = self.shapes[c]
+        dt = np.float64 if self.storage == LBM_F64 else np.float32
+        rho = np.zeros((nz, ny, nx), dt)
+        u = np.zeros((3, nz, ny, nx), dt)
+        flags = np.zeros((nz, ny, nx), np.uint8)
+        pid = np.zeros((nz, ny, nx), np.int32)
+        self._chk(load().lbm_batch_get_fields(self._h, c, rho.ctypes.data, u.ctypes.data,
+                                              flags.ctypes.data, pid.ctypes.data, 0))
+        return rho, u, flags, pid
+
+    def populations(self, c):
+        nx, ny, nz = self.shapes[c]
+        f = np.zeros((19, nz, ny, nx))
+        self._chk(load().lbm_batch_get_populations(self._h, c, _d(f)))
+        return f
+
+    def info(self):
+        i = lbm_batch_info()
+        self._chk(load().lbm_batch_get_info(self._h, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in lbm_batch_info._fields_}

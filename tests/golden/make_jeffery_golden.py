@@ -33,7 +33,7 @@ def run(seed, steps, wall_u, chunk=10000):
     sc = scenarios.single_fiber(seed=seed, wall_u=wall_u)
     f = sc.fibers[0]
     s = O.Sim(sc.nx, sc.ny, sc.nz, tau=sc.tau, magic=sc.magic, wall_u=sc.wall_u,
-              init_couette=True, implicit=True)
+              init_couette=True, coupling="implicit")
     s.add_fiber(f.X, f.q, f.length, f.radius, f.density_ratio, f.V, f.W)
     tx = np.zeros(steps)
     t0 = time.time()

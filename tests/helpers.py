@@ -39,7 +39,7 @@ def make_pair(sc, storage="f32", coupling="implicit", stream=None, history=4096,
                     init_couette=sc.init_couette, storage=storage, coupling=coupling,
                     stream=stream, history_capacity=history, **kw)
     o = O.Sim(sc.nx, sc.ny, sc.nz, tau=sc.tau, magic=sc.magic, wall_u=sc.wall_u,
-              init_couette=sc.init_couette, implicit=(coupling == "implicit"),
+              init_couette=sc.init_couette, coupling=coupling,
               z_periodic=kw.get("z_periodic", False))
     for f in sc.fibers:
         g.add_fiber(f.X, f.q, f.length, f.radius, f.density_ratio, f.V, f.W)

@@ -1,6 +1,6 @@
 """CPU checks of the library boundary: the shared library loads, exports
-every entry point declared in include/lbm.h, and the binding's structures
-match the header's layout.  No compute call is made (no GPU here)."""
+every entry point declared in include/*.h, and the binding's structures
+match the headers' layout.  No compute call is made (no GPU here)."""
 import ctypes as C
 import os
 import re
@@ -12,10 +12,16 @@ from paper_1503_06869_amd import lbm
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_functions():
-    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", src)))
+def declared_functions(header=None):
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for h in ([header] if header else sorted(os.listdir(inc))):
+        if not h.endswith(".h"):
+            continue
+        src = open(os.path.join(inc, h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", src))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -35,7 +41,8 @@ def test_header_declares_the_boundary_calls():
 def test_library_exports_every_declared_symbol(libso):
     missing = [n for n in declared_functions() if not hasattr(libso, n)]
     assert not missing, missing
-    assert sorted(lbm.EXPORTED) == declared_functions()
+    assert sorted(lbm.EXPORTED) == declared_functions("lbm.h")
+    assert sorted(lbm.EXPORTED_BATCH) == declared_functions("lbm_batch.h")
 
 
 def test_lattice_table_needs_no_gpu():
@@ -50,6 +57,12 @@ def test_struct_layout_matches_header():
     assert C.sizeof(lbm.lbm_params) == 5 * 4 + 4 + 4 * 8 + 3 * 8 + 4 * 4 + 8 + 8 + 2 * 4
     assert C.sizeof(lbm.lbm_fiber) == (3 + 4 + 3 + 3 + 3) * 8
     assert C.sizeof(lbm.lbm_info) == 8 + 4 + 4 + 8 * 4
+    # lbm_batch_case: 3 int32 (+4 pad), 2 doubles, lbm_fiber
+    assert C.sizeof(lbm.lbm_batch_case) == 3 * 4 + 4 + 2 * 8 + C.sizeof(lbm.lbm_fiber)
+    # lbm_batch_params: int32 (+4), 2 doubles, 4 int32, int64, pointer, 2 int32
+    assert C.sizeof(lbm.lbm_batch_params) == 4 + 4 + 2 * 8 + 4 * 4 + 8 + 8 + 2 * 4
+    assert C.sizeof(lbm.lbm_batch_tuning) == 4 + 4 + 8 + 4 + 4
+    assert C.sizeof(lbm.lbm_batch_info) == 8 + 4 * 3 + 4 + 8 * 4
 
 
 def test_params_default_and_argument_errors(libso):
@@ -66,3 +79,28 @@ def test_params_default_and_argument_errors(libso):
     assert L.lbm_create(C.byref(bad), C.byref(h)) == lbm.LBM_E_ARG
     assert L.lbm_create(None, C.byref(h)) == lbm.LBM_E_ARG
     assert L.lbm_step(None, 1) == lbm.LBM_E_ARG
+
+
+def test_batch_argument_errors(libso):
+    """Invalid batch arguments are rejected before any device call."""
+    L = lbm.load()
+    p = lbm.lbm_batch_params()
+    assert L.lbm_batch_params_default(C.byref(p)) == lbm.LBM_OK
+    assert p.storage == lbm.LBM_F32 and p.init_profile == lbm.LBM_INIT_COUETTE
+    h = C.c_void_p()
+    arr = (lbm.lbm_batch_case * 1)()
+    arr[0].nx = arr[0].ny = arr[0].nz = 32
+    arr[0].tau, arr[0].wall_u = 0.8, 0.005
+    arr[0].fiber = lbm._fiber_struct((15.5, 15.5, 15.5), (1, 0, 0, 0), 16.0, 2.0)
+    assert L.lbm_batch_create(C.byref(p), arr, 0, C.byref(h)) == lbm.LBM_E_ARG
+    bad = lbm.lbm_batch_params()
+    L.lbm_batch_params_default(C.byref(bad))
+    bad.threads = 300
+    assert L.lbm_batch_create(C.byref(bad), arr, 1, C.byref(h)) == lbm.LBM_E_ARG
+    arr[0].tau = 0.5
+    assert L.lbm_batch_create(C.byref(p), arr, 1, C.byref(h)) == lbm.LBM_E_GEOM
+    assert b"case 0" in L.lbm_batch_last_error(None)
+    arr[0].tau = 0.8
+    arr[0].fiber = lbm._fiber_struct((15.5, 15.5, 15.5), (1, 0, 0, 0), 30.0, 2.0)
+    assert L.lbm_batch_create(C.byref(p), arr, 1, C.byref(h)) == lbm.LBM_E_GEOM
+    assert L.lbm_batch_step(None, 1) == lbm.LBM_E_ARG

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 from oracle import pyoracle as O
+from paper_1503_06869_amd import scenarios
 
 RNG = np.random.default_rng(1234)
 
@@ -442,6 +443,31 @@ def test_uncovered_cells_are_refilled_with_equilibrium():
 
 
 # ---------------------------------------------------------------- P15 Jeffery
+def test_two_step_average_removes_the_period_two_torque_mode():
+    """At density ratio 1 and tau = 0.6 the implicit coupling without the
+    two-step average lets the torque alternate in sign from step to step
+    with growing amplitude; with the average of the velocity-free sums the
+    fiber keeps rotating at about half the shear rate.  (Property of the
+    coupled update, not of either formula alone.)"""
+    sc = scenarios.single_fiber(seed=0)
+    f = sc.fibers[0]
+    w = {}
+    for mode in ("implicit", "implicit_plain"):
+        o = O.Sim(32, 32, 32, tau=0.6, wall_u=0.005, init_couette=True, coupling=mode)
+        o.add_fiber(f.X, f.q, f.length, f.radius, 1.0, f.V, f.W)
+        o.step(60)
+        h = o.history(0, 60)
+        w[mode] = np.linalg.norm(h[:, 0, 16:19], axis=1)
+        if mode == "implicit_plain":
+            Mx = h[20:60, 0, 3:6]
+            # the growing mode flips the torque's sign every step
+            dots = np.einsum("ij,ij->i", Mx[1:], Mx[:-1])
+            assert (dots < 0).mean() > 0.9
+    half_shear = 0.5 * 2 * 0.005 / 32
+    assert np.all(w["implicit"][20:] < 3 * half_shear)
+    assert w["implicit_plain"][-1] > 30 * half_shear
+
+
 def test_oracle_tumbling_period_near_jeffery():
     """Jeffery's closed form T = 2 pi (r + 1/r) / shear rate holds for a
     spheroid in unbounded Stokes flow; a staircase cylinder of aspect ratio
