@@ -14,12 +14,16 @@ Prints one JSON line: MLUPS (all cells x steps / s), the roofline of the
 dominant kernel (the bulk stream-collide sweep, timed live with HIP events
 on the stream it runs on), and the FP64 oracle's rate on a bounded sample of
 the same workload on the host cores.  The FP16/BF16 deviation-storage forms
-of the same workload are timed too and reported under "forms".
+of the same workload, and the batched form (512 independent one-fiber shear
+cells of uneven size, edges 24..64, in one persistent graph-captured launch
+with autotuned workgroup size and bin count), are timed too and reported
+under "forms".
 """
 import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -91,6 +95,39 @@ def time_form(sc, storage, steps, warmup, torch):
     }
 
 
+def time_batched(steps, warmup, torch, trial_steps=6):
+    """Batched form: 512 cases, one persistent launch of `steps` steps."""
+    from paper_1503_06869_amd import lbm, scenarios
+    cases = scenarios.batched_cases(seed=0)
+    stream = torch.cuda.Stream()
+    b = lbm.Batch(cases, stream=stream.cuda_stream)
+    cache = os.environ.get("LBM_TUNE_CACHE", os.path.join(tempfile.gettempdir(), "lbm_batch_tune.txt"))
+    tune = b.autotune(trial_steps=trial_steps, cache_path=cache)
+    b.step(warmup)
+    b.sync()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    b.step(steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    b.sync()
+    ms = t0.elapsed_time(t1) / steps
+    info = b.info()
+    solid = 0
+    for c in range(len(cases)):
+        solid += int(b.fields(c)[2].sum())
+    b.close()
+    cells = info["cells"]
+    bytes_step = (cells - solid) * (BYTES_PER_LUP["f32"] - 1) + cells
+    return {"mlups": round(cells / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+            "steps_per_launch": steps, "cases": len(cases), "cells": cells,
+            "gbs": round(bytes_step / (ms * 1e-3) / 1e9, 1),
+            "hbm_frac": round(bytes_step / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "threads": tune["threads"], "bins": tune["bins"], "tuning_trials": tune["trials"]}
+
+
 def sweep_traffic():
     import hashlib
     src = os.path.join(ROOT, "paper_1503_06869_amd", "csrc", "sweep.hip")
@@ -122,6 +159,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--forms", default="f16,bf16", help="extra storage forms to time")
+    ap.add_argument("--batched-steps", type=int, default=200,
+                    help="steps of the batched form's timed launch (0: skip it)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run the plain copy kernel (traffic-counter calibration)")
     a = ap.parse_args()
@@ -162,6 +201,8 @@ def main():
         forms[st] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
                      "sweep_gbs": round(r["sweep_gbs"], 1),
                      "sweep_hbm_frac": round(r["sweep_gbs"] / HBM_PEAK_GBS, 4)}
+    if a.batched_steps > 0:
+        forms["batched_512_cases"] = time_batched(a.batched_steps, 10, torch)
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(sc)

@@ -336,6 +336,8 @@ typedef struct {
     double F[3], M[3];
     double F0p[3], M0p[3];  /* velocity-free sums of the previous step */
     int have_prev;
+    double corr[6];         /* closure correction dF, dM for the next step */
+    int has_corr;
     double *traj;           /* prescribed kinematics, 13 per step, or NULL */
     int64_t traj_n, traj_pos;
 } fiber;
@@ -467,6 +469,18 @@ int or_add_fiber(or_sim *s, const double X[3], const double q[4], double length,
     }
     for (int64_t i = 0; i < s->ncell; ++i) s->flag[i] = s->pid[i] >= 0;
     return (ov > 0) ? -2 : s->nf - 1;
+}
+
+int or_set_correction(or_sim *s, int id, const double dF[3], const double dM[3])
+{
+    if (id < 0 || id >= s->nf) return -1;
+    fiber *f = &s->fib[id];
+    for (int k = 0; k < 3; ++k) {
+        f->corr[k] = dF[k];
+        f->corr[3 + k] = dM[k];
+    }
+    f->has_corr = 1;
+    return 0;
 }
 
 int or_set_kinematics(or_sim *s, int id, const double *traj, int64_t nsteps)
@@ -630,10 +644,19 @@ static void one_step(or_sim *s)
         fiber *f = &s->fib[i];
         const double *rd = red + 39 * i;
         memcpy(old + 16 * i, f->st, 16 * sizeof(double));
+        /* closure correction of this step (zero when none was set) */
+        double cF[3] = {0.0, 0.0, 0.0}, cM[3] = {0.0, 0.0, 0.0};
+        if (f->has_corr)
+            for (int k = 0; k < 3; ++k) {
+                cF[k] = f->corr[k];
+                cM[k] = f->corr[3 + k];
+            }
         if (f->traj && f->traj_pos < f->traj_n) {
             /* prescribed motion: the force reported is the direct formula */
-            memcpy(f->F, rd, 3 * sizeof(double));
-            memcpy(f->M, rd + 3, 3 * sizeof(double));
+            for (int k = 0; k < 3; ++k) {
+                f->F[k] = f->has_corr ? rd[k] + cF[k] : rd[k];
+                f->M[k] = f->has_corr ? rd[3 + k] + cM[k] : rd[3 + k];
+            }
             const double *tr = f->traj + 13 * f->traj_pos++;
             memcpy(f->st, tr, 13 * sizeof(double));
             double t[3];
@@ -648,14 +671,20 @@ static void one_step(or_sim *s)
                 const int avg = p->coupling == 0 && f->have_prev;
                 F0u[k] = avg ? 0.5 * (rd[6 + k] + f->F0p[k]) : rd[6 + k];
                 M0u[k] = avg ? 0.5 * (rd[9 + k] + f->M0p[k]) : rd[9 + k];
+                if (f->has_corr) {
+                    F0u[k] += cF[k];
+                    M0u[k] += cM[k];
+                }
             }
             double out[16];
             or_rigid_step_implicit(f->st, f->mass, f->i_par, f->i_perp, F0u, M0u, rd + 12,
                                    rd + 21, rd + 30, nx, ny, nz, p->z_periodic, out, f->F, f->M);
             memcpy(f->st, out, 16 * sizeof(double));
         } else {
-            memcpy(f->F, rd, 3 * sizeof(double));
-            memcpy(f->M, rd + 3, 3 * sizeof(double));
+            for (int k = 0; k < 3; ++k) {
+                f->F[k] = f->has_corr ? rd[k] + cF[k] : rd[k];
+                f->M[k] = f->has_corr ? rd[3 + k] + cM[k] : rd[3 + k];
+            }
             double out[16];
             or_rigid_step(f->st, f->mass, f->i_par, f->i_perp, f->F, f->M, nx, ny, nz,
                           p->z_periodic, out);
@@ -666,6 +695,7 @@ static void one_step(or_sim *s)
             f->M0p[k] = rd[9 + k];
         }
         f->have_prev = 1;
+        f->has_corr = 0;
     }
     free(red);
 

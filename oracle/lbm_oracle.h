@@ -84,6 +84,9 @@ void    or_destroy(or_sim *s);
 int     or_add_fiber(or_sim *s, const double X[3], const double q[4], double length,
                      double radius, double density_ratio, const double V[3], const double W[3]);
 int     or_set_kinematics(or_sim *s, int id, const double *traj /*[nsteps][13]*/, int64_t nsteps);
+/* add dF, dM to fiber id's momentum-exchange force and torque in the next
+   step only (to the velocity-free part for the implicit couplings) */
+int     or_set_correction(or_sim *s, int id, const double dF[3], const double dM[3]);
 void    or_step(or_sim *s, int64_t n);
 void    or_get_populations(const or_sim *s, double *f /*[19][nz][ny][nx]*/);
 void    or_set_populations(or_sim *s, const double *f);

@@ -56,6 +56,7 @@ def lib():
         L.or_add_fiber.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_double, C.c_double,
                                    _dp, _dp]
         L.or_set_kinematics.argtypes = [C.c_void_p, C.c_int, _dp, C.c_int64]
+        L.or_set_correction.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
         L.or_step.argtypes = [C.c_void_p, C.c_int64]
         L.or_get_populations.argtypes = [C.c_void_p, _dp]
         L.or_set_populations.argtypes = [C.c_void_p, _dp]
@@ -174,6 +175,10 @@ class Sim:
     def set_kinematics(self, fid, traj):
         t = _arr(traj).reshape(-1, 13)
         lib().or_set_kinematics(self._h, fid, _d(t), t.shape[0])
+
+    def set_correction(self, fid, dF, dM):
+        """Add dF, dM to fiber fid's force and torque in the next step only."""
+        lib().or_set_correction(self._h, fid, _d(_arr(dF, 3)), _d(_arr(dM, 3)))
 
     def step(self, n=1):
         lib().or_step(self._h, int(n))

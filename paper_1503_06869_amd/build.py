@@ -26,6 +26,8 @@ SOURCES = {
     # the sweep part keeps the default contraction of sweep.hip; the particle
     # part and the host code follow a contraction-off pragma in the header
     "batched.hip": [],
+    "features.hip": [],
+    "mlp.hip": [],
 }
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/lbm.h"
+#include "../../include/lbm_mlp.h"
 #include "lbm_dev.h"
 
 using namespace lbm;
@@ -60,6 +61,11 @@ struct lbm_ctx {
     size_t ev_used = 0;
     int64_t timed_sweeps = 0;
     double timed_ms = 0.0;
+    // learned closure (not owned)
+    lbm_mlp *closure = nullptr;
+    float *feat = nullptr, *cy = nullptr;
+    double *corr = nullptr;
+    unsigned long long *cstats = nullptr;
 };
 
 static lbm_status fail(lbm_ctx *c, lbm_status s, const std::string &m)
@@ -168,6 +174,7 @@ static PartData part_data(lbm_ctx *c, PState *cur, PState *next)
     pd.hist_cap = c->p.history_capacity;
     pd.coupling = c->p.coupling;
     pd.rho0 = c->p.rho0;
+    pd.corr = c->closure ? c->corr : nullptr;
     pd.ctr = c->ctr;
     pd.list_cap = c->list_cap;
     return pd;
@@ -315,7 +322,19 @@ static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hi
         if (e != hipSuccess && *err == hipSuccess) *err = e;
         return;
     }
-    e = hipEventRecord(c->ev_fork, c->st);
+    if (c->closure) {
+        // learned closure: features of the state the sweep reads, network,
+        // corrections for the rigid-body update of this step
+        const MlpDev md = mlp_device_view(c->closure);
+        const double gamma = 2.0 * c->p.wall_u / c->p.nz, nu = (c->p.tau - 0.5) / 3.0;
+        e = launch_sample_features(c->sk, odd, c->f, c->flags, c->pid, cur, c->pc, c->np, c->g, c->ph, gamma,
+                                   c->feat, c->st);
+        if (e == hipSuccess) e = launch_mlp_forward(md, c->feat, c->np, c->cy, c->st);
+        if (e == hipSuccess)
+            e = launch_closure_apply(md, c->feat, c->cy, c->pc, c->np, c->p.rho0, nu, gamma, c->corr, c->cstats,
+                                     c->st);
+    }
+    if (e == hipSuccess) e = hipEventRecord(c->ev_fork, c->st);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->st2, c->ev_fork, 0);
     if (e == hipSuccess)
         e = launch_sweep(c->sk, odd, c->f, c->flags, c->g, c->ph, b, c->sweep_grid, c->bnd_grid, c->st,
@@ -484,6 +503,10 @@ lbm_status lbm_destroy(lbm_ctx *c)
     drop_graph(c);
     for (hipEvent_t e : c->ev) hipEventDestroy(e);
     free_particles(c);
+    dfree(c->feat);
+    dfree(c->cy);
+    dfree(c->corr);
+    dfree(c->cstats);
     dfree(c->f);
     dfree(c->flags);
     dfree(c->pid);
@@ -502,6 +525,7 @@ lbm_status lbm_add_fiber(lbm_ctx *c, const lbm_fiber *f, int32_t *id)
 {
     if (!c || !f) return fail(c, LBM_E_ARG, "null argument");
     if (c->steps != 0) return fail(c, LBM_E_STATE, "fibers can only be added before the first step");
+    if (c->closure) return fail(c, LBM_E_STATE, "detach the closure before adding fibers");
     if (!(f->length > 0.0) || !(f->radius > 0.0) || !(f->density_ratio > 0.0))
         return fail(c, LBM_E_ARG, "length, radius and density_ratio must be positive");
     const double qn = std::sqrt(f->quat[0] * f->quat[0] + f->quat[1] * f->quat[1] +
@@ -846,6 +870,64 @@ lbm_status lbm_get_sweep_time(lbm_ctx *c, double *total_ms, int64_t *nsweeps)
     c->ev_used = 0;
     if (total_ms) *total_ms = c->timed_ms;
     if (nsweeps) *nsweeps = c->timed_sweeps;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_closure(lbm_ctx *c, lbm_mlp *m)
+{
+    if (!c) return LBM_E_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    drop_graph(c);
+    if (!m) {
+        c->closure = nullptr;
+        return LBM_OK;
+    }
+    if (c->p.z_periodic || c->p.wall_u == 0.0)
+        return fail(c, LBM_E_ARG, "the closure needs a shear cell (moving walls, U != 0)");
+    if (c->np == 0) return fail(c, LBM_E_STATE, "add the fibers before attaching the closure");
+    dfree(c->feat);
+    dfree(c->cy);
+    dfree(c->corr);
+    HIPCHK(c, dalloc(c, &c->feat, size_t(c->np) * LBM_MLP_IN));
+    HIPCHK(c, dalloc(c, &c->cy, size_t(c->np) * LBM_MLP_OUT));
+    HIPCHK(c, dalloc(c, &c->corr, size_t(c->np) * LBM_MLP_OUT));
+    if (!c->cstats) HIPCHK(c, dalloc(c, &c->cstats, 2));
+    HIPCHK(c, hipMemsetAsync(c->corr, 0, size_t(c->np) * LBM_MLP_OUT * sizeof(double), c->st));
+    HIPCHK(c, hipMemsetAsync(c->cstats, 0, 2 * sizeof(unsigned long long), c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    c->closure = m;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_closure_stats(lbm_ctx *c, int64_t *applied, int64_t *fallbacks)
+{
+    if (!c) return LBM_E_ARG;
+    unsigned long long h[2] = {0, 0};
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (c->cstats) HIPCHK(c, hipMemcpy(h, c->cstats, sizeof h, hipMemcpyDeviceToHost));
+    if (applied) *applied = int64_t(h[0]);
+    if (fallbacks) *fallbacks = int64_t(h[1]);
+    return LBM_OK;
+}
+
+lbm_status lbm_sample_features(lbm_ctx *c, float *out, int32_t dst_is_device)
+{
+    if (!c || !out) return LBM_E_ARG;
+    if (c->np == 0) return LBM_OK;
+    if (c->p.z_periodic || c->p.wall_u == 0.0)
+        return fail(c, LBM_E_ARG, "features need a shear cell (moving walls, U != 0)");
+    lbm_status s = check_device_errors(c);
+    if (s != LBM_OK) return s;
+    const size_t n = size_t(c->np) * LBM_MLP_IN;
+    float *d = out;
+    if (!dst_is_device) HIPCHK(c, hipMalloc(&d, n * sizeof(float)));
+    const double gamma = 2.0 * c->p.wall_u / c->p.nz;
+    hipError_t e = launch_sample_features(c->sk, (c->steps & 1) != 0, c->f, c->flags, c->pid, c->ps[c->steps & 1],
+                                          c->pc, c->np, c->g, c->ph, gamma, d, c->st);
+    if (e == hipSuccess && !dst_is_device) e = hipMemcpyAsync(out, d, n * sizeof(float), hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (!dst_is_device) hipFree(d);
+    if (e != hipSuccess) return fail(c, LBM_E_HIP, hipGetErrorString(e));
     return LBM_OK;
 }
 

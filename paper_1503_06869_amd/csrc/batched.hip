@@ -29,6 +29,7 @@
 #include <vector>
 
 #include "../../include/lbm_batch.h"
+#include "../../include/lbm_mlp.h"
 #include "lbm_sweep_dev.h"
 #include "lbm_particle_dev.h"   // FP contraction off from here on, as in particles.hip
 
@@ -1074,6 +1075,33 @@ lbm_status lbm_batch_get_populations(lbm_batch *b, int32_t c, double *f)
     if (e == hipSuccess) e = hipMemcpyAsync(f, d, n * sizeof(double), hipMemcpyDeviceToHost, b->st);
     if (e == hipSuccess) e = hipStreamSynchronize(b->st);
     hipFree(d);
+    if (e != hipSuccess) return bfail(b, LBM_E_HIP, hipGetErrorString(e));
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_sample_features(lbm_batch *b, float *out, int32_t dst_is_device)
+{
+    if (!b || !out) return LBM_E_ARG;
+    lbm_status s = check_batch_errors(b);
+    if (s != LBM_OK) return s;
+    for (int i = 0; i < b->ncase; ++i)
+        if (b->hc[i].wall_u == 0.0) return bfail(b, LBM_E_ARG, "features need U != 0 in every case");
+    const size_t n = size_t(b->ncase) * LBM_MLP_IN;
+    float *d = out;
+    if (!dst_is_device) BHIP(b, hipMalloc(&d, n * sizeof(float)));
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < b->ncase && e == hipSuccess; ++i) {
+        const CaseDev &cd = b->hcd[i];
+        const void *fc = static_cast<const char *>(b->f) + cd.f_off * b->esz;
+        const PState *ps = b->ps + size_t(i) * 2 + size_t(b->steps & 1);
+        const PConst *pc = &b->cases[i].pc;
+        const double gamma = 2.0 * b->hc[i].wall_u / b->hc[i].nz;
+        e = launch_sample_features(b->sk, (b->steps & 1) != 0, fc, b->flags + cd.cell_off, b->pid + cd.cell_off,
+                                   ps, pc, 1, cd.g, cd.pd, gamma, d + size_t(i) * LBM_MLP_IN, b->st);
+    }
+    if (e == hipSuccess && !dst_is_device) e = hipMemcpyAsync(out, d, n * sizeof(float), hipMemcpyDeviceToHost, b->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->st);
+    if (!dst_is_device) hipFree(d);
     if (e != hipSuccess) return bfail(b, LBM_E_HIP, hipGetErrorString(e));
     return LBM_OK;
 }

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct lbm_mlp;
+
 namespace lbm {
 
 // ---------------------------------------------------------------------------
@@ -145,6 +147,7 @@ struct PartData {
     int64_t hist_cap;
     int32_t coupling;          // lbm_coupling
     double rho0;
+    const double *corr;        // [np][6] closure corrections dF, dM, or null
     DevCounters *ctr;
     uint32_t list_cap;
     int32_t nslab;             // blocks per fiber (z-planes of a box dealt round robin)
@@ -179,5 +182,21 @@ hipError_t launch_remap(int sk, bool next_odd, void *f, int32_t *pid, const Part
 hipError_t launch_near(uint8_t *flags, const int32_t *pid, uint32_t *list_cell, uint32_t *list_mask,
                        const PartData &pd, const Geo &g, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, size_t nbytes, hipStream_t st);
+
+// closure network (mlp.hip) and feature sampling (features.hip)
+struct MlpDev {
+    const uint16_t *wb;        // BF16 parameters
+    const float *in_mean, *in_inv_std, *out_scale, *env_min, *env_max;
+};
+MlpDev mlp_device_view(const ::lbm_mlp *m);
+hipError_t launch_mlp_forward(const MlpDev &m, const float *x, int n, float *y, hipStream_t st);
+hipError_t launch_closure_apply(const MlpDev &m, const float *feat, const float *y, const PConst *pc, int np,
+                                double rho0, double nu, double gamma, double *corr, unsigned long long *stats,
+                                hipStream_t st);
+// features [np][247] of np fibers whose states are ps[k * ps_stride] (one
+// lattice: the arrays of that lattice)
+hipError_t launch_sample_features(int sk, bool swapped, const void *f, const uint8_t *flags, const int32_t *pid,
+                                  const PState *ps, const PConst *pc, int np, const Geo &g,
+                                  const Phys<double> &ph, double gamma, float *out, hipStream_t st);
 
 }  // namespace lbm

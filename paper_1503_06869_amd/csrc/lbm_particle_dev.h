@@ -266,9 +266,12 @@ __device__ __forceinline__ void unpack(const double *acc, double A[3][3], double
 // velocities and solve the 6x6 system for (V', W'); coupling 0 takes for
 // F0, M0 the mean of this and the previous step's sums, which removes a
 // growing period-two oscillation of the torque at density ratio 1 and
-// small tau.  The new state carries this step's F0, M0 forward.
+// small tau.  The new state carries this step's F0, M0 forward.  corr
+// (dF[3], dM[3] of a closure, or null) is added to the force and torque
+// (to F0, M0 for the implicit forms).
 __device__ __forceinline__ void rigid_update(const PState &s, const PConst &c, const double *acc, int coupling,
-                             const double *traj_row, const Geo &g, PState &o, double F[3], double M[3])
+                             const double *traj_row, const Geo &g, PState &o, double F[3], double M[3],
+                             const double *corr = nullptr)
 {
     double A[3][3], B[3][3], C[3][3];
     unpack(acc, A, B, C);
@@ -280,8 +283,8 @@ __device__ __forceinline__ void rigid_update(const PState &s, const PConst &c, c
             f -= A[i][j] * s.V[j] + B[i][j] * s.W[j];
             m -= B[j][i] * s.V[j] + C[i][j] * s.W[j];
         }
-        F[i] = f;
-        M[i] = m;
+        F[i] = corr ? f + corr[i] : f;
+        M[i] = corr ? m + corr[3 + i] : m;
     }
     const bool per[3] = {true, true, g.zper != 0};
     const uint32_t n[3] = {g.nx, g.ny, g.nz};
@@ -307,6 +310,10 @@ __device__ __forceinline__ void rigid_update(const PState &s, const PConst &c, c
         for (int k = 0; k < 3; ++k) {
             F0u[k] = avg ? 0.5 * (F0[k] + s.F0p[k]) : F0[k];
             M0u[k] = avg ? 0.5 * (M0[k] + s.M0p[k]) : M0[k];
+            if (corr) {
+                F0u[k] += corr[k];
+                M0u[k] += corr[3 + k];
+            }
         }
         double K[6][6], b[6], x[6];
         for (int i = 0; i < 3; ++i)

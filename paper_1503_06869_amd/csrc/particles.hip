@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void k_rigid(PartData pd, Geo g)
         }
         PState o;
         double F[3], M[3];
-        rigid_update(s, c, ac, pd.coupling, row, g, o, F, M);
+        rigid_update(s, c, ac, pd.coupling, row, g, o, F, M, pd.corr ? pd.corr + size_t(p) * 6 : nullptr);
         bool bad = false;
         for (int k = 0; k < 3; ++k) bad |= !isfinite(F[k]) || !isfinite(M[k]);
         if (bad) atomicOr(&pd.ctr->err_unstable, 1u);

@@ -39,6 +39,13 @@ EXPORTED_BATCH = [
     "lbm_batch_get_history", "lbm_batch_get_fields", "lbm_batch_get_populations",
     "lbm_batch_get_info",
 ]
+EXPORTED_MLP = [
+    "lbm_mlp_create", "lbm_mlp_destroy", "lbm_mlp_last_error", "lbm_mlp_set_params",
+    "lbm_mlp_get_params", "lbm_mlp_set_norm", "lbm_mlp_forward", "lbm_mlp_loss_grad",
+    "lbm_mlp_adam", "lbm_mlp_train", "lbm_set_closure", "lbm_get_closure_stats",
+    "lbm_sample_features", "lbm_batch_sample_features",
+]
+MLP_IN, MLP_OUT, MLP_NPARAM = 247, 6, 20422
 
 
 class lbm_params(C.Structure):
@@ -87,6 +94,7 @@ class lbm_batch_info(C.Structure):
 
 
 _dp = C.POINTER(C.c_double)
+_fp = C.POINTER(C.c_float)
 _lib = None
 
 
@@ -136,6 +144,21 @@ def load():
         "lbm_batch_get_fields": ([vp, C.c_int32, vp, vp, vp, vp, C.c_int32], C.c_int),
         "lbm_batch_get_populations": ([vp, C.c_int32, _dp], C.c_int),
         "lbm_batch_get_info": ([vp, C.POINTER(lbm_batch_info)], C.c_int),
+        "lbm_mlp_create": ([C.c_uint64, vp, C.POINTER(vp)], C.c_int),
+        "lbm_mlp_destroy": ([vp], C.c_int),
+        "lbm_mlp_last_error": ([vp], C.c_char_p),
+        "lbm_mlp_set_params": ([vp, _fp], C.c_int),
+        "lbm_mlp_get_params": ([vp, _fp, C.POINTER(C.c_uint16)], C.c_int),
+        "lbm_mlp_set_norm": ([vp, _fp, _fp, _fp, _fp, _fp], C.c_int),
+        "lbm_mlp_forward": ([vp, vp, C.c_int32, vp], C.c_int),
+        "lbm_mlp_loss_grad": ([vp, vp, vp, C.c_int32, _dp, _fp], C.c_int),
+        "lbm_mlp_adam": ([vp, C.c_float, C.c_float, C.c_float, C.c_float], C.c_int),
+        "lbm_mlp_train": ([vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_uint64, _dp],
+                          C.c_int),
+        "lbm_set_closure": ([vp, vp], C.c_int),
+        "lbm_get_closure_stats": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
+        "lbm_sample_features": ([vp, vp, C.c_int32], C.c_int),
+        "lbm_batch_sample_features": ([vp, vp, C.c_int32], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -214,8 +237,8 @@ class Context:
             raise LBMError(r, load().lbm_last_error(self._h).decode())
 
     def close(self):
-        if getattr(self, "_h", None):
-            load().lbm_destroy(self._h)
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.lbm_destroy(self._h)
             self._h = None
 
     __del__ = close
@@ -292,6 +315,21 @@ class Context:
         self._chk(load().lbm_get_info(self._h, C.byref(i)))
         return {k: getattr(i, k) for k, _ in lbm_info._fields_}
 
+    def set_closure(self, mlp):
+        """Attach a trained Mlp (None detaches); the Mlp must outlive the use."""
+        self._closure = mlp
+        self._chk(load().lbm_set_closure(self._h, mlp._h if mlp is not None else None))
+
+    def closure_stats(self):
+        a, f = C.c_int64(), C.c_int64()
+        self._chk(load().lbm_get_closure_stats(self._h, C.byref(a), C.byref(f)))
+        return a.value, f.value
+
+    def features(self):
+        out = np.zeros((self.nfibers, MLP_IN), np.float32)
+        self._chk(load().lbm_sample_features(self._h, out.ctypes.data, 0))
+        return out
+
     def enable_sweep_timing(self, on=True):
         self._chk(load().lbm_enable_sweep_timing(self._h, int(bool(on))))
 
@@ -352,8 +390,9 @@ class Batch:
             raise LBMError(r, load().lbm_batch_last_error(self._h).decode())
 
     def close(self):
-        if getattr(self, "_h", None):
-            load().lbm_batch_destroy(self._h)
+        # _lib is None only during interpreter shutdown; then nothing is freed
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.lbm_batch_destroy(self._h)
             self._h = None
 
     __del__ = close
@@ -410,7 +449,82 @@ class Batch:
         self._chk(load().lbm_batch_get_populations(self._h, c, _d(f)))
         return f
 
+    def features(self):
+        out = np.zeros((self.ncases, MLP_IN), np.float32)
+        self._chk(load().lbm_batch_sample_features(self._h, out.ctypes.data, 0))
+        return out
+
+    def features_to_device(self, ptr):
+        self._chk(load().lbm_batch_sample_features(self._h, C.c_void_p(ptr), 1))
+
     def info(self):
         i = lbm_batch_info()
         self._chk(load().lbm_batch_get_info(self._h, C.byref(i)))
         return {k: getattr(i, k) for k, _ in lbm_batch_info._fields_}
+
+
+def _f32(x, n=None):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    if n is not None and a.size != n:
+        raise ValueError("expected %d values, got %d" % (n, a.size))
+    return a
+
+
+class Mlp:
+    """The closure network (owns an lbm_mlp).  Device arrays are passed as
+    data pointers (e.g. torch tensors' data_ptr())."""
+
+    def __init__(self, seed=0, stream=None):
+        h = C.c_void_p()
+        r = load().lbm_mlp_create(seed, stream, C.byref(h))
+        if r != LBM_OK:
+            raise LBMError(r, "lbm_mlp_create failed")
+        self._h = h
+
+    def _chk(self, r):
+        if r != LBM_OK:
+            raise LBMError(r, load().lbm_mlp_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.lbm_mlp_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def set_params(self, w):
+        a = _f32(w, MLP_NPARAM)
+        self._chk(load().lbm_mlp_set_params(self._h, a.ctypes.data_as(_fp)))
+
+    def params(self):
+        w = np.zeros(MLP_NPARAM, np.float32)
+        wb = np.zeros(MLP_NPARAM, np.uint16)
+        self._chk(load().lbm_mlp_get_params(self._h, w.ctypes.data_as(_fp),
+                                            wb.ctypes.data_as(C.POINTER(C.c_uint16))))
+        return w, wb
+
+    def set_norm(self, in_mean=None, in_inv_std=None, out_scale=None, env_min=None, env_max=None):
+        def p(a, n):
+            return None if a is None else _f32(a, n).ctypes.data_as(_fp)
+        keep = [None if a is None else _f32(a) for a in (in_mean, in_inv_std, out_scale, env_min, env_max)]
+        self._chk(load().lbm_mlp_set_norm(self._h, p(keep[0], MLP_IN), p(keep[1], MLP_IN),
+                                          p(keep[2], MLP_OUT), p(keep[3], MLP_IN), p(keep[4], MLP_IN)))
+
+    def forward(self, x_ptr, n, y_ptr):
+        self._chk(load().lbm_mlp_forward(self._h, C.c_void_p(x_ptr), n, C.c_void_p(y_ptr)))
+
+    def loss_grad(self, x_ptr, t_ptr, n, want_grad=True):
+        loss = C.c_double()
+        g = np.zeros(MLP_NPARAM, np.float32) if want_grad else None
+        self._chk(load().lbm_mlp_loss_grad(self._h, C.c_void_p(x_ptr), C.c_void_p(t_ptr), n, C.byref(loss),
+                                           g.ctypes.data_as(_fp) if g is not None else None))
+        return loss.value, g
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._chk(load().lbm_mlp_adam(self._h, lr, beta1, beta2, eps))
+
+    def train(self, x_ptr, t_ptr, n, epochs, batch, lr, shuffle_seed=0):
+        losses = np.zeros(epochs)
+        self._chk(load().lbm_mlp_train(self._h, C.c_void_p(x_ptr), C.c_void_p(t_ptr), n, epochs, batch, lr,
+                                       shuffle_seed, _d(losses)))
+        return losses

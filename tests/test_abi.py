@@ -43,6 +43,7 @@ def test_library_exports_every_declared_symbol(libso):
     assert not missing, missing
     assert sorted(lbm.EXPORTED) == declared_functions("lbm.h")
     assert sorted(lbm.EXPORTED_BATCH) == declared_functions("lbm_batch.h")
+    assert sorted(lbm.EXPORTED_MLP) == declared_functions("lbm_mlp.h")
 
 
 def test_lattice_table_needs_no_gpu():
