@@ -16,8 +16,9 @@ on the stream it runs on), and the FP64 oracle's rate on a bounded sample of
 the same workload on the host cores.  The FP16/BF16 deviation-storage forms
 of the same workload, and the batched form (512 independent one-fiber shear
 cells of uneven size, edges 24..64, in one persistent graph-captured launch
-with autotuned workgroup size and bin count), are timed too and reported
-under "forms".
+with autotuned workgroup size and bin count), and the learned-coarse form
+(128^3, 200 under-resolved fibers with the trained closure attached, beside
+the same run without it) are timed too and reported under "forms".
 """
 import argparse
 import json
@@ -128,6 +129,51 @@ def time_batched(steps, warmup, torch, trial_steps=6):
             "threads": tune["threads"], "bins": tune["bins"], "tuning_trials": tune["trials"]}
 
 
+CLOSURE_NET = os.path.join(ROOT, "paper_1503_06869_amd", "closure_net.npz")
+
+
+def time_learned(steps, warmup, torch):
+    """Learned-coarse form: 128^3, 200 under-resolved fibers (d = 2, AR 4-12),
+    with the closure attached, beside the same run without it.  One coarse
+    step stands for 2^3 fine cells x 4 fine steps of the resolved run."""
+    from paper_1503_06869_amd import closure, lbm, scenarios
+    sc = scenarios.learned_coarse(seed=0)
+    out = {"cells": sc.ncell, "fibers": len(sc.fibers)}
+    if os.path.exists(CLOSURE_NET):
+        mlp, _ = closure.load(CLOSURE_NET)
+        out["network"] = "trained (paper_1503_06869_amd/closure_net.npz)"
+    else:
+        mlp = lbm.Mlp(seed=0)
+        out["network"] = "untrained (no closure_net.npz): cost only"
+    for name, m in (("plain", None), ("learned", mlp)):
+        stream = torch.cuda.Stream()
+        g = lbm.Context(sc.nx, sc.ny, sc.nz, tau=sc.tau, wall_u=sc.wall_u, init_couette=True,
+                        stream=stream.cuda_stream)
+        for f in sc.fibers:
+            g.add_fiber(f.X, f.q, f.length, f.radius, f.density_ratio, f.V, f.W)
+        if m is not None:
+            g.set_closure(m)
+        g.step(warmup)
+        g.sync()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record(stream)
+        g.step(steps)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        g.sync()
+        ms = t0.elapsed_time(t1) / steps
+        out[name] = {"mlups": round(sc.ncell / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4)}
+        if m is not None:
+            a, fb = g.closure_stats()
+            out[name]["fallback_frac"] = round(fb / max(1, a + fb), 4)
+        g.close()
+    out["learned"]["fine_equivalent_mlups"] = round(32 * out["learned"]["mlups"], 1)
+    mlp.close()
+    return out
+
+
 def sweep_traffic():
     import hashlib
     src = os.path.join(ROOT, "paper_1503_06869_amd", "csrc", "sweep.hip")
@@ -161,6 +207,8 @@ def main():
     ap.add_argument("--forms", default="f16,bf16", help="extra storage forms to time")
     ap.add_argument("--batched-steps", type=int, default=200,
                     help="steps of the batched form's timed launch (0: skip it)")
+    ap.add_argument("--learned-steps", type=int, default=500,
+                    help="steps of the learned-coarse form (0: skip it)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run the plain copy kernel (traffic-counter calibration)")
     a = ap.parse_args()
@@ -203,6 +251,8 @@ def main():
                      "sweep_hbm_frac": round(r["sweep_gbs"] / HBM_PEAK_GBS, 4)}
     if a.batched_steps > 0:
         forms["batched_512_cases"] = time_batched(a.batched_steps, 10, torch)
+    if a.learned_steps > 0:
+        forms["learned_coarse_128cube_200fibers"] = time_learned(a.learned_steps, 20, torch)
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(sc)

@@ -17,20 +17,22 @@
  * nearest even of the FP32 master); Adam updates the FP32 master and
  * re-rounds.
  *
- * Features of a fiber (LBM_MLP_IN = 247): at the points P0 = X, P1 = X +
- * (L/2) t, P2 = X - (L/2) t, and offsets o in {-2, 0, 2}^3 (index m = (iz*3 +
- * iy)*3 + ix, i in {0,1,2} for -2, 0, 2), the fluid velocity at P_k + o
- * (trilinear in the cell-centre velocities; fiber cells contribute the
- * rigid-body velocity; x, y periodic, z clamped to [0, nz-1]) minus the
- * rigid-body velocity V + W x (P_k + o - X), divided by gamma L, with gamma
- * = 2 U / nz the shear rate of the cell: feature (k*27 + m)*3 + c.  Then the
- * orientation quaternion (w, x, y, z) with w >= 0.
+ * Features of a fiber (LBM_MLP_IN = 247), in the fiber's body frame R(q)
+ * (columns: the axis t = R(q) e_x, R(q) e_y, R(q) e_z): at the points
+ * P_k + R(q) o with P0 = X, P1 = X + (L/2) t, P2 = X - (L/2) t and o in
+ * {-2, 0, 2}^3 (index m = (iz*3 + iy)*3 + ix, i in {0,1,2} for -2, 0, 2), the
+ * fluid velocity (trilinear in the cell-centre velocities; fiber cells
+ * contribute the rigid-body velocity; x, y periodic, z clamped to
+ * [0, nz-1]) minus the rigid-body velocity V + W x (P_k + R(q) o - X),
+ * rotated by R(q)^T and divided by gamma L, with gamma = 2 U / nz the shear
+ * rate of the cell: feature (k*27 + m)*3 + c.  Then the orientation
+ * quaternion (w, x, y, z) with w >= 0.
  *
- * Outputs: y[0..2] = dF / (rho0 nu gamma L^2), y[3..5] = dM / (rho0 nu gamma
- * L^3), nu = (tau - 1/2)/3, after multiplication by out_scale.  The inputs
- * are normalised as (x - in_mean) * in_inv_std before the first layer.
- * Fallback: a fiber with any raw feature outside [env_min, env_max] gets no
- * correction (counted).
+ * Outputs (body frame): y[0..2] = R^T dF / (rho0 nu gamma L^2), y[3..5] =
+ * R^T dM / (rho0 nu gamma L^3), nu = (tau - 1/2)/3, after multiplication by
+ * out_scale.  The inputs are normalised as (x - in_mean) * in_inv_std
+ * before the first layer.  Fallback: a fiber with any raw feature outside
+ * [env_min, env_max] gets no correction (counted).
  *
  * All x / t / y pointers of the lbm_mlp_* compute calls are device memory;
  * the MLP's work is ordered on its stream.

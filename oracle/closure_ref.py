@@ -16,8 +16,8 @@ its input features, written out directly with numpy:
   * BF16 round-to-nearest-even of FP32 values;
   * the features of a fiber from a velocity field: velocities relative to
     the rigid motion on the 3 x 27 stencil (centre and tips, offsets
-    {-2, 0, 2}^3, trilinear, z clamped), divided by gamma L, and the
-    quaternion with w >= 0.
+    {-2, 0, 2}^3 along the body axes, trilinear, z clamped), in the body
+    frame, divided by gamma L, and the quaternion with w >= 0.
 """
 import numpy as np
 from scipy.special import erf
@@ -102,18 +102,27 @@ def adam(w, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8):
     return w, m, v
 
 
+def rotation(q):
+    """R(q) for a unit quaternion (w, x, y, z): columns are the body axes."""
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
 def features(u, X, q, V, W, length, gamma):
     """Features [247] of one fiber from the velocity field u[3][nz][ny][nx]
-    (fiber cells holding the rigid-body velocity), periodic in x, y."""
+    (fiber cells holding the rigid-body velocity), periodic in x, y:
+    relative velocities at X + s t + R(q) o (s in 0, L/2, -L/2; o in
+    {-2,0,2}^3), in the body frame, over gamma L; then q with w >= 0."""
     _, nz, ny, nx = u.shape
-    R = np.array([[1 - 2 * (q[2] ** 2 + q[3] ** 2)], [2 * (q[1] * q[2] + q[0] * q[3])],
-                  [2 * (q[1] * q[3] - q[0] * q[2])]]).ravel()
+    R = rotation(np.asarray(q, dtype=np.float64))
     out = np.zeros(247)
     L = float(length)
     for pt, side in enumerate((0.0, 0.5 * L, -0.5 * L)):
         for m in range(27):
-            ix, iy, iz = m % 3, (m // 3) % 3, m // 9
-            d = side * R + 2.0 * np.array([ix - 1, iy - 1, iz - 1])
+            ob = 2.0 * np.array([m % 3 - 1, (m // 3) % 3 - 1, m // 9 - 1])
+            d = side * R[:, 0] + R @ ob
             p = np.asarray(X, dtype=np.float64) + d
             pz = min(max(p[2], 0.0), nz - 1.0)
             x0, y0 = int(np.floor(p[0])), int(np.floor(p[1]))
@@ -126,7 +135,7 @@ def features(u, X, q, V, W, length, gamma):
                 val += wgt * u[:, z0 + cz, (y0 + cy) % ny, (x0 + cx) % nx]
             us = np.asarray(V) + np.cross(W, d)
             k = pt * 27 + m
-            out[3 * k:3 * k + 3] = (val - us) / (gamma * L)
+            out[3 * k:3 * k + 3] = R.T @ (val - us) / (gamma * L)
     qq = np.asarray(q, dtype=np.float64)
     out[243:] = -qq if qq[0] < 0 else qq
     return out

@@ -1,0 +1,316 @@
+"""Training and use of the learned force/torque closure (driver; every
+numeric step runs in the library's HIP kernels).
+
+Pairs of runs under diffusive scaling at fixed tau: a resolved fine case
+(fiber diameter 4) and its coarse twin (lattice spacing 2, diameter 2).  One
+coarse step is four fine steps; velocities scale by 2, angular velocities by
+4, forces by 1 and torques by 1/2 (lattice units).  The fine cases run free
+in one batched launch; their trajectories prescribe the coarse twins' motion
+(also one batched launch).  At every sampled coarse step the features of the
+coarse flow and the difference between the fine force (mean over the four
+fine steps) and the coarse momentum-exchange force form one training sample:
+
+    y[0..2] = (F_fine - F_coarse) / (rho0 nu gamma L^2)
+    y[3..5] = (M_fine / 2 - M_coarse) / (rho0 nu gamma L^3)
+
+with the coarse shear rate gamma, fiber length L and viscosity nu = (tau -
+1/2) / 3, rotated into the fiber's body frame R(q) like the features.  The
+network is trained on the GPU by the library's own forward, backward and
+Adam kernels.
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import lbm, scenarios
+
+NI, NO = lbm.MLP_IN, lbm.MLP_OUT
+
+
+def rotation(q):
+    """R(q) of a unit quaternion (w, x, y, z): columns are the body axes."""
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def coarse_of(x_fine):
+    """Coarse coordinate of a fine-lattice position (cell centres at integers)."""
+    return (np.asarray(x_fine, dtype=np.float64) - 0.5) / 2.0
+
+
+@dataclass
+class Pair:
+    fine: scenarios.Scenario
+    coarse: scenarios.Scenario
+    fine_traj: object = None      # prescribed fine motion [4T][13] or None (free)
+
+
+def rotation_traj(X, q0, W, steps):
+    """Rows [steps][13] of a fiber held at X turning at constant angular
+    velocity W: q_k = exp(k W / 2) (x) q0 after step k (k = 1..steps)."""
+    k = np.arange(1, steps + 1, dtype=np.float64)
+    w = np.linalg.norm(W)
+    ax = W / w if w > 0 else np.zeros(3)
+    h = 0.5 * w * k
+    dq = np.stack([np.cos(h), np.sin(h) * ax[0], np.sin(h) * ax[1], np.sin(h) * ax[2]], 1)
+    a0, a = dq[:, 0], dq[:, 1:]
+    b0, b = q0[0], np.asarray(q0[1:])
+    qn = np.concatenate([(a0 * b0 - a @ b)[:, None], a0[:, None] * b + b0 * a + np.cross(a, b)], 1)
+    qn /= np.linalg.norm(qn, axis=1, keepdims=True)
+    rows = np.zeros((steps, 13))
+    rows[:, 0:3] = X
+    rows[:, 3:7] = qn
+    rows[:, 10:13] = W
+    return rows
+
+
+def training_pairs(seed, n, n_coarse=32, ar=(2.0, 12.0), d_coarse=2.0, shear=(5e-4, 1.5e-3), tau=0.8,
+                   margin=8.0, prescribed=0.5, steps=2000):
+    """n fine/coarse pairs: one centred fiber per cubic cell (coarse edge
+    n_coarse, fine 2 n_coarse), orientation uniform on the sphere, aspect
+    ratio uniform in `ar` (redrawn until the coarse length fits with
+    `margin`), coarse shear rate uniform in `shear`.  A fraction
+    `prescribed` of the fine fibers turn at a constant angular velocity
+    with components uniform in +-gamma (fine units) instead of moving
+    freely, so that the data also cover rotation rates away from the free
+    motion; `steps` coarse steps are prescribed for them."""
+    g = scenarios.rng(seed)
+    out = []
+    nf = 2 * n_coarse
+    for _ in range(n):
+        while True:
+            a = g.uniform(*ar)
+            Lc = a * d_coarse
+            if Lc <= n_coarse - margin:
+                break
+        gc = g.uniform(*shear)
+        t = scenarios.axis_uniform_on_sphere(g)
+        q = scenarios.quat_from_axis(t)
+        Uc = gc * n_coarse / 2.0
+        Uf = Uc / 2.0
+        Xf = np.full(3, (nf - 1) / 2.0)
+        Vf, Wf = scenarios._initial_motion(Xf, Uf, nf)
+        traj = None
+        if g.uniform() < prescribed:
+            gf = 2.0 * Uf / nf
+            Wf = g.uniform(-gf, gf, 3)
+            Vf = np.zeros(3)
+            traj = rotation_traj(Xf, q, Wf, 4 * steps)
+        fine = scenarios.Scenario("fine", nf, nf, nf, tau, Uf,
+                                  [scenarios.Fiber(Xf, q, 2.0 * Lc, d_coarse, 1.0, Vf, Wf)], 0)
+        Xc = coarse_of(Xf)
+        coarse = scenarios.Scenario("coarse", n_coarse, n_coarse, n_coarse, tau, Uc,
+                                    [scenarios.Fiber(Xc, q, Lc, d_coarse / 2.0, 1.0, 2.0 * Vf, 4.0 * Wf)], 0)
+        out.append(Pair(fine, coarse, traj))
+    return out
+
+
+def fine_to_coarse_traj(h):
+    """Coarse prescribed rows [T][13] from fine history [4T][19] (state after
+    fine steps 4j+3, i.e. after coarse step j)."""
+    s = h[3::4]
+    X = coarse_of(s[:, 6:9])
+    return np.concatenate([X, s[:, 9:13], 2.0 * s[:, 13:16], 4.0 * s[:, 16:19]], axis=1)
+
+
+def generate(pairs, coarse_steps, sample_every, skip=100, stream=None, log=print):
+    """Run the pairs; returns features [N][247] taken at coarse steps skip,
+    skip + sample_every, ..., targets [N][6] (body frame, physical-
+    normalised) averaged over the sample_every steps that follow each
+    feature sample, case index [N], and the fine / coarse histories."""
+    nfine = 4 * coarse_steps
+    fb = lbm.Batch([p.fine for p in pairs], history_capacity=nfine, stream=stream)
+    fb.autotune(trial_steps=4)
+    for c, p in enumerate(pairs):
+        if p.fine_traj is not None:
+            fb.set_kinematics(c, p.fine_traj[:nfine])
+    fb.step(nfine)
+    fb.sync()
+    hf = [fb.history(c, 0, nfine) for c in range(len(pairs))]
+    fb.close()
+    log("fine runs done: %d cases x %d steps" % (len(pairs), nfine))
+    cb = lbm.Batch([p.coarse for p in pairs], history_capacity=coarse_steps, stream=stream)
+    for c in range(len(pairs)):
+        cb.set_kinematics(c, fine_to_coarse_traj(hf[c]))
+    cb.step(skip)
+    feats, steps = [], []
+    done = skip
+    while done + sample_every <= coarse_steps:
+        feats.append(cb.features())
+        steps.append(done)
+        cb.step(sample_every)
+        done += sample_every
+    cb.sync()
+    hc = [cb.history(c, 0, done) for c in range(len(pairs))]
+    cb.close()
+    X, Y, C = [], [], []
+    k = sample_every
+    for j, fe in zip(steps, feats):
+        for c, p in enumerate(pairs):
+            f = hf[c][4 * j:4 * (j + k)]
+            Ff = f[:, 0:3].mean(0)
+            Mf = f[:, 3:6].mean(0) / 2.0
+            Fc, Mc = hc[c][j:j + k, 0:3].mean(0), hc[c][j:j + k, 3:6].mean(0)
+            sc = p.coarse
+            L = sc.fibers[0].length
+            gamma = 2.0 * sc.wall_u / sc.nz
+            nu = (sc.tau - 0.5) / 3.0
+            sF = sc.rho0 * nu * gamma * L * L
+            Rq = rotation(fe[c][243:].astype(np.float64))     # targets in the body frame
+            X.append(fe[c])
+            Y.append(np.concatenate([Rq.T @ (Ff - Fc) / sF, Rq.T @ (Mf - Mc) / (sF * L)]))
+            C.append(c)
+    return (np.asarray(X, np.float32), np.asarray(Y, np.float64), np.asarray(C), hf, hc)
+
+
+@dataclass
+class Norm:
+    in_mean: np.ndarray
+    in_inv_std: np.ndarray
+    out_scale: np.ndarray
+    env_min: np.ndarray
+    env_max: np.ndarray
+
+
+def make_norm(X, Y, envelope_margin=0.1):
+    mean = X.mean(0)
+    std = X.std(0)
+    inv = 1.0 / np.maximum(std, 1e-6)
+    span = X.max(0) - X.min(0)
+    return Norm(mean.astype(np.float32), inv.astype(np.float32),
+                np.maximum(Y.std(0), 1e-12).astype(np.float32),
+                (X.min(0) - envelope_margin * span).astype(np.float32),
+                (X.max(0) + envelope_margin * span).astype(np.float32))
+
+
+def fit(X, Y, torch, epochs=60, batch=256, lr=1e-3, seed=0, norm=None, cases=None, val_frac=0.1, chunk=5):
+    """Train a fresh network on the GPU; returns (Mlp, Norm, loss per epoch).
+    With `cases` (case index per sample) a fraction val_frac of the cases is
+    held back and the parameters of the epoch with the lowest validation
+    error are kept (early stopping)."""
+    norm = norm or make_norm(X, Y)
+    m = lbm.Mlp(seed=seed)
+    m.set_norm(norm.in_mean, norm.in_inv_std, norm.out_scale, norm.env_min, norm.env_max)
+    val = np.zeros(X.shape[0], bool)
+    if cases is not None and val_frac > 0:
+        uc = np.unique(cases)
+        g = np.random.default_rng(seed)
+        held = g.choice(uc, max(1, int(round(val_frac * len(uc)))), replace=False)
+        val = np.isin(cases, held)
+    Xtr, Ytr = X[~val], Y[~val]
+    xd = torch.tensor(Xtr, dtype=torch.float32, device="cuda")
+    td = torch.tensor((Ytr / norm.out_scale).astype(np.float32), device="cuda")
+    if not val.any():
+        losses = m.train(xd.data_ptr(), td.data_ptr(), Xtr.shape[0], epochs, batch, lr, shuffle_seed=seed + 1)
+        return m, norm, losses
+    losses, best, best_w = [], np.inf, None
+    for k in range(0, epochs, chunk):
+        e = min(chunk, epochs - k)
+        losses.extend(m.train(xd.data_ptr(), td.data_ptr(), Xtr.shape[0], e, batch, lr, shuffle_seed=seed + 1 + k))
+        err = np.linalg.norm(Y[val] - predict(m, X[val], torch), axis=1).mean()
+        if err < best:
+            best, best_w = err, m.params()[0]
+    m.set_params(best_w)
+    return m, norm, np.asarray(losses)
+
+
+def predict(m, X, torch):
+    """Physical-normalised predictions y[N][6] for raw features X."""
+    xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    yd = torch.zeros((X.shape[0], NO), dtype=torch.float32, device="cuda")
+    m.forward(xd.data_ptr(), X.shape[0], yd.data_ptr())
+    return yd.cpu().numpy().astype(np.float64)
+
+
+def in_envelope(norm, X):
+    return np.all((X >= norm.env_min) & (X <= norm.env_max), axis=1)
+
+
+def relative_errors(Y, P):
+    """Mean over samples of |target - prediction| for force and torque
+    components, relative to the mean |target| (prediction 0 = no closure)."""
+    eF = np.linalg.norm(Y[:, 0:3] - P[:, 0:3], axis=1).mean()
+    eM = np.linalg.norm(Y[:, 3:6] - P[:, 3:6], axis=1).mean()
+    return eF, eM
+
+
+# ------------------------------------------------------------------ free tumbling runs
+def tumble_pair(seed=0, n_coarse=32, L_coarse=8.0, U_coarse=0.02, tau=0.8):
+    """A fine single-fiber shear cell (edge 2 n_coarse, diameter 4, length
+    2 L_coarse, wall speed U_coarse / 2) and its coarse twin; orientation
+    from the seed (uniform on the sphere, log-rolling draws redrawn)."""
+    fine0 = scenarios.single_fiber(seed=seed, n=2 * n_coarse, tau=tau, wall_u=U_coarse / 2.0,
+                                   length=2.0 * L_coarse, diameter=4.0)
+    ff = fine0.fibers[0]
+    Xc = coarse_of(ff.X)
+    coarse = scenarios.Scenario("coarse", n_coarse, n_coarse, n_coarse, tau, U_coarse,
+                                [scenarios.Fiber(Xc, ff.q, L_coarse, 1.0, 1.0, 2.0 * ff.V, 4.0 * ff.W)], 0)
+    return Pair(fine0, coarse)
+
+
+def run_free(sc, steps, mlp=None, chunk=20000, stream=None):
+    """Free run of a one-fiber scenario; returns the history [steps][19]
+    (with the closure attached when mlp is given) and closure counts."""
+    f = sc.fibers[0]
+    g = lbm.Context(sc.nx, sc.ny, sc.nz, tau=sc.tau, wall_u=sc.wall_u, init_couette=True,
+                    history_capacity=chunk, stream=stream)
+    g.add_fiber(f.X, f.q, f.length, f.radius, f.density_ratio, f.V, f.W)
+    if mlp is not None:
+        g.set_closure(mlp)
+    out = np.zeros((steps, 19))
+    done = 0
+    while done < steps:
+        k = min(chunk, steps - done)
+        g.step(k)
+        out[done:done + k] = g.history(done, k)[:, 0, :]
+        done += k
+    stats = g.closure_stats() if mlp is not None else (0, 0)
+    g.close()
+    return out, stats
+
+
+def save(path, mlp, norm):
+    w, _ = mlp.params()
+    np.savez(path, params=w, in_mean=norm.in_mean, in_inv_std=norm.in_inv_std, out_scale=norm.out_scale,
+             env_min=norm.env_min, env_max=norm.env_max)
+
+
+def load(path, stream=None):
+    d = np.load(path)
+    m = lbm.Mlp(seed=0, stream=stream)
+    m.set_params(d["params"])
+    norm = Norm(d["in_mean"], d["in_inv_std"], d["out_scale"], d["env_min"], d["env_max"])
+    m.set_norm(norm.in_mean, norm.in_inv_std, norm.out_scale, norm.env_min, norm.env_max)
+    return m, norm
+
+
+def main():
+    """Train a closure network and save it:
+    python -m paper_1503_06869_amd.closure OUT.npz [pairs] [coarse_steps]"""
+    import sys
+    import time
+
+    import torch
+
+    out = sys.argv[1]
+    npairs = int(sys.argv[2]) if len(sys.argv) > 2 else 512
+    steps = int(sys.argv[3]) if len(sys.argv) > 3 else 2000
+    lbm.load()
+    t0 = time.time()
+
+    def log(s):
+        print("%.1fs %s" % (time.time() - t0, s), flush=True)
+
+    X, Y, C, _, _ = generate(training_pairs(0, npairs, steps=steps), steps, 10, log=log)
+    Xt, Yt, _, _, _ = generate(training_pairs(1, 64, prescribed=0.0, steps=steps), steps, 10, log=log)
+    m, norm, losses = fit(X, Y, torch, epochs=40, cases=C)
+    e0, e1 = relative_errors(Yt, 0 * Yt), relative_errors(Yt, predict(m, Xt, torch))
+    log("samples %d, loss %.4f -> %.4f, held-out torque error %.4f -> %.4f" %
+        (X.shape[0], losses[0], losses[-1], e0[1], e1[1]))
+    save(out, m, norm)
+
+
+if __name__ == "__main__":
+    main()

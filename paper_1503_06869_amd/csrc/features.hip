@@ -1,8 +1,9 @@
 // features.hip -- the flow features of a fiber for the learned closure:
 // velocities relative to the fiber's rigid motion on a 3 x 27 stencil
-// (centre and both tips, offsets {-2,0,2}^3 cells), trilinear in the
-// cell-centre velocities, scaled by 1 / (gamma L), and the orientation.
-// One workgroup per fiber, one thread per stencil point.
+// (centre and both tips, offsets {-2,0,2}^3 cells along the body axes),
+// trilinear in the cell-centre velocities, expressed in the body frame and
+// scaled by 1 / (gamma L), and the orientation.  One workgroup per fiber,
+// one thread per stencil point.
 #include "lbm_sweep_dev.h"
 
 namespace lbm {
@@ -52,13 +53,18 @@ __global__ __launch_bounds__(128) void k_features(const S *__restrict__ f, const
     const PState s = ps[p];
     const double L = pc[p].length, vs = 1.0 / (gamma * L);
     float *o = out + size_t(p) * NFEAT;
+    // body frame: columns e0 = t (axis), e1 = R(q) e_y, e2 = R(q) e_z
+    const double w = s.q[0], qx = s.q[1], qy = s.q[2], qz = s.q[3];
+    const double Rm[3][3] = {{1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - w * qz), 2.0 * (qx * qz + w * qy)},
+                             {2.0 * (qx * qy + w * qz), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - w * qx)},
+                             {2.0 * (qx * qz - w * qy), 2.0 * (qy * qz + w * qx), 1.0 - 2.0 * (qx * qx + qy * qy)}};
     if (k < 81) {
         const int pt = k / 27, m = k % 27;
-        const int ix = m % 3, iy = (m / 3) % 3, iz = m / 9;
+        const double ob[3] = {2.0 * (m % 3 - 1), 2.0 * ((m / 3) % 3 - 1), 2.0 * (m / 9 - 1)};
         const double side = pt == 0 ? 0.0 : (pt == 1 ? 0.5 * L : -0.5 * L);
-        // offset from the centre of mass, then the sample position
-        const double d[3] = {side * s.t[0] + 2.0 * (ix - 1), side * s.t[1] + 2.0 * (iy - 1),
-                             side * s.t[2] + 2.0 * (iz - 1)};
+        // offset from the centre of mass (lab frame), then the sample position
+        double d[3];
+        for (int e = 0; e < 3; ++e) d[e] = side * Rm[e][0] + (Rm[e][0] * ob[0] + Rm[e][1] * ob[1] + Rm[e][2] * ob[2]);
         const double px = s.X[0] + d[0], py = s.X[1] + d[1];
         double pz = s.X[2] + d[2];
         const double zmax = double(g.nz) - 1.0;
@@ -71,18 +77,20 @@ __global__ __launch_bounds__(128) void k_features(const S *__restrict__ f, const
         double u[3] = {0.0, 0.0, 0.0};
         for (int c = 0; c < 8; ++c) {
             const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
-            const double w = (cx ? ax : 1.0 - ax) * (cy ? ay : 1.0 - ay) * (cz ? az : 1.0 - az);
+            const double wt = (cx ? ax : 1.0 - ax) * (cy ? ay : 1.0 - ay) * (cz ? az : 1.0 - az);
             int32_t xx = (x0 + cx) % int32_t(g.nx), yy = (y0 + cy) % int32_t(g.ny);
             xx += xx < 0 ? int32_t(g.nx) : 0;
             yy += yy < 0 ? int32_t(g.ny) : 0;
             double uc[3];
             cell_velocity<S>(f, flags, pid, ps, g, ph, swapped, uint32_t(xx), uint32_t(yy), uint32_t(z0 + cz), uc);
-            for (int e = 0; e < 3; ++e) u[e] += w * uc[e];
+            for (int e = 0; e < 3; ++e) u[e] += wt * uc[e];
         }
-        // rigid-body velocity at the sample position
-        const double us[3] = {s.V[0] + (s.W[1] * d[2] - s.W[2] * d[1]), s.V[1] + (s.W[2] * d[0] - s.W[0] * d[2]),
-                              s.V[2] + (s.W[0] * d[1] - s.W[1] * d[0])};
-        for (int e = 0; e < 3; ++e) o[k * 3 + e] = float((u[e] - us[e]) * vs);
+        // velocity relative to the rigid motion, in the body frame
+        const double v[3] = {u[0] - (s.V[0] + (s.W[1] * d[2] - s.W[2] * d[1])),
+                             u[1] - (s.V[1] + (s.W[2] * d[0] - s.W[0] * d[2])),
+                             u[2] - (s.V[2] + (s.W[0] * d[1] - s.W[1] * d[0]))};
+        for (int e = 0; e < 3; ++e)
+            o[k * 3 + e] = float((Rm[0][e] * v[0] + Rm[1][e] * v[1] + Rm[2][e] * v[2]) * vs);
     } else if (k < 85) {
         const double sg = s.q[0] < 0.0 ? -1.0 : 1.0;
         o[243 + (k - 81)] = float(sg * s.q[k - 81]);

@@ -288,9 +288,11 @@ __global__ void k_zero_d(double *p, int n)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0.0;
 }
 
-// Closure of a step: for each fiber, the network output in physical units,
-// or nothing when a raw feature lies outside the training envelope.
-//   corr[p][0..2] = y[0..2] rho0 nu gamma L^2,  corr[p][3..5] = y[3..5] rho0 nu gamma L^3
+// Closure of a step: for each fiber, the network output (body frame)
+// rotated to the lab frame and in physical units, or nothing when a raw
+// feature lies outside the training envelope:
+//   corr[p][0..2] = R(q) y[0..2] rho0 nu gamma L^2,  corr[p][3..5] = R(q) y[3..5] rho0 nu gamma L^3
+// (q: the orientation in features 243..246).
 __global__ void k_closure_apply(const float *__restrict__ feat, const float *__restrict__ y,
                                 const float *__restrict__ env_min, const float *__restrict__ env_max,
                                 const PConst *__restrict__ pc, int np, double rho0, double nu, double gamma,
@@ -307,9 +309,17 @@ __global__ void k_closure_apply(const float *__restrict__ feat, const float *__r
     }
     __syncthreads();
     if (threadIdx.x < NO) {
+        const int o = threadIdx.x, part = o / 3, row = o % 3;
+        const float *fq = feat + size_t(p) * NI + 243;
+        const double w = fq[0], qx = fq[1], qy = fq[2], qz = fq[3];
+        const double Rm[3][3] = {{1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - w * qz), 2.0 * (qx * qz + w * qy)},
+                                 {2.0 * (qx * qy + w * qz), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - w * qx)},
+                                 {2.0 * (qx * qz - w * qy), 2.0 * (qy * qz + w * qx), 1.0 - 2.0 * (qx * qx + qy * qy)}};
+        const float *yp = y + size_t(p) * NO + 3 * part;
         const double L = pc[p].length;
-        const double sF = rho0 * nu * gamma * L * L, sc = threadIdx.x < 3 ? sF : sF * L;
-        corr[size_t(p) * NO + threadIdx.x] = out ? 0.0 : double(y[size_t(p) * NO + threadIdx.x]) * sc;
+        const double sF = rho0 * nu * gamma * L * L, sc = part == 0 ? sF : sF * L;
+        const double lab = Rm[row][0] * yp[0] + Rm[row][1] * yp[1] + Rm[row][2] * yp[2];
+        corr[size_t(p) * NO + o] = out ? 0.0 : lab * sc;
     }
     if (threadIdx.x == 0) atomicAdd(&stats[out ? 1 : 0], 1ull);
 }

@@ -197,6 +197,20 @@ def batched_cases(seed=0, n_cases=512, edge=(24, 64), ar=(2.0, 10.0), diameter=4
     return cases
 
 
+def learned_coarse(seed=0, n=128, n_fibers=200, ar=(4.0, 12.0), diameter=2.0, wall_u=0.01, tau=0.8,
+                   steps=5000):
+    """Coarse shear cell of the learned form: under-resolved cylinders of
+    diameter 2, aspect ratio uniform in `ar`, placed as in many_fibers."""
+    g = rng(seed)
+    lengths = g.uniform(*ar, size=n_fibers) * diameter
+    radii = np.full(n_fibers, diameter / 2.0)
+    fibers = []
+    for X, t, L, r in place_fibers(g, n_fibers, (n, n, n), lengths, radii):
+        V, W = _initial_motion(X, wall_u, n)
+        fibers.append(Fiber(X, quat_from_axis(t), float(L), float(r), 1.0, V, W))
+    return Scenario("learned_coarse_%d" % n, n, n, n, tau, wall_u, fibers, steps)
+
+
 # ------------------------------------------------------------------ parity inputs
 def random_populations(seed, shape, weights, amplitude=1e-3, velocity=0.02):
     """Near-equilibrium random populations [19][nz][ny][nx] around rest

@@ -64,16 +64,24 @@ def test_features_of_linear_fields_are_exact():
     q /= np.linalg.norm(q)
     L, gamma = 6.0, 0.01
     f = R.features(u, X, q, np.zeros(3), np.zeros(3), L, gamma)
+    Rm = R.rotation(q)
+    # body axes: first column is the fiber axis R(q) e_x
     t = np.array([1 - 2 * (q[2] ** 2 + q[3] ** 2), 2 * (q[1] * q[2] + q[0] * q[3]), 2 * (q[1] * q[3] - q[0] * q[2])])
+    assert np.allclose(Rm[:, 0], t) and np.allclose(Rm.T @ Rm, np.eye(3))
     for pt, side in enumerate((0.0, 3.0, -3.0)):
         for m in range(27):
-            o = 2.0 * np.array([m % 3 - 1, (m // 3) % 3 - 1, m // 9 - 1])
-            p = X + side * t + o
+            ob = 2.0 * np.array([m % 3 - 1, (m // 3) % 3 - 1, m // 9 - 1])
+            p = X + side * t + Rm @ ob
             k = pt * 27 + m
-            assert np.allclose(f[3 * k:3 * k + 3], p / (gamma * L), atol=1e-12)
+            assert np.allclose(f[3 * k:3 * k + 3], Rm.T @ p / (gamma * L), atol=1e-12)
     assert np.allclose(f[243:], q)
-    # a rigid motion of the field is removed exactly
+    # a rigid motion of the field is removed exactly; q and -q are the same pose
     V, W = np.array([0.01, -0.02, 0.005]), np.array([1e-3, 2e-3, -1e-3])
     ur = V[:, None, None, None] + np.cross(W, (np.stack([x, y, z]) - X[:, None, None, None]), axis=0)
     f2 = R.features(ur, X, -q, V, W, L, gamma)
     assert np.abs(f2[:243]).max() < 1e-12 and np.allclose(f2[243:], q)
+    # a uniform flow a gives R^T (a - V) at every point when W = 0
+    a = np.array([0.02, 0.01, -0.03])
+    ua = np.broadcast_to(a[:, None, None, None], u.shape).copy()
+    f3 = R.features(ua, X, q, V, np.zeros(3), L, gamma)
+    assert np.allclose(f3[:243].reshape(81, 3), (Rm.T @ (a - V)) / (gamma * L), atol=1e-14)

@@ -141,7 +141,8 @@ def test_closure_step_matches_oracle_with_the_same_correction(torch):
         feat = _oracle_features(sc, o)
         y = R.forward(wr, (feat * 0.5)[None, :])[0] * 0.5
         sF = 1.0 * nu * gamma * L * L
-        o.set_correction(0, y[:3] * sF, y[3:] * sF * L)
+        Rq = R.rotation(feat[243:])           # body-frame output to the lab frame
+        o.set_correction(0, Rq @ y[:3] * sF, Rq @ y[3:] * sF * L)
         o.step(1)
     g.step(steps)
     hg, ho = g.history(0, steps), o.history(0, steps)

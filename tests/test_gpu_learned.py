@@ -1,0 +1,56 @@
+"""What the trained closure gains over the plain coarse method (GPU).
+
+The network in paper_1503_06869_amd/closure_net.npz was trained by
+`python -m paper_1503_06869_amd.closure` with the library's own kernels on
+512 pairs (resolved fine fiber, diameter 4, and its coarse twin, diameter
+2, under diffusive scaling; half of the fine fibers move freely, half turn
+at a prescribed random angular velocity) produced by the batched solver.
+Here it is judged on 64 held-out pairs (another seed, free fine motion):
+the mean torque error of the coarse momentum exchange against the fine
+torque must drop with the correction.  The free tumbling period of one
+fiber (fine, coarse, coarse + closure) is reported, not asserted: the
+closure does not yet bring the coarse period reliably closer to the fine
+one."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1503_06869_amd import closure, lbm
+
+pytestmark = pytest.mark.gpu
+
+NET = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1503_06869_amd",
+                   "closure_net.npz")
+
+
+def test_trained_closure_reduces_held_out_torque_error():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    lbm.load()
+    m, norm = closure.load(NET)
+    steps = 2000
+    Xt, Yt, _, _, _ = closure.generate(closure.training_pairs(1, 64, prescribed=0.0, steps=steps), steps, 10,
+                                       log=lambda s: None)
+    inside = closure.in_envelope(norm, Xt)
+    P = closure.predict(m, Xt, torch) * inside[:, None]
+    e0 = closure.relative_errors(Yt, 0 * Yt)
+    e1 = closure.relative_errors(Yt, P)
+    print("held-out samples %d (%.3f inside the envelope); torque error %.4f -> %.4f (x%.3f)" %
+          (Xt.shape[0], inside.mean(), e0[1], e1[1], e1[1] / e0[1]), flush=True)
+    assert e1[1] < 0.95 * e0[1]
+    # free tumbling of one fiber, reported
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import jeffery
+    pr = closure.tumble_pair(seed=0)
+    nc = 25000
+    res = {}
+    for name, sc, n, mlp in (("fine", pr.fine, 4 * nc, None), ("coarse", pr.coarse, nc, None),
+                             ("learned", pr.coarse, nc, m)):
+        h, stats = closure.run_free(sc, n, mlp=mlp)
+        T, _ = jeffery.period(jeffery.axis_from_quat(h[:, 9:13])[:, 0], min_crossings=3)
+        res[name] = T / (4.0 if name == "fine" else 1.0)
+    print("tumbling period in coarse steps: %s" % {k: round(v, 1) for k, v in res.items()}, flush=True)
+    m.close()
