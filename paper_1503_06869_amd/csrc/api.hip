@@ -180,6 +180,12 @@ static PartData part_data(lbm_ctx *c, PState *cur, PState *next)
     return pd;
 }
 
+// rho0 as the sweep's collision type holds it (float except for FP64 storage)
+static double link_rho0(const lbm_ctx *c)
+{
+    return c->sk == S_F64 ? c->p.rho0 : double(float(c->p.rho0));
+}
+
 static uint32_t grid_cap(uint64_t work, uint32_t lo, uint32_t hi)
 {
     uint64_t b = (work + 255) / 256;
@@ -291,8 +297,8 @@ static lbm_status check_device_errors(lbm_ctx *c)
 }
 
 // One time step as a two-branch graph of kernels:
-//   st : bulk sweep ----------------------------------------+--> near/list
-//   st2: boundary sweep -> momentum exchange -> rigid -> remap
+//   st : bulk sweep ------------------------------------------------+--> near/list
+//   st2: boundary sweep (F0, M0) -> A, B, C of the list -> rigid -> remap
 // The bulk sweep touches only slots of bulk cells; the boundary sweep, the
 // refill of the remap and the momentum exchange touch only slots and data
 // of cells next to fibers, so the branches are independent.  The flag and
@@ -340,6 +346,8 @@ static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hi
         e = launch_sweep(c->sk, odd, c->f, c->flags, c->g, c->ph, b, c->sweep_grid, c->bnd_grid, c->st,
                          c->st2, with_events ? e0 : nullptr, with_events ? e1 : nullptr);
     PartData pd = part_data(c, cur, next);
+    if (e == hipSuccess)
+        e = launch_abc(c->list_cell, c->list_mask, c->pid, pd, c->g, c->bpf, link_rho0(c), c->st2);
     if (e == hipSuccess) e = launch_rigid(pd, c->g, c->st2);
     if (e == hipSuccess) e = launch_remap(c->sk, !odd, c->f, c->pid, pd, c->g, c->p.rho0, c->scale, c->st2);
     if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->st2);

@@ -36,7 +36,6 @@
 namespace lbm {
 
 constexpr int BMAXP = 512;   // planes of a case (nz <= 512)
-constexpr int NABC = NACC - 6;
 
 struct CaseDev {
     Geo g;

@@ -82,6 +82,7 @@ constexpr int NBR_CAP = 128;   // neighbours per fiber whose boxes may intersect
 // restored once per step.  Scales leave ample range for fibers of
 // thousands of links: |F0| < 2^11, |M0| < 2^17, |A|,|B| < 2^23, |C| < 2^37.
 constexpr int NACC = 27;
+constexpr int NABC = NACC - 6;   // the population-free terms A, B, C
 __host__ __device__ constexpr int fx_shift(int k)
 {
     return k < 3 ? 52 : (k < 6 ? 46 : (k < 21 ? 40 : 26));
@@ -181,6 +182,10 @@ hipError_t launch_remap(int sk, bool next_odd, void *f, int32_t *pid, const Part
                         double rho0, double scale, hipStream_t st);
 hipError_t launch_near(uint8_t *flags, const int32_t *pid, uint32_t *list_cell, uint32_t *list_mask,
                        const PartData &pd, const Geo &g, hipStream_t st);
+// A, B, C sums of the current list at pd.ps_cur; r0: rho0 as the sweep's
+// collision type holds it (the link terms' k = 6 w rho0)
+hipError_t launch_abc(const uint32_t *list_cell, const uint32_t *list_mask, const int32_t *pid, const PartData &pd,
+                      const Geo &g, int bpf, double r0, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, size_t nbytes, hipStream_t st);
 
 // closure network (mlp.hip) and feature sampling (features.hip)

@@ -45,24 +45,24 @@ __global__ __launch_bounds__(256) void k_sweep_bnd(S *__restrict__ f, Geo g,
     const int p = blockIdx.x / b.bpf, j = blockIdx.x % b.bpf;
     const uint32_t cnt = b.seg_cnt[p], cap = b.seg_cap[p];
     const uint32_t n = cnt < cap ? cnt : cap, off = b.seg_off[p];
-    long long acc[NACC];
-#pragma unroll
-    for (int k = 0; k < NACC; ++k) acc[k] = 0;
+    // F0 and M0 only: the population-free sums A, B, C of the same links are
+    // formed when the list is built (k_near)
+    long long acc[6] = {0, 0, 0, 0, 0, 0};
     for (uint32_t r = j * 256u + threadIdx.x; r < n; r += b.bpf * 256u) {
         const uint32_t e = off + r;
-        update_cell<S, ODD, true>(f, g, ph, b.cell[e], b.mask[e], p, acc, b);
+        update_cell<S, ODD, true, 6>(f, g, ph, b.cell[e], b.mask[e], p, acc, b);
     }
     // integer sums: exact, so the reduction order does not matter
-    __shared__ long long red[4][NACC];
+    __shared__ long long red[4][6];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-    for (int k = 0; k < NACC; ++k) {
+    for (int k = 0; k < 6; ++k) {
         long long v = acc[k];
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
         if (lane == 0) red[wid][k] = v;
     }
     __syncthreads();
-    if (threadIdx.x < NACC) {
+    if (threadIdx.x < 6) {
         const int k = threadIdx.x;
         const long long v = red[0][k] + red[1][k] + red[2][k] + red[3][k];
         if (v) atomicAdd(reinterpret_cast<unsigned long long *>(b.mea + size_t(p) * NACC + k),
