@@ -174,15 +174,19 @@ class Norm:
     env_max: np.ndarray
 
 
-def make_norm(X, Y, envelope_margin=0.1):
+def make_norm(X, Y, envelope_margin=0.1, envelope_floor=0.05):
+    """Input normalisation, output scales and the training envelope: the
+    per-feature range widened by envelope_margin of its span plus
+    envelope_floor (features are O(0.1 .. 1); a feature that is always zero
+    in training, e.g. at a point inside the fiber, keeps a small band)."""
     mean = X.mean(0)
     std = X.std(0)
     inv = 1.0 / np.maximum(std, 1e-6)
     span = X.max(0) - X.min(0)
+    pad = envelope_margin * span + envelope_floor
     return Norm(mean.astype(np.float32), inv.astype(np.float32),
                 np.maximum(Y.std(0), 1e-12).astype(np.float32),
-                (X.min(0) - envelope_margin * span).astype(np.float32),
-                (X.max(0) + envelope_margin * span).astype(np.float32))
+                (X.min(0) - pad).astype(np.float32), (X.max(0) + pad).astype(np.float32))
 
 
 def fit(X, Y, torch, epochs=60, batch=256, lr=1e-3, seed=0, norm=None, cases=None, val_frac=0.1, chunk=5):
