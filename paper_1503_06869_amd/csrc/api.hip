@@ -38,7 +38,6 @@ struct lbm_ctx {
     long long *mea = nullptr;
     uint32_t *seg_off = nullptr, *seg_cap = nullptr, *seg_cnt = nullptr;
     int nslab = 4, bpf = 1;
-    int32_t *nbr = nullptr, *nbr_n = nullptr;
     double *traj = nullptr;
     int64_t *traj_pos = nullptr;
     double *ft = nullptr, *hist = nullptr;
@@ -56,8 +55,8 @@ struct lbm_ctx {
     std::vector<hipEvent_t> ev;
     bool own_stream = false;
     // second stream: boundary sweep and the particle chain run beside the bulk sweep
-    hipStream_t st2 = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipStream_t st2 = nullptr, st3 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_abc = nullptr;
     size_t ev_used = 0;
     int64_t timed_sweeps = 0;
     double timed_ms = 0.0;
@@ -109,8 +108,6 @@ static void free_particles(lbm_ctx *c)
     dfree(c->seg_off);
     dfree(c->seg_cap);
     dfree(c->seg_cnt);
-    dfree(c->nbr);
-    dfree(c->nbr_n);
     dfree(c->traj);
     dfree(c->traj_pos);
     dfree(c->ft);
@@ -165,8 +162,6 @@ static PartData part_data(lbm_ctx *c, PState *cur, PState *next)
     pd.seg_cap = c->seg_cap;
     pd.seg_cnt = c->seg_cnt;
     pd.nslab = c->nslab;
-    pd.nbr = c->nbr;
-    pd.nbr_n = c->nbr_n;
     pd.traj = c->traj;
     pd.traj_pos = c->traj_pos;
     pd.ft_out = c->ft;
@@ -214,8 +209,6 @@ static lbm_status upload_particles(lbm_ctx *c)
     HIPCHK(c, dalloc(c, &c->seg_cap, np));
     HIPCHK(c, dalloc(c, &c->seg_cnt, np));
     HIPCHK(c, hipMemsetAsync(c->seg_cnt, 0, np * sizeof(uint32_t), c->st));
-    HIPCHK(c, dalloc(c, &c->nbr, size_t(np) * NBR_CAP));
-    HIPCHK(c, dalloc(c, &c->nbr_n, np));
     HIPCHK(c, dalloc(c, &c->traj_pos, np));
     HIPCHK(c, dalloc(c, &c->ft, size_t(np) * 6));
     HIPCHK(c, dalloc(c, &c->hist, size_t(c->p.history_capacity) * np * 19));
@@ -296,12 +289,14 @@ static lbm_status check_device_errors(lbm_ctx *c)
     return LBM_OK;
 }
 
-// One time step as a two-branch graph of kernels:
+// One time step as a three-branch graph of kernels:
 //   st : bulk sweep ------------------------------------------------+--> near/list
-//   st2: boundary sweep (F0, M0) -> A, B, C of the list -> rigid -> remap
+//   st2: boundary sweep (F0, M0) --+--> rigid -> remap --------------+
+//   st3: A, B, C of the list ------+
 // The bulk sweep touches only slots of bulk cells; the boundary sweep, the
 // refill of the remap and the momentum exchange touch only slots and data
-// of cells next to fibers, so the branches are independent.  The flag and
+// of cells next to fibers, so the branches are independent; the sums A, B, C
+// read only the list, the cell owners and the poses.  The flag and
 // list rebuild reads and writes the flags the bulk sweep reads, so it waits
 // for both branches.
 static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hipEvent_t e0,
@@ -342,12 +337,15 @@ static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hi
     }
     if (e == hipSuccess) e = hipEventRecord(c->ev_fork, c->st);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->st2, c->ev_fork, 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->st3, c->ev_fork, 0);
     if (e == hipSuccess)
         e = launch_sweep(c->sk, odd, c->f, c->flags, c->g, c->ph, b, c->sweep_grid, c->bnd_grid, c->st,
                          c->st2, with_events ? e0 : nullptr, with_events ? e1 : nullptr);
     PartData pd = part_data(c, cur, next);
     if (e == hipSuccess)
-        e = launch_abc(c->list_cell, c->list_mask, c->pid, pd, c->g, c->bpf, link_rho0(c), c->st2);
+        e = launch_abc(c->list_cell, c->list_mask, c->pid, pd, c->g, c->bpf, link_rho0(c), c->st3);
+    if (e == hipSuccess) e = hipEventRecord(c->ev_abc, c->st3);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->st2, c->ev_abc, 0);
     if (e == hipSuccess) e = launch_rigid(pd, c->g, c->st2);
     if (e == hipSuccess) e = launch_remap(c->sk, !odd, c->f, c->pid, pd, c->g, c->p.rho0, c->scale, c->st2);
     if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->st2);
@@ -440,8 +438,10 @@ lbm_status lbm_create(const lbm_params *p, lbm_ctx **out)
         c->own_stream = true;
     }
     if (hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->st3, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_abc, hipEventDisableTiming) != hipSuccess) {
         lbm_destroy(c);
         return LBM_E_HIP;
     }
@@ -520,8 +520,10 @@ lbm_status lbm_destroy(lbm_ctx *c)
     dfree(c->pid);
     dfree(c->ctr);
     if (c->st2) hipStreamDestroy(c->st2);
+    if (c->st3) hipStreamDestroy(c->st3);
     if (c->ev_fork) hipEventDestroy(c->ev_fork);
     if (c->ev_join) hipEventDestroy(c->ev_join);
+    if (c->ev_abc) hipEventDestroy(c->ev_abc);
     if (c->own_stream) hipStreamDestroy(c->st);
     delete c;
     return LBM_OK;

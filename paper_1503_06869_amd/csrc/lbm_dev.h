@@ -90,7 +90,6 @@ __host__ __device__ constexpr int fx_shift(int k)
 
 // device-side counters and error flags
 struct DevCounters {
-    uint32_t block_ticket;     // "last block" ticket of the particle kernel
     uint32_t list_count;       // boundary-cell list length
     uint32_t err_unstable;     // non-finite F/M seen
     uint32_t err_capacity;     // list or neighbour capacity exceeded
@@ -139,8 +138,6 @@ struct PartData {
     PState *ps_cur, *ps_next;
     Box *box_cur;              // box of the current pose (read by the MEA, rewritten by the last block)
     Box *box_remap;            // old-and-new union boxes for the remap
-    int32_t *nbr;              // [np][NBR_CAP]
-    int32_t *nbr_n;            // [np]
     const double *traj;        // prescribed rows [.][13]
     int64_t *traj_pos;         // [np] rows consumed
     double *ft_out;            // [np][6] F, M of the step

@@ -28,57 +28,18 @@ __device__ __forceinline__ Rect remap_rect(const PartData &pd, int o, int32_t z,
 }
 
 // ------------------------------------------------------------------ boxes of the remap
-// Runs in one block: union of the box of the old pose (box_cur) and the new
-// pose (ps_next) per fiber, their cell-count prefix, and for every fiber the
-// ascending list of other fibers whose boxes meet its box.
-__device__ void build_remap_work(const PartData &pd, const Geo &g)
+// Union of the box of the old pose (box_cur) and the new pose s of fiber p,
+// the new box, and the reset of the fiber's boundary-list segment.
+__device__ __forceinline__ void fiber_remap_boxes(const PartData &pd, int p, const PState &s, const Geo &g)
 {
-    const int np = pd.np;
-    for (int p = threadIdx.x; p < np; p += blockDim.x) {
-        const PState s = pd.ps_next[p];   // visible: acquire fence by the caller
-        Box ub, nb;
-        remap_boxes(s, pd.pc[p], pd.box_cur[p], g, ub, nb);
-        pd.box_remap[p] = ub;
-        pd.box_cur[p] = nb;
-    }
-    __syncthreads();
-    for (int p = threadIdx.x; p < np; p += blockDim.x) pd.seg_cnt[p] = 0u;
-    // neighbour lists: the boxes are staged in LDS in chunks
-    __shared__ Box sbox[512];
-    for (int p0 = 0; p0 < np; p0 += blockDim.x) {
-    const int p = p0 + threadIdx.x;
-    const Box a = p < np ? pd.box_remap[p] : Box{};
-    int cnt = 0;
-    for (int o0 = 0; o0 < np; o0 += 512) {
-        const int no = min(512, np - o0);
-        __syncthreads();
-        for (int k = threadIdx.x; k < no; k += blockDim.x) sbox[k] = pd.box_remap[o0 + k];
-        __syncthreads();
-        if (p >= np) continue;
-        for (int oo = 0; oo < no; ++oo) {
-            const int o = o0 + oo;
-            if (o == p) continue;
-            if (!boxes_meet(a, sbox[oo], g)) continue;
-            if (cnt < NBR_CAP) pd.nbr[p * NBR_CAP + cnt] = o;
-            ++cnt;
-        }
-    }
-    if (p < np) {
-        if (cnt > NBR_CAP) {
-            atomicOr(&pd.ctr->err_capacity, 1u);
-            cnt = NBR_CAP;
-        }
-        pd.nbr_n[p] = cnt;
-    }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        pd.ctr->block_ticket = 0u;
-    }
+    Box ub, nb;
+    remap_boxes(s, pd.pc[p], pd.box_cur[p], g, ub, nb);
+    pd.box_remap[p] = ub;
+    pd.box_cur[p] = nb;
+    pd.seg_cnt[p] = 0u;
 }
 
-// end of a time step: advance the device step counter (last block only)
+// end of a time step: advance the device step counter
 __device__ void finish_step(const PartData &pd)
 {
     if (threadIdx.x == 0) pd.ctr->step += 1ull;
@@ -86,13 +47,14 @@ __device__ void finish_step(const PartData &pd)
 
 __global__ __launch_bounds__(256) void k_setup_boxes(PartData pd, Geo g)
 {
-    build_remap_work(pd, g);
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < pd.np; p += gridDim.x * blockDim.x)
+        fiber_remap_boxes(pd, p, pd.ps_next[p], g);
 }
 
 // ------------------------------------------------------------------ rigid update kernel
 // One block: the momentum-exchange sums of every fiber (accumulated in fixed
 // point by the boundary sweep) back to FP64, the rigid-body update, outputs,
-// then the boxes and neighbour lists of the remap and the list reset.
+// the boxes of the remap and the list reset.
 __global__ __launch_bounds__(256) void k_rigid(PartData pd, Geo g)
 {
     extern __shared__ double tot[];   // [np][NACC]
@@ -121,6 +83,7 @@ __global__ __launch_bounds__(256) void k_rigid(PartData pd, Geo g)
         for (int k = 0; k < 3; ++k) bad |= !isfinite(F[k]) || !isfinite(M[k]);
         if (bad) atomicOr(&pd.ctr->err_unstable, 1u);
         pd.ps_next[p] = o;
+        fiber_remap_boxes(pd, p, o, g);
         for (int k = 0; k < 3; ++k) {
             pd.ft_out[p * 6 + k] = F[k];
             pd.ft_out[p * 6 + 3 + k] = M[k];
@@ -130,8 +93,7 @@ __global__ __launch_bounds__(256) void k_rigid(PartData pd, Geo g)
         for (int k = 0; k < 4; ++k) h[9 + k] = o.q[k];
         for (int k = 0; k < 3; ++k) { h[13 + k] = o.V[k]; h[16 + k] = o.W[k]; }
     }
-    __syncthreads();
-    build_remap_work(pd, g);
+    __syncthreads();   // every thread has read the step counter
     finish_step(pd);
 }
 
@@ -148,19 +110,49 @@ struct NbrStage {
     int32_t n, nlow;
 };
 
-__device__ __forceinline__ void stage_nbrs(const PartData &pd, int p, NbrStage &sh)
+// The fibers whose remap boxes meet fiber p's, in ascending order: every
+// block scans all boxes (one per thread and pass) and compacts the hits in
+// thread order, so all blocks of the step form the same list.
+__device__ __forceinline__ void stage_nbrs(const PartData &pd, int p, NbrStage &sh, const Geo &g)
 {
-    const int nn = pd.nbr_n[p];
-    for (int k = threadIdx.x; k < nn; k += blockDim.x) {
-        const int o = pd.nbr[p * NBR_CAP + k];
-        sh.id[k] = o;
-        sh.box[k] = pd.box_remap[o];
-    }
+    __shared__ uint32_t s_wc[4], s_low;
+    const Box a = pd.box_remap[p];
     if (threadIdx.x == 0) {
-        int nl = 0;
-        while (nl < nn && pd.nbr[p * NBR_CAP + nl] < p) ++nl;   // ascending ids
-        sh.n = nn;
-        sh.nlow = nl;
+        sh.n = 0;
+        s_low = 0u;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int o0 = 0; o0 < pd.np; o0 += blockDim.x) {   // block-uniform
+        const int o = o0 + int(threadIdx.x);
+        Box bo{};
+        bool hit = false;
+        if (o < pd.np && o != p) {
+            bo = pd.box_remap[o];
+            hit = boxes_meet(a, bo, g);
+        }
+        const unsigned long long bal = __ballot(hit);
+        if (lane == 0) s_wc[wid] = uint32_t(__popcll(bal));
+        __syncthreads();
+        uint32_t k = uint32_t(sh.n) + uint32_t(__popcll(bal & ((1ull << lane) - 1ull)));
+        for (int w = 0; w < wid; ++w) k += s_wc[w];
+        const uint32_t pass = s_wc[0] + s_wc[1] + s_wc[2] + s_wc[3];   // read before the next pass writes
+        if (hit) {
+            if (k < uint32_t(NBR_CAP)) {
+                sh.id[k] = o;
+                sh.box[k] = bo;
+            }
+            if (o < p) atomicAdd(&s_low, 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) sh.n += int32_t(pass);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (sh.n > NBR_CAP) {
+            atomicOr(&pd.ctr->err_capacity, 1u);
+            sh.n = NBR_CAP;
+        }
+        sh.nlow = min(int32_t(s_low), sh.n);
     }
     __syncthreads();
 }
@@ -193,7 +185,7 @@ __global__ __launch_bounds__(256) void k_remap(S *__restrict__ f, int32_t *__res
     const int ns = pd.nslab;
     const int p = blockIdx.x / ns, sl = blockIdx.x % ns;
     __shared__ NbrStage sh;
-    stage_nbrs(pd, p, sh);
+    stage_nbrs(pd, p, sh, g);
     const Box b = pd.box_remap[p];
     const PState sp = pd.ps_next[p];
     const PConst cp = pd.pc[p];
@@ -287,7 +279,7 @@ __global__ __launch_bounds__(256) void k_near(uint8_t *__restrict__ flags, const
     __shared__ NbrStage sh;
     __shared__ uint32_t s_cell[LSTAGE], s_mask[LSTAGE];
     __shared__ uint32_t s_n, s_base;
-    stage_nbrs(pd, p, sh);
+    stage_nbrs(pd, p, sh, g);
     if (threadIdx.x == 0) s_n = 0u;
     __syncthreads();
     const Box b = pd.box_remap[p];
@@ -404,7 +396,7 @@ hipError_t launch_rigid(const PartData &pd, const Geo &g, hipStream_t st)
 
 hipError_t launch_setup_boxes(const PartData &pd, const Geo &g, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_setup_boxes, dim3(1), dim3(256), 0, st, pd, g);
+    hipLaunchKernelGGL(k_setup_boxes, dim3((pd.np + 255) / 256), dim3(256), 0, st, pd, g);
     return hipGetLastError();
 }
 
