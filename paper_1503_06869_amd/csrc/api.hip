@@ -25,7 +25,9 @@ struct lbm_ctx {
     double scale = 1.0;
     // lattice
     void *f = nullptr;
-    uint8_t *flags = nullptr;
+    // cell flags of the even and odd steps: step n reads flags[n & 1] and
+    // writes those of step n + 1 into the other buffer
+    uint8_t *flags[2] = {nullptr, nullptr};
     int32_t *pid = nullptr;
     // particles
     int np = 0;
@@ -34,7 +36,8 @@ struct lbm_ctx {
     std::vector<std::vector<double>> traj_h;
     PState *ps[2] = {nullptr, nullptr};
     PConst *pc = nullptr;
-    Box *box_cur = nullptr, *box_remap = nullptr;
+    Box *box_cur = nullptr, *box_prev = nullptr, *box_remap = nullptr;
+    PState *ps_prev = nullptr;
     long long *mea = nullptr;
     uint32_t *seg_off = nullptr, *seg_cap = nullptr, *seg_cnt = nullptr;
     int nslab = 4, bpf = 1;
@@ -103,7 +106,9 @@ static void free_particles(lbm_ctx *c)
     dfree(c->ps[1]);
     dfree(c->pc);
     dfree(c->box_cur);
+    dfree(c->box_prev);
     dfree(c->box_remap);
+    dfree(c->ps_prev);
     dfree(c->mea);
     dfree(c->seg_off);
     dfree(c->seg_cap);
@@ -155,7 +160,9 @@ static PartData part_data(lbm_ctx *c, PState *cur, PState *next)
     pd.pc = c->pc;
     pd.ps_cur = cur;
     pd.ps_next = next;
+    pd.ps_prev = c->ps_prev;
     pd.box_cur = c->box_cur;
+    pd.box_prev = c->box_prev;
     pd.box_remap = c->box_remap;
     pd.mea = c->mea;
     pd.seg_off = c->seg_off;
@@ -199,7 +206,9 @@ static lbm_status upload_particles(lbm_ctx *c)
     HIPCHK(c, dalloc(c, &c->ps[0], np));
     HIPCHK(c, dalloc(c, &c->ps[1], np));
     HIPCHK(c, dalloc(c, &c->pc, np));
+    HIPCHK(c, dalloc(c, &c->ps_prev, np));
     HIPCHK(c, dalloc(c, &c->box_cur, np));
+    HIPCHK(c, dalloc(c, &c->box_prev, np));
     HIPCHK(c, dalloc(c, &c->box_remap, np));
     // blocks per fiber for the momentum exchange, remap and list kernels
     c->nslab = std::max(4, std::min(32, 2048 / np));
@@ -272,7 +281,14 @@ static lbm_status setup_mapping(lbm_ctx *c, PState *old_states)
     HIPCHK(c, launch_setup_boxes(pd, c->g, c->st));
     HIPCHK(c, launch_remap(c->sk, (c->steps & 1) != 0, c->f, c->pid, pd, c->g, c->p.rho0, c->scale,
                            c->st));
-    HIPCHK(c, launch_near(c->flags, c->pid, c->list_cell, c->list_mask, pd, c->g, c->st));
+    const int s = int(c->steps & 1);
+    HIPCHK(c, launch_near(c->flags[s], c->pid, c->list_cell, c->list_mask, pd, c->g, c->st));
+    // the other flag buffer and pose buffer start as copies of the current
+    // ones: the first step writes its successor flags over the region of
+    // this pose, which then covers every flag the buffer holds
+    HIPCHK(c, hipMemcpyAsync(c->flags[s ^ 1], c->flags[s], c->g.ncell, hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->ps[s ^ 1], c->ps[s], size_t(c->np) * sizeof(PState), hipMemcpyDeviceToDevice,
+                             c->st));
     return LBM_OK;
 }
 
@@ -290,15 +306,17 @@ static lbm_status check_device_errors(lbm_ctx *c)
 }
 
 // One time step as a three-branch graph of kernels:
-//   st : bulk sweep ------------------------------------------------+--> near/list
-//   st2: boundary sweep (F0, M0) --+--> rigid -> remap --------------+
+//   st : bulk sweep ------------------------------------------------------+
+//   st2: boundary sweep (F0, M0) --+--> rigid -> remap -> near/list ------+--> next step
 //   st3: A, B, C of the list ------+
 // The bulk sweep touches only slots of bulk cells; the boundary sweep, the
 // refill of the remap and the momentum exchange touch only slots and data
 // of cells next to fibers, so the branches are independent; the sums A, B, C
-// read only the list, the cell owners and the poses.  The flag and
-// list rebuild reads and writes the flags the bulk sweep reads, so it waits
-// for both branches.
+// read only the list, the cell owners and the poses.  The bulk sweep of step
+// n reads flags[n & 1]; the flag and list rebuild writes the flags of step
+// n + 1 into flags[(n + 1) & 1], over the remap region of the previous,
+// current and new poses, which holds every cell whose flag differs between
+// steps n - 1 and n + 1, so it runs beside the bulk sweep.
 static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hipEvent_t e0,
                             hipEvent_t e1, hipError_t *err)
 {
@@ -318,7 +336,7 @@ static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hi
     b.ctr = c->ctr;
     hipError_t e = hipSuccess;
     if (!c->np) {
-        e = launch_sweep(c->sk, odd, c->f, c->flags, c->g, c->ph, b, c->sweep_grid, 0, c->st, c->st,
+        e = launch_sweep(c->sk, odd, c->f, c->flags[step_index & 1], c->g, c->ph, b, c->sweep_grid, 0, c->st, c->st,
                          with_events ? e0 : nullptr, with_events ? e1 : nullptr);
         if (e != hipSuccess && *err == hipSuccess) *err = e;
         return;
@@ -328,7 +346,8 @@ static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hi
         // corrections for the rigid-body update of this step
         const MlpDev md = mlp_device_view(c->closure);
         const double gamma = 2.0 * c->p.wall_u / c->p.nz, nu = (c->p.tau - 0.5) / 3.0;
-        e = launch_sample_features(c->sk, odd, c->f, c->flags, c->pid, cur, c->pc, c->np, c->g, c->ph, gamma,
+        e = launch_sample_features(c->sk, odd, c->f, c->flags[step_index & 1], c->pid, cur, c->pc, c->np, c->g,
+                                   c->ph, gamma,
                                    c->feat, c->st);
         if (e == hipSuccess) e = launch_mlp_forward(md, c->feat, c->np, c->cy, c->st);
         if (e == hipSuccess)
@@ -339,7 +358,8 @@ static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hi
     if (e == hipSuccess) e = hipStreamWaitEvent(c->st2, c->ev_fork, 0);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->st3, c->ev_fork, 0);
     if (e == hipSuccess)
-        e = launch_sweep(c->sk, odd, c->f, c->flags, c->g, c->ph, b, c->sweep_grid, c->bnd_grid, c->st,
+        e = launch_sweep(c->sk, odd, c->f, c->flags[step_index & 1], c->g, c->ph, b, c->sweep_grid, c->bnd_grid,
+                         c->st,
                          c->st2, with_events ? e0 : nullptr, with_events ? e1 : nullptr);
     PartData pd = part_data(c, cur, next);
     if (e == hipSuccess)
@@ -348,10 +368,10 @@ static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hi
     if (e == hipSuccess) e = hipStreamWaitEvent(c->st2, c->ev_abc, 0);
     if (e == hipSuccess) e = launch_rigid(pd, c->g, c->st2);
     if (e == hipSuccess) e = launch_remap(c->sk, !odd, c->f, c->pid, pd, c->g, c->p.rho0, c->scale, c->st2);
+    if (e == hipSuccess)
+        e = launch_near(c->flags[(step_index + 1) & 1], c->pid, c->list_cell, c->list_mask, pd, c->g, c->st2);
     if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->st2);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->st, c->ev_join, 0);
-    if (e == hipSuccess)
-        e = launch_near(c->flags, c->pid, c->list_cell, c->list_mask, pd, c->g, c->st);
     if (e != hipSuccess && *err == hipSuccess) *err = e;
 }
 
@@ -488,10 +508,12 @@ lbm_status lbm_create(const lbm_params *p, lbm_ctx **out)
     };
     if (hipMalloc(&c->f, size_t(Q) * g.qstride * c->esz) != hipSuccess) return bail(LBM_E_NOMEM, "f");
     c->device_bytes += int64_t(size_t(Q) * g.qstride * c->esz);
-    if (dalloc(c, &c->flags, g.ncell) != hipSuccess || dalloc(c, &c->pid, g.ncell) != hipSuccess ||
+    if (dalloc(c, &c->flags[0], g.ncell) != hipSuccess || dalloc(c, &c->flags[1], g.ncell) != hipSuccess ||
+        dalloc(c, &c->pid, g.ncell) != hipSuccess ||
         dalloc(c, &c->ctr, 1) != hipSuccess)
         return bail(LBM_E_NOMEM, "fields");
-    if (hipMemsetAsync(c->flags, 0, g.ncell, c->st) != hipSuccess ||
+    if (hipMemsetAsync(c->flags[0], 0, g.ncell, c->st) != hipSuccess ||
+        hipMemsetAsync(c->flags[1], 0, g.ncell, c->st) != hipSuccess ||
         hipMemsetAsync(c->pid, 0xFF, size_t(g.ncell) * 4, c->st) != hipSuccess ||
         hipMemsetAsync(c->ctr, 0, sizeof(DevCounters), c->st) != hipSuccess)
         return bail(LBM_E_HIP, "memset");
@@ -516,7 +538,8 @@ lbm_status lbm_destroy(lbm_ctx *c)
     dfree(c->corr);
     dfree(c->cstats);
     dfree(c->f);
-    dfree(c->flags);
+    dfree(c->flags[0]);
+    dfree(c->flags[1]);
     dfree(c->pid);
     dfree(c->ctr);
     if (c->st2) hipStreamDestroy(c->st2);
@@ -582,7 +605,8 @@ lbm_status lbm_add_fiber(lbm_ctx *c, const lbm_fiber *f, int32_t *id)
         c->pch.pop_back();
         c->traj_h.pop_back();
         c->np--;
-        hipMemsetAsync(c->flags, 0, c->g.ncell, c->st);
+        hipMemsetAsync(c->flags[0], 0, c->g.ncell, c->st);
+        hipMemsetAsync(c->flags[1], 0, c->g.ncell, c->st);
         hipMemsetAsync(c->pid, 0xFF, size_t(c->g.ncell) * 4, c->st);
         hipMemsetAsync(c->ctr, 0, sizeof(DevCounters), c->st);
         lbm_status s2 = upload_particles(c);
@@ -715,7 +739,7 @@ lbm_status lbm_get_fields(lbm_ctx *c, void *rho, void *u, uint8_t *flags, int32_
     }
     PState *cur = c->np ? c->ps[c->steps & 1] : nullptr;
     if (rho || u)
-        HIPCHK(c, launch_decode(c->sk, (c->steps & 1) != 0, c->f, c->flags, c->pid, cur, c->g, c->ph,
+        HIPCHK(c, launch_decode(c->sk, (c->steps & 1) != 0, c->f, c->flags[c->steps & 1], c->pid, cur, c->g, c->ph,
                                 drho, du, nullptr, c->st));
     const hipMemcpyKind k = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (rho && !dst_is_device) HIPCHK(c, hipMemcpyAsync(rho, drho, n * rsz, k, c->st));
@@ -723,7 +747,7 @@ lbm_status lbm_get_fields(lbm_ctx *c, void *rho, void *u, uint8_t *flags, int32_
     if (flags) {
         // logical flags: 0 fluid, 1 fiber (the near-boundary bit is internal)
         std::vector<uint8_t> hf(n);
-        HIPCHK(c, hipMemcpyAsync(hf.data(), c->flags, n, hipMemcpyDeviceToHost, c->st));
+        HIPCHK(c, hipMemcpyAsync(hf.data(), c->flags[c->steps & 1], n, hipMemcpyDeviceToHost, c->st));
         HIPCHK(c, hipStreamSynchronize(c->st));
         for (auto &v : hf) v &= F_SOLID;
         HIPCHK(c, hipMemcpyAsync(flags, hf.data(), n, dst_is_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost, c->st));
@@ -810,7 +834,7 @@ lbm_status lbm_get_populations(lbm_ctx *c, double *f)
     const size_t n = size_t(Q) * c->g.ncell;
     HIPCHK(c, hipMalloc(&d, n * sizeof(double)));
     PState *cur = c->np ? c->ps[c->steps & 1] : nullptr;
-    hipError_t e = launch_decode(c->sk, (c->steps & 1) != 0, c->f, c->flags, c->pid, cur, c->g, c->ph,
+    hipError_t e = launch_decode(c->sk, (c->steps & 1) != 0, c->f, c->flags[c->steps & 1], c->pid, cur, c->g, c->ph,
                                  nullptr, nullptr, d, c->st);
     if (e == hipSuccess) e = hipMemcpyAsync(f, d, n * sizeof(double), hipMemcpyDeviceToHost, c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
@@ -932,7 +956,7 @@ lbm_status lbm_sample_features(lbm_ctx *c, float *out, int32_t dst_is_device)
     float *d = out;
     if (!dst_is_device) HIPCHK(c, hipMalloc(&d, n * sizeof(float)));
     const double gamma = 2.0 * c->p.wall_u / c->p.nz;
-    hipError_t e = launch_sample_features(c->sk, (c->steps & 1) != 0, c->f, c->flags, c->pid, c->ps[c->steps & 1],
+    hipError_t e = launch_sample_features(c->sk, (c->steps & 1) != 0, c->f, c->flags[c->steps & 1], c->pid, c->ps[c->steps & 1],
                                           c->pc, c->np, c->g, c->ph, gamma, d, c->st);
     if (e == hipSuccess && !dst_is_device) e = hipMemcpyAsync(out, d, n * sizeof(float), hipMemcpyDeviceToHost, c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);

@@ -136,8 +136,10 @@ struct PartData {
     int32_t np;
     const PConst *pc;
     PState *ps_cur, *ps_next;
-    Box *box_cur;              // box of the current pose (read by the MEA, rewritten by the last block)
-    Box *box_remap;            // old-and-new union boxes for the remap
+    PState *ps_prev;           // pose of the previous step (saved by the rigid update)
+    Box *box_cur;              // box of the current pose
+    Box *box_prev;             // box of the previous pose
+    Box *box_remap;            // union of the boxes of the previous, current and new poses
     const double *traj;        // prescribed rows [.][13]
     int64_t *traj_pos;         // [np] rows consumed
     double *ft_out;            // [np][6] F, M of the step

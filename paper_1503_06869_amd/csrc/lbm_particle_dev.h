@@ -375,10 +375,10 @@ __device__ __forceinline__ void rigid_update(const PState &s, const PConst &c, c
 }
 
 // Boxes of the remap of one fiber: nb = box of the new pose s, ub = union of
-// nb with the box of the old pose (old.len[0] == 0: no old pose), the old
-// interval moved by whole periods next to the new one where periodic.
-__device__ __forceinline__ void remap_boxes(const PState &s, const PConst &c, const Box &old, const Geo &g,
-                                            Box &ub, Box &nb)
+// nb with the boxes of older poses (a box with len[0] == 0 is absent), each
+// old interval moved by whole periods next to the new one where periodic.
+__device__ __forceinline__ void remap_boxes(const PState &s, const PConst &c, const Box &old, const Box &older,
+                                            const Geo &g, Box &ub, Box &nb)
 {
     double Xref[3];
     for (int k = 0; k < 3; ++k) Xref[k] = s.X[k];
@@ -386,23 +386,32 @@ __device__ __forceinline__ void remap_boxes(const PState &s, const PConst &c, co
     fiber_box(s, c, g, Xref, lo, hi);
     int32_t lo2[3] = {lo[0], lo[1], lo[2]}, hi2[3] = {hi[0], hi[1], hi[2]};
     finish_box(lo2, hi2, g, nb);
-    if (old.len[0] > 0) {
-        const int32_t n[3] = {int32_t(g.nx), int32_t(g.ny), int32_t(g.nz)};
+    const int32_t n[3] = {int32_t(g.nx), int32_t(g.ny), int32_t(g.nz)};
+    int32_t mid_new[3];
+    for (int k = 0; k < 3; ++k) mid_new[k] = (lo[k] + hi[k]) / 2;
+    const Box *olds[2] = {&old, &older};
+    for (int j = 0; j < 2; ++j) {
+        const Box &ob = *olds[j];
+        if (ob.len[0] <= 0) continue;
         for (int k = 0; k < 3; ++k) {
             const bool per = k < 2 || g.zper;
-            int32_t olo = old.lo[k];
+            int32_t olo = ob.lo[k];
             if (per) {
-                const int32_t mid_new = (lo[k] + hi[k]) / 2;
-                const int32_t mid_old = olo + old.len[k] / 2;
-                int32_t sh = mid_new - mid_old;
+                const int32_t mid_old = olo + ob.len[k] / 2;
+                int32_t sh = mid_new[k] - mid_old;
                 sh = int32_t(floor(double(sh) / n[k] + 0.5)) * n[k];
                 olo += sh;
             }
             lo[k] = min(lo[k], olo);
-            hi[k] = max(hi[k], olo + old.len[k] - 1);
+            hi[k] = max(hi[k], olo + ob.len[k] - 1);
         }
     }
     finish_box(lo, hi, g, ub);
+}
+__device__ __forceinline__ void remap_boxes(const PState &s, const PConst &c, const Box &old, const Geo &g,
+                                            Box &ub, Box &nb)
+{
+    remap_boxes(s, c, old, Box{{0, 0, 0}, {0, 0, 0}}, g, ub, nb);
 }
 
 // neighbour mask of cell (x, y, z): bit q set when x + c_q is a fiber cell

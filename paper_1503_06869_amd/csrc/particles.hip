@@ -19,22 +19,30 @@ namespace lbm {
 
 #pragma clang fp contract(off)
 
-// plane rectangle of fiber o's remap region: both poses of the step
+// Plane rectangle of fiber o's remap region: the current and new poses
+// (where cell owners can change), and with PREV also the previous pose (the
+// flags of the next step are written into the buffer that held those of the
+// previous step, so the flag rebuild covers every cell flagged then).
+template <bool PREV>
 __device__ __forceinline__ Rect remap_rect(const PartData &pd, int o, int32_t z, const Geo &g)
 {
     const Box b = pd.box_remap[o];
     const PConst c = pd.pc[o];
-    return rect_union(plane_rect(pd.ps_cur[o], c, z, b, g), plane_rect(pd.ps_next[o], c, z, b, g), g);
+    const Rect r = rect_union(plane_rect(pd.ps_cur[o], c, z, b, g), plane_rect(pd.ps_next[o], c, z, b, g), g);
+    return PREV ? rect_union(r, plane_rect(pd.ps_prev[o], c, z, b, g), g) : r;
 }
 
 // ------------------------------------------------------------------ boxes of the remap
-// Union of the box of the old pose (box_cur) and the new pose s of fiber p,
-// the new box, and the reset of the fiber's boundary-list segment.
+// Union of the boxes of the previous (box_prev), current (box_cur) and new
+// pose s of fiber p, the new box, and the reset of the fiber's boundary-list
+// segment.
 __device__ __forceinline__ void fiber_remap_boxes(const PartData &pd, int p, const PState &s, const Geo &g)
 {
     Box ub, nb;
-    remap_boxes(s, pd.pc[p], pd.box_cur[p], g, ub, nb);
+    const Box bc = pd.box_cur[p];
+    remap_boxes(s, pd.pc[p], bc, pd.box_prev[p], g, ub, nb);
     pd.box_remap[p] = ub;
+    pd.box_prev[p] = bc;
     pd.box_cur[p] = nb;
     pd.seg_cnt[p] = 0u;
 }
@@ -45,10 +53,15 @@ __device__ void finish_step(const PartData &pd)
     if (threadIdx.x == 0) pd.ctr->step += 1ull;
 }
 
+// Set-up of the mapping from ps_cur (old poses, or the current ones) to
+// ps_next: the previous pose is taken equal to the old one.
 __global__ __launch_bounds__(256) void k_setup_boxes(PartData pd, Geo g)
 {
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < pd.np; p += gridDim.x * blockDim.x)
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < pd.np; p += gridDim.x * blockDim.x) {
+        pd.ps_prev[p] = pd.ps_cur[p];
+        pd.box_prev[p] = pd.box_cur[p];
         fiber_remap_boxes(pd, p, pd.ps_next[p], g);
+    }
 }
 
 // ------------------------------------------------------------------ rigid update kernel
@@ -82,6 +95,7 @@ __global__ __launch_bounds__(256) void k_rigid(PartData pd, Geo g)
         bool bad = false;
         for (int k = 0; k < 3; ++k) bad |= !isfinite(F[k]) || !isfinite(M[k]);
         if (bad) atomicOr(&pd.ctr->err_unstable, 1u);
+        pd.ps_prev[p] = pd.ps_next[p];   // the pose of the previous step, about to be overwritten
         pd.ps_next[p] = o;
         fiber_remap_boxes(pd, p, o, g);
         for (int k = 0; k < 3; ++k) {
@@ -158,13 +172,14 @@ __device__ __forceinline__ void stage_nbrs(const PartData &pd, int p, NbrStage &
 }
 
 // rectangles of the lower-indexed neighbours for plane z (block-uniform call)
+template <bool PREV>
 __device__ __forceinline__ void stage_plane(const PartData &pd, NbrStage &sh, int32_t z, const Geo &g)
 {
     __syncthreads();
     for (int k = threadIdx.x; k < sh.nlow; k += blockDim.x) {
         const int o = sh.id[k];
         sh.zin[k] = in_zrange(sh.box[k], z, g);
-        if (sh.zin[k]) sh.rect[k] = remap_rect(pd, o, z, g);
+        if (sh.zin[k]) sh.rect[k] = remap_rect<PREV>(pd, o, z, g);
     }
     __syncthreads();
 }
@@ -194,8 +209,8 @@ __global__ __launch_bounds__(256) void k_remap(S *__restrict__ f, int32_t *__res
         int32_t z = b.lo[2] + iz;
         if (g.zper) z = wrapc(z, nz);
         else if (z < 0 || z >= nz) continue;
-        stage_plane(pd, sh, z, g);
-        const Rect rc = remap_rect(pd, p, z, g);
+        stage_plane<false>(pd, sh, z, g);
+        const Rect rc = remap_rect<false>(pd, p, z, g);
         if (rc.x0 > rc.x1 || rc.y0 > rc.y1) continue;
         const int wx = rc.x1 - rc.x0 + 1, area = wx * (rc.y1 - rc.y0 + 1);
         for (int i = threadIdx.x; i < area; i += blockDim.x) {
@@ -289,8 +304,8 @@ __global__ __launch_bounds__(256) void k_near(uint8_t *__restrict__ flags, const
         int32_t z = b.lo[2] + iz;
         if (g.zper) z = wrapc(z, nz);
         else if (z < 0 || z >= nz) continue;
-        stage_plane(pd, sh, z, g);
-        const Rect rc = remap_rect(pd, p, z, g);
+        stage_plane<true>(pd, sh, z, g);
+        const Rect rc = remap_rect<true>(pd, p, z, g);
         const int wx = rc.x1 - rc.x0 + 1;
         const int area = (rc.x0 > rc.x1 || rc.y0 > rc.y1) ? 0 : wx * (rc.y1 - rc.y0 + 1);
         for (int i = threadIdx.x; i < area; i += blockDim.x) {
