@@ -21,6 +21,9 @@ ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = {
     "sweep.hip": [],
+    # boundary update with the default contraction of the sweep; the A, B, C
+    # part follows the particle header's contraction-off pragma
+    "boundary.hip": [],
     "particles.hip": ["-ffp-contract=off"],
     "api.hip": ["-ffp-contract=off"],
     # the sweep part keeps the default contraction of sweep.hip; the particle

@@ -58,8 +58,8 @@ struct lbm_ctx {
     std::vector<hipEvent_t> ev;
     bool own_stream = false;
     // second stream: boundary sweep and the particle chain run beside the bulk sweep
-    hipStream_t st2 = nullptr, st3 = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_abc = nullptr;
+    hipStream_t st2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     size_t ev_used = 0;
     int64_t timed_sweeps = 0;
     double timed_ms = 0.0;
@@ -305,11 +305,10 @@ static lbm_status check_device_errors(lbm_ctx *c)
     return LBM_OK;
 }
 
-// One time step as a three-branch graph of kernels:
-//   st : bulk sweep ------------------------------------------------------+
-//   st2: boundary sweep (F0, M0) --+--> rigid -> remap -> near/list ------+--> next step
-//   st3: A, B, C of the list ------+
-// The bulk sweep touches only slots of bulk cells; the boundary sweep, the
+// One time step as a two-branch graph of kernels:
+//   st : bulk sweep -----------------------------------------------------------+
+//   st2: boundary cells (F0, M0) + A, B, C sums -> rigid -> remap -> near/list -+--> next step
+// The bulk sweep touches only slots of bulk cells; the boundary update, the
 // refill of the remap and the momentum exchange touch only slots and data
 // of cells next to fibers, so the branches are independent; the sums A, B, C
 // read only the list, the cell owners and the poses.  The bulk sweep of step
@@ -336,7 +335,7 @@ static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hi
     b.ctr = c->ctr;
     hipError_t e = hipSuccess;
     if (!c->np) {
-        e = launch_sweep(c->sk, odd, c->f, c->flags[step_index & 1], c->g, c->ph, b, c->sweep_grid, 0, c->st, c->st,
+        e = launch_sweep(c->sk, odd, c->f, c->flags[step_index & 1], c->g, c->ph, c->sweep_grid, c->st,
                          with_events ? e0 : nullptr, with_events ? e1 : nullptr);
         if (e != hipSuccess && *err == hipSuccess) *err = e;
         return;
@@ -356,16 +355,11 @@ static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hi
     }
     if (e == hipSuccess) e = hipEventRecord(c->ev_fork, c->st);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->st2, c->ev_fork, 0);
-    if (e == hipSuccess) e = hipStreamWaitEvent(c->st3, c->ev_fork, 0);
     if (e == hipSuccess)
-        e = launch_sweep(c->sk, odd, c->f, c->flags[step_index & 1], c->g, c->ph, b, c->sweep_grid, c->bnd_grid,
-                         c->st,
-                         c->st2, with_events ? e0 : nullptr, with_events ? e1 : nullptr);
+        e = launch_sweep(c->sk, odd, c->f, c->flags[step_index & 1], c->g, c->ph, c->sweep_grid, c->st,
+                         with_events ? e0 : nullptr, with_events ? e1 : nullptr);
+    if (e == hipSuccess) e = launch_boundary(c->sk, odd, c->f, c->g, c->ph, b, link_rho0(c), c->st2);
     PartData pd = part_data(c, cur, next);
-    if (e == hipSuccess)
-        e = launch_abc(c->list_cell, c->list_mask, c->pid, pd, c->g, c->bpf, link_rho0(c), c->st3);
-    if (e == hipSuccess) e = hipEventRecord(c->ev_abc, c->st3);
-    if (e == hipSuccess) e = hipStreamWaitEvent(c->st2, c->ev_abc, 0);
     if (e == hipSuccess) e = launch_rigid(pd, c->g, c->st2);
     if (e == hipSuccess) e = launch_remap(c->sk, !odd, c->f, c->pid, pd, c->g, c->p.rho0, c->scale, c->st2);
     if (e == hipSuccess)
@@ -458,10 +452,8 @@ lbm_status lbm_create(const lbm_params *p, lbm_ctx **out)
         c->own_stream = true;
     }
     if (hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&c->st3, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_abc, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
         lbm_destroy(c);
         return LBM_E_HIP;
     }
@@ -543,10 +535,8 @@ lbm_status lbm_destroy(lbm_ctx *c)
     dfree(c->pid);
     dfree(c->ctr);
     if (c->st2) hipStreamDestroy(c->st2);
-    if (c->st3) hipStreamDestroy(c->st3);
     if (c->ev_fork) hipEventDestroy(c->ev_fork);
     if (c->ev_join) hipEventDestroy(c->ev_join);
-    if (c->ev_abc) hipEventDestroy(c->ev_abc);
     if (c->own_stream) hipStreamDestroy(c->st);
     delete c;
     return LBM_OK;

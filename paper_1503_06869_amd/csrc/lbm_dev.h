@@ -164,12 +164,14 @@ enum StorageKind { S_F32 = 0, S_F16 = 1, S_BF16 = 2, S_F64 = 3 };
 
 hipError_t launch_init(int sk, void *f, const Geo &g, double rho0, double wall_u, int couette,
                        double scale, hipStream_t st);
-// bulk sweep on st (bracketed by ev0/ev1 if given), boundary sweep on st_bnd;
-// either part is skipped when its grid is 0
-hipError_t launch_sweep(int sk, bool odd, void *f, const uint8_t *flags, const Geo &g,
-                        const Phys<double> &ph, const BndData &b, uint32_t sweep_grid,
-                        uint32_t bnd_grid, hipStream_t st, hipStream_t st_bnd, hipEvent_t ev0,
-                        hipEvent_t ev1);
+// bulk sweep on st (bracketed by ev0/ev1 if given); skipped when the grid is 0
+hipError_t launch_sweep(int sk, bool odd, void *f, const uint8_t *flags, const Geo &g, const Phys<double> &ph,
+                        uint32_t sweep_grid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
+// boundary cells of the list (update, F0, M0) and the A, B, C sums of their
+// links, one launch (boundary.hip); r0: rho0 as the sweep's collision type
+// holds it (the link terms' k = 6 w rho0)
+hipError_t launch_boundary(int sk, bool odd, void *f, const Geo &g, const Phys<double> &ph, const BndData &b,
+                           double r0, hipStream_t st);
 hipError_t launch_decode(int sk, bool swapped, const void *f, const uint8_t *flags,
                          const int32_t *pid, const PState *ps, const Geo &g, const Phys<double> &ph,
                          void *rho, void *u, double *fout, hipStream_t st);
@@ -181,10 +183,6 @@ hipError_t launch_remap(int sk, bool next_odd, void *f, int32_t *pid, const Part
                         double rho0, double scale, hipStream_t st);
 hipError_t launch_near(uint8_t *flags, const int32_t *pid, uint32_t *list_cell, uint32_t *list_mask,
                        const PartData &pd, const Geo &g, hipStream_t st);
-// A, B, C sums of the current list at pd.ps_cur; r0: rho0 as the sweep's
-// collision type holds it (the link terms' k = 6 w rho0)
-hipError_t launch_abc(const uint32_t *list_cell, const uint32_t *list_mask, const int32_t *pid, const PartData &pd,
-                      const Geo &g, int bpf, double r0, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, size_t nbytes, hipStream_t st);
 
 // closure network (mlp.hip) and feature sampling (features.hip)

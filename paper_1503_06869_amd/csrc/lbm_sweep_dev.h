@@ -68,6 +68,22 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb)
     return xcd * per + (xcd < rem ? xcd : rem) + k;
 }
 
+// the physical parameters in the collision type R (host side, for launches)
+template <typename R>
+inline Phys<R> cast_phys(const Phys<double> &p)
+{
+    Phys<R> o;
+    o.rho0 = R(p.rho0);
+    o.omega_e = R(p.omega_e);
+    o.omega_o = R(p.omega_o);
+    o.wall_u = R(p.wall_u);
+    for (int k = 0; k < 3; ++k) o.g[k] = R(p.g[k]);
+    o.has_g = p.has_g;
+    o.scale = R(p.scale);
+    o.inv_scale = R(p.inv_scale);
+    return o;
+}
+
 // ------------------------------------------------------------------ collision
 // TRT in deviation form: f' = f - w rho0, drho = sum f', j = sum c f'.
 // Even/odd equilibrium parts of Eq. EqPDF_TRT minus w rho0:

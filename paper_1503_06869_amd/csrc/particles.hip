@@ -9,9 +9,7 @@
 //                refill of uncovered cells with f_eq(rho0, u_s) of the
 //                previous step's motion;
 //   k_near       flags of fluid cells next to fibers and the boundary-cell
-//                list consumed by the next sweep;
-//   k_abc        the population-free momentum-exchange sums (A, B, C) of
-//                the list's links at the current poses.
+//                list consumed by the next sweep.
 #include "lbm_sweep_dev.h"
 #include "lbm_particle_dev.h"
 
@@ -247,44 +245,6 @@ __global__ __launch_bounds__(256) void k_remap(S *__restrict__ f, int32_t *__res
 // atomic.
 constexpr int LSTAGE = 2048;
 
-// Terms 6..26 of the momentum exchange (A, B, C; they depend only on the
-// link and the pose) of every link of a boundary cell at the poses ps of
-// the sweep, added to acc for links to fiber home and with atomics for links
-// to another fiber.  The neighbour coordinates and lever arm are formed as
-// in the sweep.
-__device__ __forceinline__ void abc_links(uint32_t cell, uint32_t mask, const int32_t *pid, const PState *ps,
-                                          long long *mea, const Geo &g, int home, double r0,
-                                          long long (&acc)[NABC])
-{
-    const uint32_t z = cell / g.nxy, rem = cell - z * g.nxy, y = rem / g.nx, x = rem - y * g.nx;
-    static_for<1, Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        if ((mask >> q) & 1u) {
-            const uint32_t yx = uint32_t(wrapc(int32_t(x) + CX[q], int32_t(g.nx)));
-            const uint32_t yy = (y + g.ny + CY[q]) % g.ny;
-            const int32_t yzi = int32_t(z) + CZ[q];
-            const uint32_t yz = g.zper ? uint32_t((yzi + int32_t(g.nz)) % int32_t(g.nz)) : uint32_t(yzi);
-            const int o = pid[(yz * g.ny + yy) * g.nx + yx];
-            const PState &sp = ps[o];
-            const double rx = mi(double(yx) - sp.X[0], g.nx, true);
-            const double ry = mi(double(yy) - sp.X[1], g.ny, true);
-            const double rz = mi(double(yz) - sp.X[2], g.nz, g.zper != 0);
-            if (o == home) {
-                link_terms<q, 6, NACC>(acc, 0.0, rx, ry, rz, r0);
-            } else {
-                long long tmp[NABC];
-#pragma unroll
-                for (int k = 0; k < NABC; ++k) tmp[k] = 0;
-                link_terms<q, 6, NACC>(tmp, 0.0, rx, ry, rz, r0);
-#pragma unroll
-                for (int k = 0; k < NABC; ++k)
-                    atomicAdd(reinterpret_cast<unsigned long long *>(mea + size_t(o) * NACC + 6 + k),
-                              (unsigned long long)tmp[k]);
-            }
-        }
-    });
-}
-
 __global__ __launch_bounds__(256) void k_near(uint8_t *__restrict__ flags, const int32_t *__restrict__ pid,
                                               uint32_t *__restrict__ list_cell,
                                               uint32_t *__restrict__ list_mask, PartData pd, Geo g)
@@ -362,47 +322,7 @@ __global__ __launch_bounds__(256) void k_near(uint8_t *__restrict__ flags, const
     }
 }
 
-// A, B, C of the boundary list of the current step at the current poses:
-// block (fiber p, part j) of the fiber's list segment, like the boundary
-// sweep; it runs beside the bulk sweep, before the rigid-body update.
-__global__ __launch_bounds__(256) void k_abc(const uint32_t *__restrict__ list_cell,
-                                             const uint32_t *__restrict__ list_mask,
-                                             const int32_t *__restrict__ pid, PartData pd, Geo g, int bpf,
-                                             double r0)
-{
-    const int p = blockIdx.x / bpf, j = blockIdx.x % bpf;
-    const uint32_t cnt = pd.seg_cnt[p], cap = pd.seg_cap[p];
-    const uint32_t n = cnt < cap ? cnt : cap, off = pd.seg_off[p];
-    long long acc[NABC];
-#pragma unroll
-    for (int k = 0; k < NABC; ++k) acc[k] = 0;
-    for (uint32_t r = j * 256u + threadIdx.x; r < n; r += bpf * 256u)
-        abc_links(list_cell[off + r], list_mask[off + r], pid, pd.ps_cur, pd.mea, g, p, r0, acc);
-    __shared__ long long red[4][NABC];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < NABC; ++k) {
-        long long v = acc[k];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) red[wid][k] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < NABC) {
-        const int k = threadIdx.x;
-        const long long v = red[0][k] + red[1][k] + red[2][k] + red[3][k];
-        if (v) atomicAdd(reinterpret_cast<unsigned long long *>(pd.mea + size_t(p) * NACC + 6 + k),
-                         (unsigned long long)v);
-    }
-}
-
 // ------------------------------------------------------------------ launchers
-hipError_t launch_abc(const uint32_t *list_cell, const uint32_t *list_mask, const int32_t *pid, const PartData &pd,
-                      const Geo &g, int bpf, double r0, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_abc, dim3(pd.np * bpf), dim3(256), 0, st, list_cell, list_mask, pid, pd, g, bpf, r0);
-    return hipGetLastError();
-}
-
 hipError_t launch_rigid(const PartData &pd, const Geo &g, hipStream_t st)
 {
     hipLaunchKernelGGL(k_rigid, dim3(1), dim3(256), size_t(pd.np) * NACC * sizeof(double), st, pd, g);

@@ -32,41 +32,8 @@ __global__ __launch_bounds__(256) void k_sweep_bulk(S *__restrict__ f, const uin
     const uint32_t nchunk = (g.ncell + 255u) >> 8;
     for (uint32_t ch = xcd_block(blockIdx.x, gridDim.x); ch < nchunk; ch += gridDim.x) {
         const uint32_t cell = (ch << 8) + threadIdx.x;
-        if (cell < g.ncell && !flags[cell])   // fiber cells idle; boundary cells: k_sweep_bnd
+        if (cell < g.ncell && !flags[cell])   // fiber cells idle; boundary cells: k_boundary
             update_cell<S, ODD, false>(f, g, ph, cell, 0u, -1, nullptr, BndData{});
-    }
-}
-
-template <typename S, bool ODD>
-__global__ __launch_bounds__(256) void k_sweep_bnd(S *__restrict__ f, Geo g,
-                                                   Phys<typename St<S>::R> ph, BndData b)
-{
-    // block (fiber p, part j) of the fiber's list segment
-    const int p = blockIdx.x / b.bpf, j = blockIdx.x % b.bpf;
-    const uint32_t cnt = b.seg_cnt[p], cap = b.seg_cap[p];
-    const uint32_t n = cnt < cap ? cnt : cap, off = b.seg_off[p];
-    // F0 and M0 only: the population-free sums A, B, C of the same links are
-    // formed when the list is built (k_near)
-    long long acc[6] = {0, 0, 0, 0, 0, 0};
-    for (uint32_t r = j * 256u + threadIdx.x; r < n; r += b.bpf * 256u) {
-        const uint32_t e = off + r;
-        update_cell<S, ODD, true, 6>(f, g, ph, b.cell[e], b.mask[e], p, acc, b);
-    }
-    // integer sums: exact, so the reduction order does not matter
-    __shared__ long long red[4][6];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        long long v = acc[k];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) red[wid][k] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < 6) {
-        const int k = threadIdx.x;
-        const long long v = red[0][k] + red[1][k] + red[2][k] + red[3][k];
-        if (v) atomicAdd(reinterpret_cast<unsigned long long *>(b.mea + size_t(p) * NACC + k),
-                         (unsigned long long)v);
     }
 }
 
@@ -175,57 +142,30 @@ __global__ __launch_bounds__(256) void k_copy(uint4 *__restrict__ dst, const uin
 }
 
 // ------------------------------------------------------------------ launchers
-template <typename R>
-static Phys<R> cast_phys(const Phys<double> &p)
-{
-    Phys<R> o;
-    o.rho0 = R(p.rho0);
-    o.omega_e = R(p.omega_e);
-    o.omega_o = R(p.omega_o);
-    o.wall_u = R(p.wall_u);
-    for (int k = 0; k < 3; ++k) o.g[k] = R(p.g[k]);
-    o.has_g = p.has_g;
-    o.scale = R(p.scale);
-    o.inv_scale = R(p.inv_scale);
-    return o;
-}
-
 template <typename S>
-static hipError_t sweep_t(bool odd, void *f, const uint8_t *flags, const Geo &g,
-                          const Phys<double> &ph, const BndData &b, uint32_t sweep_grid,
-                          uint32_t bnd_grid, hipStream_t st, hipStream_t st_bnd, hipEvent_t ev0,
-                          hipEvent_t ev1)
+static hipError_t sweep_t(bool odd, void *f, const uint8_t *flags, const Geo &g, const Phys<double> &ph,
+                          uint32_t sweep_grid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     using R = typename St<S>::R;
     const Phys<R> p = cast_phys<R>(ph);
-    if (sweep_grid) {
-        if (ev0) hipEventRecord(ev0, st);
-        if (odd)
-            hipLaunchKernelGGL((k_sweep_bulk<S, true>), dim3(sweep_grid), dim3(256), 0, st, (S *)f, flags, g, p);
-        else
-            hipLaunchKernelGGL((k_sweep_bulk<S, false>), dim3(sweep_grid), dim3(256), 0, st, (S *)f, flags, g, p);
-        if (ev1) hipEventRecord(ev1, st);
-    }
-    if (bnd_grid) {
-        bnd_grid = uint32_t(b.np * b.bpf);
-        if (odd)
-            hipLaunchKernelGGL((k_sweep_bnd<S, true>), dim3(bnd_grid), dim3(256), 0, st_bnd, (S *)f, g, p, b);
-        else
-            hipLaunchKernelGGL((k_sweep_bnd<S, false>), dim3(bnd_grid), dim3(256), 0, st_bnd, (S *)f, g, p, b);
-    }
+    if (!sweep_grid) return hipSuccess;
+    if (ev0) hipEventRecord(ev0, st);
+    if (odd)
+        hipLaunchKernelGGL((k_sweep_bulk<S, true>), dim3(sweep_grid), dim3(256), 0, st, (S *)f, flags, g, p);
+    else
+        hipLaunchKernelGGL((k_sweep_bulk<S, false>), dim3(sweep_grid), dim3(256), 0, st, (S *)f, flags, g, p);
+    if (ev1) hipEventRecord(ev1, st);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(int sk, bool odd, void *f, const uint8_t *flags, const Geo &g,
-                        const Phys<double> &ph, const BndData &b, uint32_t sweep_grid,
-                        uint32_t bnd_grid, hipStream_t st, hipStream_t st_bnd, hipEvent_t ev0,
-                        hipEvent_t ev1)
+hipError_t launch_sweep(int sk, bool odd, void *f, const uint8_t *flags, const Geo &g, const Phys<double> &ph,
+                        uint32_t sweep_grid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     switch (sk) {
-    case S_F32: return sweep_t<float>(odd, f, flags, g, ph, b, sweep_grid, bnd_grid, st, st_bnd, ev0, ev1);
-    case S_F16: return sweep_t<_Float16>(odd, f, flags, g, ph, b, sweep_grid, bnd_grid, st, st_bnd, ev0, ev1);
-    case S_BF16: return sweep_t<bf16s>(odd, f, flags, g, ph, b, sweep_grid, bnd_grid, st, st_bnd, ev0, ev1);
-    default: return sweep_t<double>(odd, f, flags, g, ph, b, sweep_grid, bnd_grid, st, st_bnd, ev0, ev1);
+    case S_F32: return sweep_t<float>(odd, f, flags, g, ph, sweep_grid, st, ev0, ev1);
+    case S_F16: return sweep_t<_Float16>(odd, f, flags, g, ph, sweep_grid, st, ev0, ev1);
+    case S_BF16: return sweep_t<bf16s>(odd, f, flags, g, ph, sweep_grid, st, ev0, ev1);
+    default: return sweep_t<double>(odd, f, flags, g, ph, sweep_grid, st, ev0, ev1);
     }
 }
 
