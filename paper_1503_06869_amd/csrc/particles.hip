@@ -241,8 +241,9 @@ __global__ __launch_bounds__(256) void k_remap(S *__restrict__ f, int32_t *__res
 
 // Flags of the cells in the remap regions and the boundary-cell list.  The
 // list is cut into one segment per fiber; a block stages the boundary cells
-// it finds in LDS and reserves a range of its fiber's segment with a single
-// atomic.
+// it finds in all its planes in LDS and reserves a range of its fiber's
+// segment with a single atomic (cells beyond the stage are appended one by
+// one).
 constexpr int LSTAGE = 2048;
 
 __global__ __launch_bounds__(256) void k_near(uint8_t *__restrict__ flags, const int32_t *__restrict__ pid,
@@ -273,13 +274,12 @@ __global__ __launch_bounds__(256) void k_near(uint8_t *__restrict__ flags, const
             const int32_t x = wrapi(rc.x0 + ix, nx), y = wrapi(rc.y0 + iy, ny);
             if (!owned_here(sh, x, y, g)) continue;
             const uint32_t cell = (uint32_t(z) * g.ny + uint32_t(y)) * g.nx + uint32_t(x);
-            if (pid[cell] >= 0) {
-                flags[cell] = F_SOLID;
-                continue;
-            }
+            // the cell's owner and its neighbours' in one round of loads
+            const int32_t own = pid[cell];
             const uint32_t mask = fiber_mask(pid, g, x, y, z);
-            if (!mask) {
-                flags[cell] = 0;
+            const bool near = (own < 0) & (mask != 0u);
+            if (!near) {
+                flags[cell] = own >= 0 ? F_SOLID : uint8_t(0);
                 continue;
             }
             const uint32_t k = atomicAdd(&s_n, 1u);
@@ -300,25 +300,23 @@ __global__ __launch_bounds__(256) void k_near(uint8_t *__restrict__ flags, const
                 }
             }
         }
-        __syncthreads();
-        const uint32_t n = min(s_n, uint32_t(LSTAGE));
-        if (threadIdx.x == 0 && n) s_base = atomicAdd(&pd.seg_cnt[p], n);
-        __syncthreads();
-        for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {
-            const uint32_t r = s_base + k, cell = s_cell[k];
-            if (r < cap) {
-                const uint32_t e = off + r;
-                list_cell[e] = cell;
-                list_mask[e] = s_mask[k];
-                flags[cell] = F_NEAR;
-            } else {
-                flags[cell] = 0;
-                atomicOr(&pd.ctr->err_capacity, 2u);
-            }
+    }
+    // one reservation for all planes of the block
+    __syncthreads();
+    const uint32_t n = min(s_n, uint32_t(LSTAGE));
+    if (threadIdx.x == 0 && n) s_base = atomicAdd(&pd.seg_cnt[p], n);
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {
+        const uint32_t r = s_base + k, cell = s_cell[k];
+        if (r < cap) {
+            const uint32_t e = off + r;
+            list_cell[e] = cell;
+            list_mask[e] = s_mask[k];
+            flags[cell] = F_NEAR;
+        } else {
+            flags[cell] = 0;
+            atomicOr(&pd.ctr->err_capacity, 2u);
         }
-        __syncthreads();
-        if (threadIdx.x == 0) s_n = 0u;
-        __syncthreads();
     }
 }
 
