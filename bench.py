@@ -38,8 +38,8 @@ HBM_PEAK_GBS = 8000.0
 # FETCH_SIZE / WRITE_SIZE passes (profiles/sweep_bulk_256cube_64fibers_traffic.md),
 # scaled by the counters' readings for a plain copy of known size.  Valid only
 # for the sweep source it was measured on (SHA-1 below); otherwise reported null.
-SWEEP_TRAFFIC = {"sweep_sha1": "be0f0ea5074d9793a69aa414251bed4d374b834d",
-                 "bytes_per_launch": 2.5726e9}
+SWEEP_TRAFFIC = {"sweep_sha1": "ba6548a6bfe6baca34ba1430b5beef5a089e22b2",
+                 "bytes_per_launch": 2.5725e9}
 # algorithmic bytes per lattice update of the bulk sweep: 19 loads + 19
 # stores of the population type + the 1-byte cell flag
 BYTES_PER_LUP = {"f32": 19 * 4 * 2 + 1, "f16": 19 * 2 * 2 + 1, "bf16": 19 * 2 * 2 + 1,
