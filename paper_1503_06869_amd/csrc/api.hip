@@ -65,7 +65,6 @@ struct lbm_ctx {
     double timed_ms = 0.0;
     // learned closure (not owned)
     lbm_mlp *closure = nullptr;
-    float *feat = nullptr, *cy = nullptr;
     double *corr = nullptr;
     unsigned long long *cstats = nullptr;
 };
@@ -346,13 +345,8 @@ static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hi
         // corrections for the rigid-body update of this step
         const MlpDev md = mlp_device_view(c->closure);
         const double gamma = 2.0 * c->p.wall_u / c->p.nz, nu = (c->p.tau - 0.5) / 3.0;
-        e = launch_sample_features(c->sk, odd, c->f, c->flags[step_index & 1], c->pid, cur, c->pc, c->np, c->g,
-                                   c->ph, gamma,
-                                   c->feat, c->st);
-        if (e == hipSuccess) e = launch_mlp_forward(md, c->feat, c->np, c->cy, c->st);
-        if (e == hipSuccess)
-            e = launch_closure_apply(md, c->feat, c->cy, c->pc, c->np, c->p.rho0, nu, gamma, c->corr, c->cstats,
-                                     c->st);
+        e = launch_closure_step(c->sk, odd, c->f, c->flags[step_index & 1], c->pid, cur, c->pc, c->np, c->g, c->ph,
+                                gamma, md, c->p.rho0, nu, c->corr, c->cstats, c->st);
     }
     if (e == hipSuccess) e = hipEventRecord(c->ev_fork, c->st);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->st2, c->ev_fork, 0);
@@ -526,8 +520,6 @@ lbm_status lbm_destroy(lbm_ctx *c)
     drop_graph(c);
     for (hipEvent_t e : c->ev) hipEventDestroy(e);
     free_particles(c);
-    dfree(c->feat);
-    dfree(c->cy);
     dfree(c->corr);
     dfree(c->cstats);
     dfree(c->f);
@@ -910,11 +902,7 @@ lbm_status lbm_set_closure(lbm_ctx *c, lbm_mlp *m)
     if (c->p.z_periodic || c->p.wall_u == 0.0)
         return fail(c, LBM_E_ARG, "the closure needs a shear cell (moving walls, U != 0)");
     if (c->np == 0) return fail(c, LBM_E_STATE, "add the fibers before attaching the closure");
-    dfree(c->feat);
-    dfree(c->cy);
     dfree(c->corr);
-    HIPCHK(c, dalloc(c, &c->feat, size_t(c->np) * LBM_MLP_IN));
-    HIPCHK(c, dalloc(c, &c->cy, size_t(c->np) * LBM_MLP_OUT));
     HIPCHK(c, dalloc(c, &c->corr, size_t(c->np) * LBM_MLP_OUT));
     if (!c->cstats) HIPCHK(c, dalloc(c, &c->cstats, 2));
     HIPCHK(c, hipMemsetAsync(c->corr, 0, size_t(c->np) * LBM_MLP_OUT * sizeof(double), c->st));

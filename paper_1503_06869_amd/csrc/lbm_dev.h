@@ -192,9 +192,12 @@ struct MlpDev {
 };
 MlpDev mlp_device_view(const ::lbm_mlp *m);
 hipError_t launch_mlp_forward(const MlpDev &m, const float *x, int n, float *y, hipStream_t st);
-hipError_t launch_closure_apply(const MlpDev &m, const float *feat, const float *y, const PConst *pc, int np,
-                                double rho0, double nu, double gamma, double *corr, unsigned long long *stats,
-                                hipStream_t st);
+// one step's closure of np fibers (features, network, correction into
+// corr[np][6], applied/fallback counts into stats[2]), one launch
+hipError_t launch_closure_step(int sk, bool swapped, const void *f, const uint8_t *flags, const int32_t *pid,
+                               const PState *ps, const PConst *pc, int np, const Geo &g, const Phys<double> &ph,
+                               double gamma, const MlpDev &m, double rho0, double nu, double *corr,
+                               unsigned long long *stats, hipStream_t st);
 // features [np][247] of np fibers whose states are ps[k * ps_stride] (one
 // lattice: the arrays of that lattice)
 hipError_t launch_sample_features(int sk, bool swapped, const void *f, const uint8_t *flags, const int32_t *pid,

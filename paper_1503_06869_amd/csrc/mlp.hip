@@ -1,6 +1,7 @@
 // mlp.hip -- the closure network (247 -> 64 -> 64 -> 6, GELU, BF16 weights,
-// FP32 activations and accumulation): forward, loss and gradient, Adam, the
-// training loop, and the per-step closure kernel used by lbm_step.
+// FP32 activations and accumulation): forward, loss and gradient, Adam and
+// the training loop.  The per-step closure (features, one-sample forward,
+// correction in one launch) is in features.hip.
 //
 // Work layout.  A workgroup of 256 threads takes a tile of 32 samples: the
 // tile's inputs, both hidden layers and the BF16 weights sit in LDS; thread
@@ -19,18 +20,11 @@
 #include <string>
 #include <vector>
 
-#include "../../include/lbm_mlp.h"
-#include "lbm_dev.h"
+#include "lbm_mlp_dev.h"
 
 namespace lbm {
 
-constexpr int NI = LBM_MLP_IN, NH = LBM_MLP_HIDDEN, NO = LBM_MLP_OUT, NP = LBM_MLP_NPARAM;
-constexpr int OW1 = 0, OB1 = NH * NI, OW2 = OB1 + NH, OB2 = OW2 + NH * NH, OW3 = OB2 + NH,
-              OB3 = OW3 + NO * NH;
-static_assert(OB3 + NO == NP, "parameter layout");
 constexpr int TILE = 32, MB = 256, GRAD_BLOCKS = 64;
-
-__device__ __forceinline__ float bf(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
 
 __host__ __device__ inline uint16_t to_bf16(float v)
 {
@@ -40,8 +34,7 @@ __host__ __device__ inline uint16_t to_bf16(float v)
     return uint16_t(u >> 16);
 }
 
-// exact GELU and its derivative: g(z) = z Phi(z), g'(z) = Phi(z) + z phi(z)
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// derivative of the exact GELU: g'(z) = Phi(z) + z phi(z)
 __device__ __forceinline__ float gelu_d(float z)
 {
     return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
@@ -288,42 +281,6 @@ __global__ void k_zero_d(double *p, int n)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0.0;
 }
 
-// Closure of a step: for each fiber, the network output (body frame)
-// rotated to the lab frame and in physical units, or nothing when a raw
-// feature lies outside the training envelope:
-//   corr[p][0..2] = R(q) y[0..2] rho0 nu gamma L^2,  corr[p][3..5] = R(q) y[3..5] rho0 nu gamma L^3
-// (q: the orientation in features 243..246).
-__global__ void k_closure_apply(const float *__restrict__ feat, const float *__restrict__ y,
-                                const float *__restrict__ env_min, const float *__restrict__ env_max,
-                                const PConst *__restrict__ pc, int np, double rho0, double nu, double gamma,
-                                double *__restrict__ corr, unsigned long long *__restrict__ stats)
-{
-    const int p = blockIdx.x;
-    if (p >= np) return;
-    __shared__ int out;
-    if (threadIdx.x == 0) out = 0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < NI; i += blockDim.x) {
-        const float v = feat[size_t(p) * NI + i];
-        if (!(v >= env_min[i] && v <= env_max[i])) atomicOr(&out, 1);
-    }
-    __syncthreads();
-    if (threadIdx.x < NO) {
-        const int o = threadIdx.x, part = o / 3, row = o % 3;
-        const float *fq = feat + size_t(p) * NI + 243;
-        const double w = fq[0], qx = fq[1], qy = fq[2], qz = fq[3];
-        const double Rm[3][3] = {{1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy - w * qz), 2.0 * (qx * qz + w * qy)},
-                                 {2.0 * (qx * qy + w * qz), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz - w * qx)},
-                                 {2.0 * (qx * qz - w * qy), 2.0 * (qy * qz + w * qx), 1.0 - 2.0 * (qx * qx + qy * qy)}};
-        const float *yp = y + size_t(p) * NO + 3 * part;
-        const double L = pc[p].length;
-        const double sF = rho0 * nu * gamma * L * L, sc = part == 0 ? sF : sF * L;
-        const double lab = Rm[row][0] * yp[0] + Rm[row][1] * yp[1] + Rm[row][2] * yp[2];
-        corr[size_t(p) * NO + o] = out ? 0.0 : lab * sc;
-    }
-    if (threadIdx.x == 0) atomicAdd(&stats[out ? 1 : 0], 1ull);
-}
-
 }  // namespace lbm
 
 using namespace lbm;
@@ -361,15 +318,6 @@ hipError_t launch_mlp_forward(const MlpDev &m, const float *x, int n, float *y, 
     return hipGetLastError();
 }
 
-hipError_t launch_closure_apply(const MlpDev &m, const float *feat, const float *y, const PConst *pc, int np,
-                                double rho0, double nu, double gamma, double *corr, unsigned long long *stats,
-                                hipStream_t st)
-{
-    if (np <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_closure_apply, dim3(np), dim3(256), 0, st, feat, y, m.env_min, m.env_max, pc, np, rho0,
-                       nu, gamma, corr, stats);
-    return hipGetLastError();
-}
 }  // namespace lbm
 
 static lbm_status mfail(lbm_mlp *m, lbm_status s, const std::string &e)
