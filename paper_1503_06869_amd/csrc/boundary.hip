@@ -57,24 +57,43 @@ namespace lbm {
 // Terms 6..26 of the momentum exchange (A, B, C) of every link of a boundary
 // cell at the poses ps of the sweep, added to acc for links to fiber home and
 // with atomics for links to another fiber.  The neighbour coordinates and
-// lever arm are formed as in the sweep.
+// lever arm are formed as in the sweep; the owners across all links are
+// loaded together first, the home pose is passed in.
 __device__ __forceinline__ void abc_links(uint32_t cell, uint32_t mask, const int32_t *pid, const PState *ps,
-                                          long long *mea, const Geo &g, int home, double r0,
+                                          const double hX[3], long long *mea, const Geo &g, int home, double r0,
                                           long long (&acc)[NABC])
 {
     const uint32_t z = cell / g.nxy, rem = cell - z * g.nxy, y = rem / g.nx, x = rem - y * g.nx;
+    // far cell of link q (periodic x, y; z periodic or walled)
+    auto far = [&](auto qc, uint32_t &yx, uint32_t &yy, uint32_t &yz) {
+        constexpr int q = decltype(qc)::value;
+        yx = uint32_t(wrapc(int32_t(x) + CX[q], int32_t(g.nx)));
+        yy = uint32_t(wrapc(int32_t(y) + CY[q], int32_t(g.ny)));
+        const int32_t yzi = int32_t(z) + CZ[q];
+        yz = g.zper ? uint32_t(wrapc(yzi, int32_t(g.nz))) : uint32_t(yzi);
+    };
+    int32_t own[Q];
+    static_for<1, Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        uint32_t yx, yy, yz;
+        far(qc, yx, yy, yz);
+        own[q] = pid[((mask >> q) & 1u) ? (yz * g.ny + yy) * g.nx + yx : cell];
+    });
     static_for<1, Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         if ((mask >> q) & 1u) {
-            const uint32_t yx = uint32_t(wrapc(int32_t(x) + CX[q], int32_t(g.nx)));
-            const uint32_t yy = (y + g.ny + CY[q]) % g.ny;
-            const int32_t yzi = int32_t(z) + CZ[q];
-            const uint32_t yz = g.zper ? uint32_t((yzi + int32_t(g.nz)) % int32_t(g.nz)) : uint32_t(yzi);
-            const int o = pid[(yz * g.ny + yy) * g.nx + yx];
-            const PState &sp = ps[o];
-            const double rx = mi(double(yx) - sp.X[0], g.nx, true);
-            const double ry = mi(double(yy) - sp.X[1], g.ny, true);
-            const double rz = mi(double(yz) - sp.X[2], g.nz, g.zper != 0);
+            uint32_t yx, yy, yz;
+            far(qc, yx, yy, yz);
+            const int o = own[q];
+            double sX[3];
+            if (o == home) {
+                for (int k = 0; k < 3; ++k) sX[k] = hX[k];
+            } else {
+                for (int k = 0; k < 3; ++k) sX[k] = ps[o].X[k];
+            }
+            const double rx = mi(double(yx) - sX[0], g.nx, true);
+            const double ry = mi(double(yy) - sX[1], g.ny, true);
+            const double rz = mi(double(yz) - sX[2], g.nz, g.zper != 0);
             if (o == home) {
                 link_terms<q, 6, NACC>(acc, 0.0, rx, ry, rz, r0);
             } else {
@@ -101,8 +120,9 @@ __device__ __forceinline__ void abc_block(const BndData &b, const Geo &g, double
     long long acc[NABC];
 #pragma unroll
     for (int k = 0; k < NABC; ++k) acc[k] = 0;
+    const double hX[3] = {b.ps[p].X[0], b.ps[p].X[1], b.ps[p].X[2]};
     for (uint32_t r = j * 256u + threadIdx.x; r < n; r += b.bpf * 256u)
-        abc_links(b.cell[off + r], b.mask[off + r], b.pid, b.ps, b.mea, g, p, r0, acc);
+        abc_links(b.cell[off + r], b.mask[off + r], b.pid, b.ps, hX, b.mea, g, p, r0, acc);
     __shared__ long long red[4][NABC];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -120,6 +140,10 @@ __device__ __forceinline__ void abc_block(const BndData &b, const Geo &g, double
     }
 }
 
+// Register budget: the bulk sweep keeps 2 waves of 80 VGPRs per SIMD
+// resident for its whole grid-stride run; this kernel runs beside it with
+// up to 2 waves per SIMD, so it must stay within 176 VGPRs (171 for FP32),
+// or bulk workgroups launched after it start late and the sweep stretches.
 template <typename S, bool ODD>
 __global__ __launch_bounds__(256) void k_boundary(S *__restrict__ f, Geo g, Phys<typename St<S>::R> ph,
                                                   BndData b, double r0)
