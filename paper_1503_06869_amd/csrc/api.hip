@@ -350,10 +350,22 @@ static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hi
     }
     if (e == hipSuccess) e = hipEventRecord(c->ev_fork, c->st);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->st2, c->ev_fork, 0);
+    // Launch order of the two branches (measured): the branch expected to be
+    // longer goes first.  A resident grid-stride bulk grid (up to 1024
+    // workgroups, FP32/FP64) over a lattice large against the boundary list
+    // (256^3 with 64 fibers) goes first, since all its workgroups must start
+    // together; the boundary launch goes first when the bulk grid is large
+    // (16-bit storage: it would hold the boundary workgroups off until it
+    // drains) or the lattice is small against the list (128^3 with 200
+    // fibers: the particle branch is the longer one).
+    const bool bulk_first = c->sweep_grid <= 1024u && uint64_t(c->g.ncell) >= 32ull * c->list_cap;
+    if (e == hipSuccess && !bulk_first)
+        e = launch_boundary(c->sk, odd, c->f, c->g, c->ph, b, link_rho0(c), c->st2);
     if (e == hipSuccess)
         e = launch_sweep(c->sk, odd, c->f, c->flags[step_index & 1], c->g, c->ph, c->sweep_grid, c->st,
                          with_events ? e0 : nullptr, with_events ? e1 : nullptr);
-    if (e == hipSuccess) e = launch_boundary(c->sk, odd, c->f, c->g, c->ph, b, link_rho0(c), c->st2);
+    if (e == hipSuccess && bulk_first)
+        e = launch_boundary(c->sk, odd, c->f, c->g, c->ph, b, link_rho0(c), c->st2);
     PartData pd = part_data(c, cur, next);
     if (e == hipSuccess) e = launch_rigid(pd, c->g, c->st2);
     if (e == hipSuccess) e = launch_remap(c->sk, !odd, c->f, c->pid, pd, c->g, c->p.rho0, c->scale, c->st2);
