@@ -117,14 +117,22 @@ __global__ __launch_bounds__(256) void k_rigid(PartData pd, Geo g)
 struct NbrStage {
     int32_t id[NBR_CAP];
     Box box[NBR_CAP];
-    Rect rect[NBR_CAP];   // plane rectangle of each lower-indexed neighbour (current plane)
-    uint8_t zin[NBR_CAP]; // current plane inside the neighbour's box
     int32_t n, nlow;
 };
 
-// The fibers whose remap boxes meet fiber p's, in ascending order: every
-// block scans all boxes (one per thread and pass) and compacts the hits in
-// thread order, so all blocks of the step form the same list.
+// Rectangles of a chunk of the block's planes, for one flattened pass over
+// all their cells: rect[k * ne + 0] is the own fiber's rectangle in plane k
+// of the chunk, rect[k * ne + j] that of the j-th lower-indexed neighbour
+// (empty where the plane is outside the neighbour's box); pref holds the
+// prefix of the own rectangles' cell counts.
+constexpr int RT_MAXE = 512, RT_MAXP = 32;
+struct RegionTable {
+    Rect rect[RT_MAXE];
+    int32_t z[RT_MAXP];
+    int32_t pref[RT_MAXP + 1];
+    int32_t npl, ne;
+};
+
 __device__ __forceinline__ void stage_nbrs(const PartData &pd, int p, NbrStage &sh, const Geo &g)
 {
     __shared__ uint32_t s_wc[4], s_low;
@@ -169,24 +177,64 @@ __device__ __forceinline__ void stage_nbrs(const PartData &pd, int p, NbrStage &
     __syncthreads();
 }
 
-// rectangles of the lower-indexed neighbours for plane z (block-uniform call)
+// Table of the planes iz0, iz0 + ns, ... of box b (as many as fit); returns
+// the number of planes taken (block-uniform call).
 template <bool PREV>
-__device__ __forceinline__ void stage_plane(const PartData &pd, NbrStage &sh, int32_t z, const Geo &g)
+__device__ int build_table(const PartData &pd, const NbrStage &sh, int p, const Box &b, int iz0, int ns,
+                           const Geo &g, RegionTable &t)
 {
-    __syncthreads();
-    for (int k = threadIdx.x; k < sh.nlow; k += blockDim.x) {
-        const int o = sh.id[k];
-        sh.zin[k] = in_zrange(sh.box[k], z, g);
-        if (sh.zin[k]) sh.rect[k] = remap_rect<PREV>(pd, o, z, g);
+    const int ne = sh.nlow + 1;
+    const int left = iz0 < b.len[2] ? (b.len[2] - iz0 + ns - 1) / ns : 0;
+    const int npl = min(left, min(RT_MAXP, RT_MAXE / ne));
+    __syncthreads();   // the previous chunk's pass is done with the table
+    for (int e = threadIdx.x; e < npl * ne; e += blockDim.x) {
+        const int k = e / ne, j = e - k * ne;
+        int32_t z = b.lo[2] + iz0 + k * ns;
+        bool valid = true;
+        if (g.zper) z = wrapc(z, int32_t(g.nz));
+        else valid = z >= 0 && z < int32_t(g.nz);
+        Rect r{1, 0, 1, 0};
+        if (valid) {
+            if (j == 0) r = remap_rect<PREV>(pd, p, z, g);
+            else if (in_zrange(sh.box[j - 1], z, g)) r = remap_rect<PREV>(pd, sh.id[j - 1], z, g);
+        }
+        t.rect[e] = r;
+        if (j == 0) t.z[k] = z;
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t acc = 0;
+        for (int k = 0; k < npl; ++k) {
+            t.pref[k] = acc;
+            const Rect r = t.rect[k * ne];
+            if (r.x0 <= r.x1 && r.y0 <= r.y1) acc += (r.x1 - r.x0 + 1) * (r.y1 - r.y0 + 1);
+        }
+        t.pref[npl] = acc;
+        t.npl = npl;
+        t.ne = ne;
+    }
+    __syncthreads();
+    return npl;
 }
 
-// a cell is handled by the lowest-indexed fiber whose remap region holds it
-__device__ __forceinline__ bool owned_here(const NbrStage &sh, int32_t x, int32_t y, const Geo &g)
+// cell idx of the chunk's flattened index space: plane k, position (x, y)
+__device__ __forceinline__ void table_cell(const RegionTable &t, int idx, const Geo &g, int &k, int32_t &x,
+                                           int32_t &y)
 {
-    for (int k = 0; k < sh.nlow; ++k)
-        if (sh.zin[k] && in_rect(sh.rect[k], x, y, g)) return false;
+    k = 0;
+    while (k + 1 < t.npl && t.pref[k + 1] <= idx) ++k;
+    const Rect r = t.rect[k * t.ne];
+    const int wx = r.x1 - r.x0 + 1, i = idx - t.pref[k];
+    const int iy = i / wx, ix = i - iy * wx;
+    x = wrapi(r.x0 + ix, int32_t(g.nx));
+    y = wrapi(r.y0 + iy, int32_t(g.ny));
+}
+
+// a cell is handled by the lowest-indexed fiber whose region holds it
+__device__ __forceinline__ bool owned_here(const RegionTable &t, int k, int32_t x, int32_t y, const Geo &g)
+{
+    for (int j = 1; j < t.ne; ++j)
+        if (in_rect(t.rect[k * t.ne + j], x, y, g)) return false;
     return true;
 }
 
@@ -202,28 +250,24 @@ __global__ __launch_bounds__(256) void k_remap(S *__restrict__ f, int32_t *__res
     const Box b = pd.box_remap[p];
     const PState sp = pd.ps_next[p];
     const PConst cp = pd.pc[p];
-    const int32_t nx = g.nx, ny = g.ny, nz = g.nz;
-    for (int iz = sl; iz < b.len[2]; iz += ns) {   // block-uniform
-        int32_t z = b.lo[2] + iz;
-        if (g.zper) z = wrapc(z, nz);
-        else if (z < 0 || z >= nz) continue;
-        stage_plane<false>(pd, sh, z, g);
-        const Rect rc = remap_rect<false>(pd, p, z, g);
-        if (rc.x0 > rc.x1 || rc.y0 > rc.y1) continue;
-        const int wx = rc.x1 - rc.x0 + 1, area = wx * (rc.y1 - rc.y0 + 1);
-        for (int i = threadIdx.x; i < area; i += blockDim.x) {
-            const int iy = i / wx, ix = i - iy * wx;
-            const int32_t x = wrapi(rc.x0 + ix, nx), y = wrapi(rc.y0 + iy, ny);
-            if (!owned_here(sh, x, y, g)) continue;
+    __shared__ RegionTable t;
+    for (int iz0 = sl; iz0 < b.len[2];) {   // block-uniform: chunks of planes
+        iz0 += ns * build_table<false>(pd, sh, p, b, iz0, ns, g, t);
+        for (int idx = threadIdx.x; idx < t.pref[t.npl]; idx += blockDim.x) {
+            int k;
+            int32_t x, y;
+            table_cell(t, idx, g, k, x, y);
+            if (!owned_here(t, k, x, y, g)) continue;
+            const int32_t z = t.z[k];
             const double cx = x, cy = y, cz = z;
             int owner = -1, claims = 0;
             if (inside(sp, cp, cx, cy, cz, g)) {
                 owner = p;
                 claims = 1;
             }
-            for (int k = sh.nlow; k < sh.n; ++k) {
-                const int o = sh.id[k];
-                if (!in_box(sh.box[k], x, y, z, g)) continue;
+            for (int j = sh.nlow; j < sh.n; ++j) {
+                const int o = sh.id[j];
+                if (!in_box(sh.box[j], x, y, z, g)) continue;
                 if (inside(pd.ps_next[o], pd.pc[o], cx, cy, cz, g)) {
                     if (owner < 0) owner = o;
                     ++claims;
@@ -244,7 +288,7 @@ __global__ __launch_bounds__(256) void k_remap(S *__restrict__ f, int32_t *__res
 // it finds in all its planes in LDS and reserves a range of its fiber's
 // segment with a single atomic (cells beyond the stage are appended one by
 // one).
-constexpr int LSTAGE = 2048;
+constexpr int LSTAGE = 1024;
 
 __global__ __launch_bounds__(256) void k_near(uint8_t *__restrict__ flags, const int32_t *__restrict__ pid,
                                               uint32_t *__restrict__ list_cell,
@@ -260,19 +304,15 @@ __global__ __launch_bounds__(256) void k_near(uint8_t *__restrict__ flags, const
     __syncthreads();
     const Box b = pd.box_remap[p];
     const uint32_t off = pd.seg_off[p], cap = pd.seg_cap[p];
-    const int32_t nx = g.nx, ny = g.ny, nz = g.nz;
-    for (int iz = sl; iz < b.len[2]; iz += ns) {   // block-uniform
-        int32_t z = b.lo[2] + iz;
-        if (g.zper) z = wrapc(z, nz);
-        else if (z < 0 || z >= nz) continue;
-        stage_plane<true>(pd, sh, z, g);
-        const Rect rc = remap_rect<true>(pd, p, z, g);
-        const int wx = rc.x1 - rc.x0 + 1;
-        const int area = (rc.x0 > rc.x1 || rc.y0 > rc.y1) ? 0 : wx * (rc.y1 - rc.y0 + 1);
-        for (int i = threadIdx.x; i < area; i += blockDim.x) {
-            const int iy = i / wx, ix = i - iy * wx;
-            const int32_t x = wrapi(rc.x0 + ix, nx), y = wrapi(rc.y0 + iy, ny);
-            if (!owned_here(sh, x, y, g)) continue;
+    __shared__ RegionTable t;
+    for (int iz0 = sl; iz0 < b.len[2];) {   // block-uniform: chunks of planes
+        iz0 += ns * build_table<true>(pd, sh, p, b, iz0, ns, g, t);
+        for (int idx = threadIdx.x; idx < t.pref[t.npl]; idx += blockDim.x) {
+            int k;
+            int32_t x, y;
+            table_cell(t, idx, g, k, x, y);
+            if (!owned_here(t, k, x, y, g)) continue;
+            const int32_t z = t.z[k];
             const uint32_t cell = (uint32_t(z) * g.ny + uint32_t(y)) * g.nx + uint32_t(x);
             // the cell's owner and its neighbours' in one round of loads
             const int32_t own = pid[cell];
@@ -282,10 +322,10 @@ __global__ __launch_bounds__(256) void k_near(uint8_t *__restrict__ flags, const
                 flags[cell] = own >= 0 ? F_SOLID : uint8_t(0);
                 continue;
             }
-            const uint32_t k = atomicAdd(&s_n, 1u);
-            if (k < LSTAGE) {
-                s_cell[k] = cell;
-                s_mask[k] = mask;
+            const uint32_t kk = atomicAdd(&s_n, 1u);
+            if (kk < LSTAGE) {
+                s_cell[kk] = cell;
+                s_mask[kk] = mask;
             } else {
                 // stage full: append directly
                 const uint32_t r = atomicAdd(&pd.seg_cnt[p], 1u);
@@ -296,7 +336,7 @@ __global__ __launch_bounds__(256) void k_near(uint8_t *__restrict__ flags, const
                     flags[cell] = F_NEAR;
                 } else {
                     flags[cell] = 0;
-                        atomicOr(&pd.ctr->err_capacity, 2u);
+                    atomicOr(&pd.ctr->err_capacity, 2u);
                 }
             }
         }
