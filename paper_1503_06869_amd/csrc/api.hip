@@ -224,14 +224,16 @@ static lbm_status upload_particles(lbm_ctx *c)
     // boundary-list segments, one per fiber: fluid cells next to a fiber lie
     // within sqrt(2) of its cylinder; bound them by the cylinder widened by 2.5
     std::vector<uint32_t> soff(np), scap(np);
-    double total = 0.0, maxcap = 0.0;
+    double total = 0.0, maxsurf = 0.0;
     for (int i = 0; i < np; ++i) {
         const double r = c->fib[i].radius + 2.5, L = c->fib[i].length + 5.0;
         const double cap = 1.25 * (M_PI * r * r * L + 4.0 * M_PI * r * r) + 256.0;
         soff[i] = uint32_t(total);
         scap[i] = uint32_t(cap);
         total += double(scap[i]);
-        maxcap = std::max(maxcap, double(scap[i]));
+        // expected boundary cells: about one shell of the cylinder widened by 1
+        const double rs = c->fib[i].radius + 1.0, ls = c->fib[i].length + 2.0;
+        maxsurf = std::max(maxsurf, 2.0 * M_PI * rs * ls);
     }
     if (total >= 4294967295.0) return fail(c, LBM_E_ARG, "boundary list too large");
     c->list_cap = uint32_t(total);
@@ -239,8 +241,10 @@ static lbm_status upload_particles(lbm_ctx *c)
     HIPCHK(c, dalloc(c, &c->list_mask, c->list_cap));
     HIPCHK(c, hipMemcpyAsync(c->seg_off, soff.data(), np * sizeof(uint32_t), hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipMemcpyAsync(c->seg_cap, scap.data(), np * sizeof(uint32_t), hipMemcpyHostToDevice, c->st));
-    // boundary sweep: blocks per fiber segment, about four entries per thread
-    c->bpf = std::max(1, std::min(16, int(maxcap / 1.25 / 1024.0) + 1));
+    // boundary launch: blocks per fiber segment, about one entry per thread
+    // for the largest fiber (each pass over a segment is a chain of
+    // dependent loads, so extra passes add latency, not throughput)
+    c->bpf = std::max(1, std::min(16, int(std::ceil(maxsurf / 256.0))));
     c->remap_grid = uint32_t(np * c->nslab);
     c->bnd_grid = uint32_t(np * c->bpf);
     std::vector<PState> hs(np);
