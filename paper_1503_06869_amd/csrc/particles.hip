@@ -2,14 +2,14 @@
 //   k_rigid      the momentum-exchange sums of each fiber (Eq.
 //                LBMhydrodynForce and the torque after it, Sec. 4.2),
 //                accumulated by the boundary sweep, back to FP64; the
-//                rigid-body update (Sec. 4.3); the cell boxes and neighbour
-//                lists of the remap;
+//                rigid-body update (Sec. 4.3); the cell boxes of the remap;
 //   k_remap      cell mapping with the new poses (Sec. 4.2: a cell is an
 //                obstacle cell when its centre lies inside a particle) and
 //                refill of uncovered cells with f_eq(rho0, u_s) of the
 //                previous step's motion;
-//   k_near       flags of fluid cells next to fibers and the boundary-cell
-//                list consumed by the next sweep.
+//   k_near       flags of fluid cells next to fibers, written into the flag
+//                buffer of the next step, and the boundary-cell list consumed
+//                by the next step's boundary launch.
 #include "lbm_sweep_dev.h"
 #include "lbm_particle_dev.h"
 
@@ -110,10 +110,11 @@ __global__ __launch_bounds__(256) void k_rigid(PartData pd, Geo g)
 }
 
 // ------------------------------------------------------------------ remap and boundary list
-// Grid: np * nslab blocks; block (p, s) walks the z-planes s, s + nslab, ...
-// of fiber p's remap box.  A cell inside the box of a lower-indexed fiber is
-// left to that fiber's blocks, so every cell is handled once.  The boxes of
-// the neighbouring fibers are staged in LDS.
+// Grid: np * nslab blocks; block (p, s) takes the z-planes s, s + nslab, ...
+// of fiber p's remap box.  A cell inside the plane rectangle of a
+// lower-indexed fiber is left to that fiber's blocks, so every cell is
+// handled once.  The ids and boxes of the neighbouring fibers are staged in
+// LDS.
 struct NbrStage {
     int32_t id[NBR_CAP];
     Box box[NBR_CAP];
