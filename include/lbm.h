@@ -98,10 +98,23 @@ typedef struct {
     int32_t q_pad;             /* extra elements between direction arrays; -1 = automatic */
 } lbm_params;
 
-/* A rigid circular cylinder.  The axis is t = R(q) e_x for the unit
- * quaternion q = (w, x, y, z).  Cells whose centre lies inside belong to
- * the fiber (Sec. 4.2).  Mass = density_ratio * rho0 * pi r^2 L,
- * I_par = m r^2 / 2, I_perp = m (3 r^2 + L^2) / 12. */
+/* Fiber shapes: a circular cylinder of length L, or a spherocylinder (a
+ * cylinder with hemispherical caps, L including the caps, so the
+ * cylindrical part is L - 2r long; the particle shape of Sec. 2). */
+typedef enum { LBM_SHAPE_CYLINDER = 0, LBM_SHAPE_SPHEROCYLINDER = 1 } lbm_shape;
+
+/* A rigid fiber.  The axis is t = R(q) e_x for the unit quaternion
+ * q = (w, x, y, z).  Cells whose centre lies inside belong to the fiber
+ * (Sec. 4.2).  Mass m = density_ratio * rho0 * V; for the cylinder
+ * V = pi r^2 L, I_par = m r^2 / 2, I_perp = m (3 r^2 + L^2) / 12; for the
+ * spherocylinder with h = L - 2r, cylinder part m_c = m pi r^2 h / V and
+ * caps m_s = m (4/3) pi r^3 / V: I_par = m_c r^2 / 2 + (2/5) m_s r^2,
+ * I_perp = m_c (3 r^2 + h^2) / 12 + m_s (2 r^2 / 5 + h^2 / 4 + 3 h r / 8).
+ * force and torque: a constant external load added to the hydrodynamic
+ * force and torque in every step, e.g. the buoyancy-corrected weight
+ * (rho_p - rho_f) g V of Eq. ForceDensDiff (lattice units).  The fields
+ * from shape on were appended to the original layout; zero-filled they
+ * give a cylinder without external load. */
 typedef struct {
     double center[3];
     double quat[4];
@@ -110,6 +123,10 @@ typedef struct {
     double density_ratio;
     double vel[3];
     double omega[3];
+    int32_t shape;             /* lbm_shape */
+    int32_t reserved;          /* 0 */
+    double force[3];
+    double torque[3];
 } lbm_fiber;
 
 typedef struct {

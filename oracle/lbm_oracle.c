@@ -124,8 +124,15 @@ static double min_image(double d, int n, int periodic)
     return d;
 }
 
-int or_cell_inside(const double c[3], const double X[3], const double t[3],
-                   double length, double radius, int nx, int ny, int nz, int zper)
+/* Sec. 4.2: a cell belongs to the particle when its centre lies inside it.
+   Cylinder of length L and radius r: the axial coordinate a = d.t obeys
+   |a| <= L/2 and the squared distance from the axis q = |d|^2 - a^2 <= r^2.
+   Spherocylinder (Sec. 2: L includes the hemispherical caps): the set of
+   points within r of the axis segment of half-length L/2 - r; with
+   e = |a| - (L/2 - r) the distance past the segment's end, q <= r^2 where
+   e <= 0, else q + e^2 <= r^2 (squared distance to the cap centre). */
+int or_cell_inside_shape(const double c[3], const double X[3], const double t[3], double length,
+                         double radius, int shape, int nx, int ny, int nz, int zper)
 {
     double dx = min_image(c[0] - X[0], nx, 1);
     double dy = min_image(c[1] - X[1], ny, 1);
@@ -133,7 +140,19 @@ int or_cell_inside(const double c[3], const double X[3], const double t[3],
     double a = dx * t[0] + dy * t[1] + dz * t[2];
     double dd = dx * dx + dy * dy + dz * dz;
     double hl = 0.5 * length;
-    return (a * a <= hl * hl) && (dd - a * a <= radius * radius);
+    double q = dd - a * a, r2 = radius * radius;
+    if (shape == 1) {
+        double e = fabs(a) - (hl - radius);
+        if (e <= 0.0) return q <= r2;
+        return q + e * e <= r2;
+    }
+    return (a * a <= hl * hl) && (q <= r2);
+}
+
+int or_cell_inside(const double c[3], const double X[3], const double t[3],
+                   double length, double radius, int nx, int ny, int nz, int zper)
+{
+    return or_cell_inside_shape(c, X, t, length, radius, 0, nx, ny, nz, zper);
 }
 
 static int wrapi(int i, int n) { return ((i % n) + n) % n; }
@@ -143,6 +162,15 @@ static int wrapi(int i, int n) { return ((i % n) + n) % n; }
 /* cell inside the cylinder satisfies |d|^2 <= (L/2)^2 + r^2 <= (L/2 + r)^2. */
 void or_map(int nx, int ny, int nz, int zper, int np, const double *X, const double *q,
             const double *length, const double *radius, int32_t *pid, int64_t *overlaps)
+{
+    or_map_shapes(nx, ny, nz, zper, np, X, q, length, radius, NULL, pid, overlaps);
+}
+
+/* shape: per-particle shape codes (NULL: all cylinders).  The search box     */
+/* L/2 + r around the centre contains both shapes.                           */
+void or_map_shapes(int nx, int ny, int nz, int zper, int np, const double *X, const double *q,
+                   const double *length, const double *radius, const int32_t *shape, int32_t *pid,
+                   int64_t *overlaps)
 {
     int64_t ncell = (int64_t)nx * ny * nz, ov = 0;
     for (int64_t i = 0; i < ncell; ++i) pid[i] = -1;
@@ -165,7 +193,8 @@ void or_map(int nx, int ny, int nz, int zper, int np, const double *X, const dou
                 for (int kx = lo[0]; kx <= hi[0]; ++kx) {
                     int x = wrapi(kx, nx);
                     double c[3] = {(double)x, (double)y, (double)z};
-                    if (!or_cell_inside(c, X + 3 * p, t, length[p], radius[p], nx, ny, nz, zper))
+                    if (!or_cell_inside_shape(c, X + 3 * p, t, length[p], radius[p], shape ? shape[p] : 0,
+                                              nx, ny, nz, zper))
                         continue;
                     int64_t idx = ((int64_t)z * ny + y) * nx + x;
                     if (pid[idx] < 0) pid[idx] = p;
@@ -269,10 +298,31 @@ static void solve6(double K[6][6], double b[6], double x[6])
 /*   (m I + A) V' + B W'           = m V + F0                                */
 /*   B^T V'       + (I(q) + C) W'  = Lang + M0                               */
 /* after which X, Lang and q advance as in the explicit step.                */
+/* With a constant external load Fe, Me (Eq. ForceDensDiff for the weight):  */
+/* it joins the right-hand side, m V + F0 + Fe and Lang + M0 + Me, and the    */
+/* angular momentum update, Lang' = Lang + M + Me; Fap, Map stay the          */
+/* hydrodynamic force and torque.                                             */
+static void rigid_implicit(const double *s, double mass, double i_par, double i_perp,
+                           const double F0[3], const double M0[3], const double *A,
+                           const double *B, const double *Cm, const double Fe[3],
+                           const double Me[3], int nx, int ny, int nz, int zper, double *out,
+                           double *Fap, double *Map);
+
 void or_rigid_step_implicit(const double *s, double mass, double i_par, double i_perp,
                             const double F0[3], const double M0[3], const double *A,
                             const double *B, const double *Cm, int nx, int ny, int nz,
                             int zper, double *out, double *Fap, double *Map)
+{
+    const double zero[3] = {0.0, 0.0, 0.0};
+    rigid_implicit(s, mass, i_par, i_perp, F0, M0, A, B, Cm, zero, zero, nx, ny, nz, zper, out, Fap,
+                   Map);
+}
+
+static void rigid_implicit(const double *s, double mass, double i_par, double i_perp,
+                           const double F0[3], const double M0[3], const double *A,
+                           const double *B, const double *Cm, const double Fe[3],
+                           const double Me[3], int nx, int ny, int nz, int zper, double *out,
+                           double *Fap, double *Map)
 {
     const double *X = s, *q = s + 3, *V = s + 7, *La = s + 13;
     double t[3];
@@ -287,8 +337,8 @@ void or_rigid_step_implicit(const double *s, double mass, double i_par, double i
             K[3 + i][3 + j] = Iw + Cm[3 * i + j];
         }
     for (int i = 0; i < 3; ++i) {
-        b[i] = mass * V[i] + F0[i];
-        b[3 + i] = La[i] + M0[i];
+        b[i] = mass * V[i] + F0[i] + Fe[i];
+        b[3 + i] = La[i] + M0[i] + Me[i];
     }
     solve6(K, b, x);
     double Vn[3] = {x[0], x[1], x[2]}, Wn[3] = {x[3], x[4], x[5]};
@@ -305,7 +355,7 @@ void or_rigid_step_implicit(const double *s, double mass, double i_par, double i
     double Xn[3], Ln[3];
     for (int k = 0; k < 3; ++k) {
         Xn[k] = wrap_pos(X[k] + Vn[k], n[k], per[k]);
-        Ln[k] = La[k] + Map[k];
+        Ln[k] = La[k] + Map[k] + Me[k];
     }
     double ang = sqrt(Wn[0] * Wn[0] + Wn[1] * Wn[1] + Wn[2] * Wn[2]);
     double dq[4] = {1.0, 0.0, 0.0, 0.0};
@@ -333,6 +383,8 @@ void or_rigid_step_implicit(const double *s, double mass, double i_par, double i
 typedef struct {
     double st[16];          /* X3 q4 V3 W3 Lang3 */
     double length, radius, mass, i_par, i_perp;
+    int shape;              /* 0 cylinder, 1 spherocylinder */
+    double fext[3], mext[3];/* constant external force and torque */
     double F[3], M[3];
     double F0p[3], M0p[3];  /* velocity-free sums of the previous step */
     int have_prev;
@@ -407,14 +459,17 @@ static int64_t remap(or_sim *s, int32_t *pid_out)
     int np = s->nf;
     double *X = (double *)malloc((size_t)(3 * np + 4 * np + 2 * np + 1) * sizeof(double));
     double *q = X + 3 * np, *L = q + 4 * np, *r = L + np;
+    int32_t *shape = (int32_t *)malloc((size_t)(np + 1) * sizeof(int32_t));
     for (int i = 0; i < np; ++i) {
         memcpy(X + 3 * i, s->fib[i].st, 3 * sizeof(double));
         memcpy(q + 4 * i, s->fib[i].st + 3, 4 * sizeof(double));
         L[i] = s->fib[i].length;
         r[i] = s->fib[i].radius;
+        shape[i] = s->fib[i].shape;
     }
     int64_t ov = 0;
-    or_map(s->p.nx, s->p.ny, s->p.nz, s->p.z_periodic, np, X, q, L, r, pid_out, &ov);
+    or_map_shapes(s->p.nx, s->p.ny, s->p.nz, s->p.z_periodic, np, X, q, L, r, shape, pid_out, &ov);
+    free(shape);
     free(X);
     return ov;
 }
@@ -432,9 +487,46 @@ static void surface_velocity(const or_sim *s, const double *st, int x, int y, in
     us[2] = V[2] + (W[0] * d[1] - W[1] * d[0]);
 }
 
+/* Mass and principal moments of inertia (about the axis, and about a      */
+/* transverse axis through the centre) of a homogeneous body of density rho. */
+void or_body_inertia(int shape, double length, double radius, double rho, double out[3])
+{
+    if (shape == 1) {
+        /* spherocylinder: a cylinder of length h = L - 2r and two hemispheres */
+        /* (one sphere of mass ms).  Axial moment: mc r^2/2 + 2 ms r^2/5.      */
+        /* Transverse: the cylinder's mc (3r^2 + h^2)/12; each hemisphere of  */
+        /* mass ms/2 has (2/5)(ms/2) r^2 about a transverse axis through its  */
+        /* flat face, its centroid 3r/8 from that face, which is h/2 from     */
+        /* the centre: by the parallel-axis theorem the pair adds             */
+        /* ms (2r^2/5 - 9r^2/64 + (h/2 + 3r/8)^2) = ms (2r^2/5 + h^2/4 + 3hr/8). */
+        double h = length - 2.0 * radius;
+        double mc = rho * M_PI * radius * radius * h;
+        double ms = rho * (4.0 / 3.0) * M_PI * radius * radius * radius;
+        out[0] = mc + ms;
+        out[1] = mc * radius * radius / 2.0 + 2.0 * ms * radius * radius / 5.0;
+        out[2] = mc * (3.0 * radius * radius + h * h) / 12.0 +
+                 ms * (2.0 * radius * radius / 5.0 + h * h / 4.0 + 3.0 * h * radius / 8.0);
+    } else {
+        double m = rho * M_PI * radius * radius * length;
+        out[0] = m;
+        out[1] = 0.5 * m * radius * radius;
+        out[2] = m * (3.0 * radius * radius + length * length) / 12.0;
+    }
+}
+
 int or_add_fiber(or_sim *s, const double X[3], const double q[4], double length, double radius,
                  double density_ratio, const double V[3], const double W[3])
 {
+    const double zero[3] = {0.0, 0.0, 0.0};
+    return or_add_fiber_ex(s, X, q, length, radius, density_ratio, V, W, 0, zero, zero);
+}
+
+int or_add_fiber_ex(or_sim *s, const double X[3], const double q[4], double length, double radius,
+                    double density_ratio, const double V[3], const double W[3], int shape,
+                    const double Fext[3], const double Mext[3])
+{
+    if (shape != 0 && shape != 1) return -1;
+    if (shape == 1 && !(length >= 2.0 * radius)) return -1;
     if (s->steps != 0) return -1;
     if (s->nf == s->capf) {
         int nc = s->capf ? 2 * s->capf : 8;
@@ -452,11 +544,17 @@ int or_add_fiber(or_sim *s, const double X[3], const double q[4], double length,
     for (int k = 0; k < 3; ++k) f->st[10 + k] = W[k];
     f->length = length;
     f->radius = radius;
-    /* mass and inertia from the geometric cylinder, not the cell count */
-    double rho_p = density_ratio * s->p.rho0;
-    f->mass = rho_p * M_PI * radius * radius * length;
-    f->i_par = 0.5 * f->mass * radius * radius;
-    f->i_perp = f->mass * (3.0 * radius * radius + length * length) / 12.0;
+    f->shape = shape;
+    for (int k = 0; k < 3; ++k) {
+        f->fext[k] = Fext[k];
+        f->mext[k] = Mext[k];
+    }
+    /* mass and inertia from the geometric body, not the cell count */
+    double mi[3];
+    or_body_inertia(shape, length, radius, density_ratio * s->p.rho0, mi);
+    f->mass = mi[0];
+    f->i_par = mi[1];
+    f->i_perp = mi[2];
     double t[3];
     or_fiber_axis(f->st + 3, t);
     double tw = t[0] * W[0] + t[1] * W[1] + t[2] * W[2];
@@ -677,17 +775,21 @@ static void one_step(or_sim *s)
                 }
             }
             double out[16];
-            or_rigid_step_implicit(f->st, f->mass, f->i_par, f->i_perp, F0u, M0u, rd + 12,
-                                   rd + 21, rd + 30, nx, ny, nz, p->z_periodic, out, f->F, f->M);
+            rigid_implicit(f->st, f->mass, f->i_par, f->i_perp, F0u, M0u, rd + 12, rd + 21, rd + 30,
+                           f->fext, f->mext, nx, ny, nz, p->z_periodic, out, f->F, f->M);
             memcpy(f->st, out, 16 * sizeof(double));
         } else {
             for (int k = 0; k < 3; ++k) {
                 f->F[k] = f->has_corr ? rd[k] + cF[k] : rd[k];
                 f->M[k] = f->has_corr ? rd[3 + k] + cM[k] : rd[3 + k];
             }
-            double out[16];
-            or_rigid_step(f->st, f->mass, f->i_par, f->i_perp, f->F, f->M, nx, ny, nz,
-                          p->z_periodic, out);
+            double out[16], Ft[3], Mt[3];
+            for (int k = 0; k < 3; ++k) {   /* with the external load */
+                Ft[k] = f->F[k] + f->fext[k];
+                Mt[k] = f->M[k] + f->mext[k];
+            }
+            or_rigid_step(f->st, f->mass, f->i_par, f->i_perp, Ft, Mt, nx, ny, nz, p->z_periodic,
+                          out);
             memcpy(f->st, out, 16 * sizeof(double));
         }
         for (int k = 0; k < 3; ++k) {

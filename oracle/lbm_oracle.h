@@ -62,8 +62,17 @@ void   or_collide_cell(const double *f, double rho0, double omega_e, double omeg
 void   or_fiber_axis(const double q[4], double t[3]);
 int    or_cell_inside(const double c[3], const double X[3], const double t[3],
                       double length, double radius, int nx, int ny, int nz, int zper);
+/* shape 0: cylinder; 1: spherocylinder (length including the caps) */
+int    or_cell_inside_shape(const double c[3], const double X[3], const double t[3], double length,
+                            double radius, int shape, int nx, int ny, int nz, int zper);
 void   or_map(int nx, int ny, int nz, int zper, int np, const double *X, const double *q,
               const double *length, const double *radius, int32_t *pid, int64_t *overlaps);
+void   or_map_shapes(int nx, int ny, int nz, int zper, int np, const double *X, const double *q,
+                     const double *length, const double *radius, const int32_t *shape,
+                     int32_t *pid, int64_t *overlaps);
+/* mass, axial and transverse moment of inertia of a homogeneous cylinder
+   (shape 0) or spherocylinder (shape 1) of density rho */
+void   or_body_inertia(int shape, double length, double radius, double rho, double out[3]);
 /* one semi-implicit Euler step; state = X[3] q[4] V[3] W[3] Lang[3] */
 void   or_rigid_step(const double *state, double mass, double i_par, double i_perp,
                      const double F[3], const double M[3], int nx, int ny, int nz, int zper,
@@ -83,6 +92,11 @@ or_sim *or_create(const or_params *p);
 void    or_destroy(or_sim *s);
 int     or_add_fiber(or_sim *s, const double X[3], const double q[4], double length,
                      double radius, double density_ratio, const double V[3], const double W[3]);
+/* with a shape (0 cylinder, 1 spherocylinder) and a constant external force
+   Fext and torque Mext added to the hydrodynamic ones in every step */
+int     or_add_fiber_ex(or_sim *s, const double X[3], const double q[4], double length,
+                        double radius, double density_ratio, const double V[3], const double W[3],
+                        int shape, const double Fext[3], const double Mext[3]);
 int     or_set_kinematics(or_sim *s, int id, const double *traj /*[nsteps][13]*/, int64_t nsteps);
 /* add dF, dM to fiber id's momentum-exchange force and torque in the next
    step only (to the velocity-free part for the implicit couplings) */

@@ -45,6 +45,11 @@ def lib():
                                      C.c_int, C.c_int, C.c_int, C.c_int]
         L.or_map.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _dp,
                              _ip, _i64p]
+        L.or_body_inertia.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, _dp]
+        L.or_cell_inside_shape.argtypes = [_dp, _dp, _dp, C.c_double, C.c_double, C.c_int,
+                                           C.c_int, C.c_int, C.c_int, C.c_int]
+        L.or_map_shapes.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp,
+                                    _dp, _ip, _ip, _i64p]
         L.or_rigid_step.argtypes = [_dp, C.c_double, C.c_double, C.c_double, _dp, _dp,
                                     C.c_int, C.c_int, C.c_int, C.c_int, _dp]
         L.or_rigid_step_implicit.argtypes = [_dp, C.c_double, C.c_double, C.c_double, _dp,
@@ -55,6 +60,8 @@ def lib():
         L.or_destroy.argtypes = [C.c_void_p]
         L.or_add_fiber.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_double, C.c_double,
                                    _dp, _dp]
+        L.or_add_fiber_ex.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_double, C.c_double,
+                                      _dp, _dp, C.c_int, _dp, _dp]
         L.or_set_kinematics.argtypes = [C.c_void_p, C.c_int, _dp, C.c_int64]
         L.or_set_correction.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
         L.or_step.argtypes = [C.c_void_p, C.c_int64]
@@ -116,17 +123,40 @@ def fiber_axis(q):
     return t
 
 
-def map_fibers(shape, X, q, length, radius, z_periodic=False):
-    """shape = (nx, ny, nz); returns (pid[nz][ny][nx], overlaps)."""
+SHAPES = {"cylinder": 0, "spherocylinder": 1}
+
+
+def map_fibers(shape, X, q, length, radius, z_periodic=False, shapes=None):
+    """shape = (nx, ny, nz); returns (pid[nz][ny][nx], overlaps).  shapes:
+    per-fiber "cylinder"/"spherocylinder" (default all cylinders)."""
     nx, ny, nz = shape
     X = _arr(X).reshape(-1, 3)
     n = X.shape[0]
     pid = np.zeros((nz, ny, nx), np.int32)
     ov = np.zeros(1, np.int64)
-    lib().or_map(nx, ny, nz, int(z_periodic), n, _d(X), _d(_arr(q, 4 * n)),
-                 _d(_arr(length, n)), _d(_arr(radius, n)), pid.ctypes.data_as(_ip),
-                 ov.ctypes.data_as(_i64p))
+    codes = np.array([SHAPES[k] if isinstance(k, str) else int(k) for k in
+                      (shapes if shapes is not None else ["cylinder"] * n)], np.int32)
+    lib().or_map_shapes(nx, ny, nz, int(z_periodic), n, _d(X), _d(_arr(q, 4 * n)),
+                        _d(_arr(length, n)), _d(_arr(radius, n)), codes.ctypes.data_as(_ip),
+                        pid.ctypes.data_as(_ip), ov.ctypes.data_as(_i64p))
     return pid, int(ov[0])
+
+
+def body_inertia(shape, length, radius, rho):
+    """(mass, I about the axis, I about a transverse axis through the centre)."""
+    out = np.zeros(3)
+    code = SHAPES[shape] if isinstance(shape, str) else int(shape)
+    lib().or_body_inertia(code, float(length), float(radius), float(rho), _d(out))
+    return out
+
+
+def cell_inside(c, X, t, length, radius, shape="cylinder", dims=(1 << 20, 1 << 20, 1 << 20),
+                z_periodic=True):
+    """The cell-centre predicate for one cell and one fiber axis t."""
+    code = SHAPES[shape] if isinstance(shape, str) else int(shape)
+    return bool(lib().or_cell_inside_shape(_d(_arr(c, 3)), _d(_arr(X, 3)), _d(_arr(t, 3)),
+                                           float(length), float(radius), code, dims[0], dims[1],
+                                           dims[2], int(z_periodic)))
 
 
 def rigid_step(state, mass, i_par, i_perp, F, M, shape=(1 << 20, 1 << 20, 1 << 20),
@@ -164,10 +194,12 @@ class Sim:
             lib().or_destroy(h)
             self._h = None
 
-    def add_fiber(self, X, q, length, radius, density_ratio=1.0, V=(0, 0, 0), W=(0, 0, 0)):
-        r = lib().or_add_fiber(self._h, _d(_arr(X, 3)), _d(_arr(q, 4)), float(length),
-                               float(radius), float(density_ratio), _d(_arr(V, 3)),
-                               _d(_arr(W, 3)))
+    def add_fiber(self, X, q, length, radius, density_ratio=1.0, V=(0, 0, 0), W=(0, 0, 0),
+                  shape="cylinder", force=(0, 0, 0), torque=(0, 0, 0)):
+        code = SHAPES[shape] if isinstance(shape, str) else int(shape)
+        r = lib().or_add_fiber_ex(self._h, _d(_arr(X, 3)), _d(_arr(q, 4)), float(length),
+                                  float(radius), float(density_ratio), _d(_arr(V, 3)),
+                                  _d(_arr(W, 3)), code, _d(_arr(force, 3)), _d(_arr(torque, 3)))
         if r < 0:
             raise ValueError("oracle rejected the fiber (code %d)" % r)
         return r

@@ -560,6 +560,13 @@ lbm_status lbm_add_fiber(lbm_ctx *c, const lbm_fiber *f, int32_t *id)
     if (c->closure) return fail(c, LBM_E_STATE, "detach the closure before adding fibers");
     if (!(f->length > 0.0) || !(f->radius > 0.0) || !(f->density_ratio > 0.0))
         return fail(c, LBM_E_ARG, "length, radius and density_ratio must be positive");
+    if (f->shape != LBM_SHAPE_CYLINDER && f->shape != LBM_SHAPE_SPHEROCYLINDER)
+        return fail(c, LBM_E_ARG, "unknown fiber shape");
+    if (f->shape == LBM_SHAPE_SPHEROCYLINDER && !(f->length >= 2.0 * f->radius))
+        return fail(c, LBM_E_ARG, "a spherocylinder needs length >= 2 radius");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(f->force[k]) || !std::isfinite(f->torque[k]))
+            return fail(c, LBM_E_ARG, "non-finite external force or torque");
     const double qn = std::sqrt(f->quat[0] * f->quat[0] + f->quat[1] * f->quat[1] +
                                 f->quat[2] * f->quat[2] + f->quat[3] * f->quat[3]);
     if (!(qn > 0.0)) return fail(c, LBM_E_ARG, "zero quaternion");
@@ -570,7 +577,10 @@ lbm_status lbm_add_fiber(lbm_ctx *c, const lbm_fiber *f, int32_t *id)
     for (int k = 0; k < 3; ++k) {
         if (!(f->center[k] >= 0.0 && f->center[k] < n[k]))
             return fail(c, LBM_E_GEOM, "centre outside the domain");
-        const double ext = 0.5 * f->length * std::fabs(t[k]) + f->radius * std::sqrt(std::fmax(0.0, 1.0 - t[k] * t[k]));
+        const double ext = f->shape == LBM_SHAPE_SPHEROCYLINDER
+                               ? (0.5 * f->length - f->radius) * std::fabs(t[k]) + f->radius
+                               : 0.5 * f->length * std::fabs(t[k]) +
+                                     f->radius * std::sqrt(std::fmax(0.0, 1.0 - t[k] * t[k]));
         const bool per = k < 2 || c->p.z_periodic;
         if (per && !(f->length * 0.5 + f->radius < 0.5 * n[k] - 1.0))
             return fail(c, LBM_E_GEOM, "fiber longer than half the periodic domain");
@@ -578,13 +588,8 @@ lbm_status lbm_add_fiber(lbm_ctx *c, const lbm_fiber *f, int32_t *id)
             return fail(c, LBM_E_GEOM, "fiber within one cell of a wall");
     }
     if ((c->np + 1) * NACC * 8 > 65536) return fail(c, LBM_E_ARG, "at most 302 fibers per context");
-    PConst pc{};
-    pc.length = f->length;
-    pc.radius = f->radius;
-    pc.mass = f->density_ratio * c->p.rho0 * M_PI * f->radius * f->radius * f->length;
-    pc.i_par = 0.5 * pc.mass * f->radius * f->radius;
-    pc.i_perp = pc.mass * (3.0 * f->radius * f->radius + f->length * f->length) / 12.0;
-    pc.traj_off = -1;
+    const PConst pc = fiber_constants(f->length, f->radius, f->density_ratio * c->p.rho0, f->shape, f->force,
+                                      f->torque);
     c->fib.push_back(*f);
     c->pch.push_back(pc);
     c->traj_h.emplace_back();

@@ -476,6 +476,10 @@ static const char *check_case(const lbm_batch_case &k)
     if (!(k.tau > 0.5) || !(std::fabs(k.wall_u) < 0.1)) return "tau or wall_u out of range";
     const lbm_fiber &f = k.fiber;
     if (!(f.length > 0.0) || !(f.radius > 0.0) || !(f.density_ratio > 0.0)) return "bad fiber size";
+    if (f.shape != LBM_SHAPE_CYLINDER && f.shape != LBM_SHAPE_SPHEROCYLINDER) return "unknown fiber shape";
+    if (f.shape == LBM_SHAPE_SPHEROCYLINDER && !(f.length >= 2.0 * f.radius)) return "spherocylinder shorter than 2 r";
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(f.force[i]) || !std::isfinite(f.torque[i])) return "non-finite external load";
     const double qn = std::sqrt(f.quat[0] * f.quat[0] + f.quat[1] * f.quat[1] + f.quat[2] * f.quat[2] +
                                 f.quat[3] * f.quat[3]);
     if (!(qn > 0.0)) return "zero quaternion";
@@ -485,7 +489,10 @@ static const char *check_case(const lbm_batch_case &k)
     const int n[3] = {k.nx, k.ny, k.nz};
     for (int i = 0; i < 3; ++i) {
         if (!(f.center[i] >= 0.0 && f.center[i] < n[i])) return "fiber centre outside the domain";
-        const double ext = 0.5 * f.length * std::fabs(t[i]) + f.radius * std::sqrt(std::fmax(0.0, 1.0 - t[i] * t[i]));
+        const double ext = f.shape == LBM_SHAPE_SPHEROCYLINDER
+                               ? (0.5 * f.length - f.radius) * std::fabs(t[i]) + f.radius
+                               : 0.5 * f.length * std::fabs(t[i]) +
+                                     f.radius * std::sqrt(std::fmax(0.0, 1.0 - t[i] * t[i]));
         if (i < 2 && !(f.length * 0.5 + f.radius < 0.5 * n[i] - 1.0)) return "fiber longer than half the periodic domain";
         if (i == 2 && (f.center[i] - ext < 1.0 || f.center[i] + ext > n[i] - 2.0)) return "fiber within one cell of a wall";
     }
@@ -772,14 +779,8 @@ lbm_status lbm_batch_create(const lbm_batch_params *p, const lbm_batch_case *cas
         cd.list_off = uint32_t(loff);
         cd.list_cap = uint32_t(cap);
         loff += cd.list_cap;
-        PConst &pc = cd.pc;
-        pc.length = fb.length;
-        pc.radius = fb.radius;
-        pc.mass = fb.density_ratio * p->rho0 * M_PI * fb.radius * fb.radius * fb.length;
-        pc.i_par = 0.5 * pc.mass * fb.radius * fb.radius;
-        pc.i_perp = pc.mass * (3.0 * fb.radius * fb.radius + fb.length * fb.length) / 12.0;
-        pc.traj_off = -1;
-        pc.traj_n = 0;
+        cd.pc = fiber_constants(fb.length, fb.radius, fb.density_ratio * p->rho0, fb.shape, fb.force, fb.torque);
+        const PConst &pc = cd.pc;
         b->ps0[i] = make_state_b(fb, pc);
     }
     if (loff >= 4294967295ull) return bail(LBM_E_ARG, "boundary lists too large");

@@ -68,7 +68,39 @@ struct PConst {
     double length, radius, mass, i_par, i_perp;
     int64_t traj_off;      // offset (rows) into the trajectory array, or -1
     int64_t traj_n;        // rows prescribed
+    int32_t shape;         // 0 cylinder, 1 spherocylinder (L including the caps)
+    double fext[3], mext[3];   // constant external force and torque
 };
+// Constants of a fiber (host side): mass and principal moments of inertia
+// of the cylinder or spherocylinder of the given density, external load.
+inline PConst fiber_constants(double length, double radius, double density, int shape, const double force[3],
+                              const double torque[3])
+{
+    const double pi = 3.14159265358979323846;
+    PConst pc{};
+    pc.length = length;
+    pc.radius = radius;
+    pc.shape = shape;
+    const double r2 = radius * radius;
+    if (shape == 1) {
+        const double h = length - 2.0 * radius;
+        const double mc = density * pi * r2 * h, ms = density * 4.0 / 3.0 * pi * r2 * radius;
+        pc.mass = mc + ms;
+        pc.i_par = 0.5 * mc * r2 + 0.4 * ms * r2;
+        pc.i_perp = mc * (3.0 * r2 + h * h) / 12.0 + ms * (0.4 * r2 + 0.25 * h * h + 0.375 * h * radius);
+    } else {
+        pc.mass = density * pi * radius * radius * length;
+        pc.i_par = 0.5 * pc.mass * radius * radius;
+        pc.i_perp = pc.mass * (3.0 * radius * radius + length * length) / 12.0;
+    }
+    for (int k = 0; k < 3; ++k) {
+        pc.fext[k] = force ? force[k] : 0.0;
+        pc.mext[k] = torque ? torque[k] : 0.0;
+    }
+    pc.traj_off = -1;
+    pc.traj_n = 0;
+    return pc;
+}
 struct Box {               // cells lo[k] .. lo[k]+len[k]-1 (wrapped where periodic)
     int32_t lo[3];
     int32_t len[3];

@@ -33,9 +33,12 @@ __device__ __forceinline__ void axis_of(const double q[4], double t[3])
     t[2] = 2.0 * (x * z - w * y);
 }
 
-// Cell centre (cx, cy, cz) inside the cylinder: with d the minimum-image
-// vector from the centre and a = d.t, require a^2 <= (L/2)^2 and
-// |d|^2 - a^2 <= r^2.  FP64, no contraction, fixed evaluation order.
+// Cell centre (cx, cy, cz) inside the fiber: with d the minimum-image
+// vector from the centre, a = d.t and q = |d|^2 - a^2 (squared distance from
+// the axis line), the cylinder requires a^2 <= (L/2)^2 and q <= r^2; the
+// spherocylinder, with e = |a| - (L/2 - r) beyond the cylindrical part,
+// q <= r^2 where e <= 0 and q + e^2 <= r^2 in the caps.  FP64, no
+// contraction, fixed evaluation order.
 __device__ __forceinline__ bool inside(const PState &s, const PConst &c, double cx, double cy,
                                        double cz, const Geo &g)
 {
@@ -45,7 +48,12 @@ __device__ __forceinline__ bool inside(const PState &s, const PConst &c, double 
     const double a = dx * s.t[0] + dy * s.t[1] + dz * s.t[2];
     const double dd = dx * dx + dy * dy + dz * dz;
     const double hl = 0.5 * c.length;
-    return (a * a <= hl * hl) && (dd - a * a <= c.radius * c.radius);
+    const double q = dd - a * a, r2 = c.radius * c.radius;
+    if (c.shape == 1) {
+        const double e = fabs(a) - (hl - c.radius);
+        return e <= 0.0 ? q <= r2 : q + e * e <= r2;
+    }
+    return (a * a <= hl * hl) && (q <= r2);
 }
 
 // box (dilated AABB) of the cells a fiber can own or border
@@ -55,7 +63,9 @@ __device__ __forceinline__ void fiber_box(const PState &s, const PConst &c, cons
     const uint32_t n[3] = {g.nx, g.ny, g.nz};
     for (int k = 0; k < 3; ++k) {
         const double tk = s.t[k];
-        const double ext = 0.5 * c.length * fabs(tk) + c.radius * sqrt(fmax(0.0, 1.0 - tk * tk));
+        const double ext = c.shape == 1
+                               ? (0.5 * c.length - c.radius) * fabs(tk) + c.radius
+                               : 0.5 * c.length * fabs(tk) + c.radius * sqrt(fmax(0.0, 1.0 - tk * tk));
         // centre expressed in the frame of Xref (minimum image), so boxes of
         // successive poses can be merged without a wrap in between
         const bool per = k < 2 || g.zper;
@@ -259,8 +269,10 @@ __device__ __forceinline__ void unpack(const double *acc, double A[3][3], double
 
 // Advance one fiber from state s with the momentum-exchange sums acc.
 // Semi-implicit Euler, dt = 1 (the paper leaves the integrator open):
-//   V' = V + F/m, X' = X + V', Lang' = Lang + M, W' = I(q)^-1 Lang',
-//   q' = normalize(exp(W'/2) (x) q).
+//   V' = V + (F + Fe)/m, X' = X + V', Lang' = Lang + M + Me,
+//   W' = I(q)^-1 Lang', q' = normalize(exp(W'/2) (x) q),
+// with the constant external load Fe, Me of the fiber (c.fext, c.mext);
+// F, M (reported) are the hydrodynamic force and torque.
 // coupling 1 (explicit): F, M at the old velocities.  Coupling 0 and 2
 // evaluate F = F0 - A V' - B W', M = M0 - B^T V' - C W' at the new
 // velocities and solve the 6x6 system for (V', W'); coupling 0 takes for
@@ -325,8 +337,8 @@ __device__ __forceinline__ void rigid_update(const PState &s, const PConst &c, c
                 K[3 + i][3 + j] = Iw + C[i][j];
             }
         for (int i = 0; i < 3; ++i) {
-            b[i] = c.mass * s.V[i] + F0u[i];
-            b[3 + i] = s.L[i] + M0u[i];
+            b[i] = c.mass * s.V[i] + F0u[i] + c.fext[i];
+            b[3 + i] = s.L[i] + M0u[i] + c.mext[i];
         }
         chol6(K, b, x);
         for (int i = 0; i < 3; ++i) {
@@ -342,11 +354,11 @@ __device__ __forceinline__ void rigid_update(const PState &s, const PConst &c, c
             F[i] = f;
             M[i] = m;
         }
-        for (int i = 0; i < 3; ++i) Ln[i] = s.L[i] + M[i];
+        for (int i = 0; i < 3; ++i) Ln[i] = s.L[i] + M[i] + c.mext[i];
     } else {
         for (int i = 0; i < 3; ++i) {
-            Vn[i] = s.V[i] + F[i] / c.mass;
-            Ln[i] = s.L[i] + M[i];
+            Vn[i] = s.V[i] + (F[i] + c.fext[i]) / c.mass;
+            Ln[i] = s.L[i] + (M[i] + c.mext[i]);
         }
         const double tl = s.t[0] * Ln[0] + s.t[1] * Ln[1] + s.t[2] * Ln[2];
         for (int i = 0; i < 3; ++i)

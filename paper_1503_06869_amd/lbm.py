@@ -61,7 +61,12 @@ class lbm_params(C.Structure):
 class lbm_fiber(C.Structure):
     _fields_ = [("center", C.c_double * 3), ("quat", C.c_double * 4), ("length", C.c_double),
                 ("radius", C.c_double), ("density_ratio", C.c_double),
-                ("vel", C.c_double * 3), ("omega", C.c_double * 3)]
+                ("vel", C.c_double * 3), ("omega", C.c_double * 3),
+                ("shape", C.c_int32), ("reserved", C.c_int32),
+                ("force", C.c_double * 3), ("torque", C.c_double * 3)]
+
+
+SHAPES = {"cylinder": 0, "spherocylinder": 1}
 
 
 class lbm_info(C.Structure):
@@ -243,13 +248,11 @@ class Context:
 
     __del__ = close
 
-    def add_fiber(self, X, q, length, radius, density_ratio=1.0, V=(0, 0, 0), W=(0, 0, 0)):
-        f = lbm_fiber()
-        f.center = (C.c_double * 3)(*_f64(X, 3))
-        f.quat = (C.c_double * 4)(*_f64(q, 4))
-        f.length, f.radius, f.density_ratio = float(length), float(radius), float(density_ratio)
-        f.vel = (C.c_double * 3)(*_f64(V, 3))
-        f.omega = (C.c_double * 3)(*_f64(W, 3))
+    def add_fiber(self, X, q, length, radius, density_ratio=1.0, V=(0, 0, 0), W=(0, 0, 0),
+                  shape="cylinder", force=(0, 0, 0), torque=(0, 0, 0)):
+        """shape: "cylinder" or "spherocylinder" (length including the caps);
+        force, torque: constant external load added in every step."""
+        f = _fiber_struct(X, q, length, radius, density_ratio, V, W, shape, force, torque)
         i = C.c_int32()
         self._chk(load().lbm_add_fiber(self._h, C.byref(f), C.byref(i)))
         self.nfibers += 1
@@ -340,20 +343,26 @@ class Context:
         return ms.value, n.value
 
 
-def _fiber_struct(X, q, length, radius, density_ratio=1.0, V=(0, 0, 0), W=(0, 0, 0)):
+def _fiber_struct(X, q, length, radius, density_ratio=1.0, V=(0, 0, 0), W=(0, 0, 0), shape="cylinder",
+                  force=(0, 0, 0), torque=(0, 0, 0)):
     f = lbm_fiber()
     f.center = (C.c_double * 3)(*_f64(X, 3))
     f.quat = (C.c_double * 4)(*_f64(q, 4))
     f.length, f.radius, f.density_ratio = float(length), float(radius), float(density_ratio)
     f.vel = (C.c_double * 3)(*_f64(V, 3))
     f.omega = (C.c_double * 3)(*_f64(W, 3))
+    f.shape = SHAPES[shape] if isinstance(shape, str) else int(shape)
+    f.reserved = 0
+    f.force = (C.c_double * 3)(*_f64(force, 3))
+    f.torque = (C.c_double * 3)(*_f64(torque, 3))
     return f
 
 
 class Batch:
     """Many independent one-fiber shear cells advanced by one persistent
     launch (owns an lbm_batch).  ``cases``: objects with nx, ny, nz, tau,
-    wall_u and fibers[0] (X, q, length, radius, density_ratio, V, W)."""
+    wall_u and fibers[0] (X, q, length, radius, density_ratio, V, W, and
+    optionally shape, force, torque)."""
 
     def __init__(self, cases, storage="f32", collision="trt", magic=3.0 / 16.0, rho0=1.0,
                  init_couette=True, coupling="implicit", fp16_scale_log2=14,
@@ -375,7 +384,9 @@ class Batch:
             fb = sc.fibers[0]
             arr[i].nx, arr[i].ny, arr[i].nz = sc.nx, sc.ny, sc.nz
             arr[i].tau, arr[i].wall_u = sc.tau, sc.wall_u
-            arr[i].fiber = _fiber_struct(fb.X, fb.q, fb.length, fb.radius, fb.density_ratio, fb.V, fb.W)
+            arr[i].fiber = _fiber_struct(fb.X, fb.q, fb.length, fb.radius, fb.density_ratio, fb.V, fb.W,
+                                         getattr(fb, "shape", "cylinder"), getattr(fb, "force", (0, 0, 0)),
+                                         getattr(fb, "torque", (0, 0, 0)))
         h = C.c_void_p()
         r = L.lbm_batch_create(C.byref(p), arr, len(cases), C.byref(h))
         if r != LBM_OK:

@@ -293,6 +293,122 @@ def test_mapping_overlap_lowest_id_wins():
     assert (pid == 0).sum() == 81 and (pid == 1).sum() + ov == 81  # 9 x 9 cells each
 
 
+# ---------------------------------------------------------------- spherocylinder and external load
+def _unit(rng):
+    v = rng.normal(size=3)
+    return v / np.linalg.norm(v)
+
+
+def _quat_to(t):
+    """A unit quaternion whose rotation maps e_x to the unit vector t."""
+    ax = np.cross([1.0, 0.0, 0.0], t)
+    s = np.linalg.norm(ax)
+    if s < 1e-12:
+        return np.array([1.0, 0, 0, 0]) if t[0] > 0 else np.array([0.0, 0, 0, 1])
+    ang = np.arctan2(s, t[0])
+    return np.r_[np.cos(ang / 2), np.sin(ang / 2) * ax / s]
+
+
+def test_spherocylinder_predicate_is_the_distance_to_the_axis_segment():
+    """Sec. 2: the particles are spherocylinders, L including the caps, i.e.
+    the points within r of an axis segment of length L - 2r.  The oracle's
+    cell predicate against that definition written as a point-segment
+    distance, for random points away from the surface (|dist - r| > 1e-9),
+    including the sphere L = 2r."""
+    rng = np.random.default_rng(5)
+    checked = 0
+    for trial in range(24):
+        t = _unit(rng)
+        X = rng.uniform(20, 40, 3)
+        r = rng.uniform(0.5, 3.0)
+        L = 2 * r if trial == 0 else rng.uniform(2 * r, 20.0)
+        pts = X + rng.uniform(-0.5 * L - r - 1, 0.5 * L + r + 1, (300, 3))
+        d = pts - X
+        a = np.clip(d @ t, -(0.5 * L - r), 0.5 * L - r)
+        dist = np.linalg.norm(d - a[:, None] * t[None, :], axis=1)
+        for pt, dd in zip(pts, dist):
+            if abs(dd - r) <= 1e-9:
+                continue
+            assert O.cell_inside(pt, X, t, L, r, "spherocylinder") == (dd <= r)
+            checked += 1
+    assert checked > 7000
+
+
+def test_spherocylinder_cell_count_converges_to_its_volume():
+    """Obstacle cells (Sec. 4.2) of a spherocylinder approach its volume
+    pi r^2 (L - 2r) + (4/3) pi r^3 as the resolution grows."""
+    t = np.array([0.6, 0.48, 0.64])
+    q = _quat_to(t)
+    np.testing.assert_allclose(O.fiber_axis(q), t, atol=1e-14)
+    errs = []
+    for scale in (2, 4, 8):
+        L, r = 6.0 * scale, 1.0 * scale
+        n = int(L + 4 * r + 8)
+        pid, _ = O.map_fibers((n, n, n), [[n / 2 + 0.3, n / 2 - 0.2, n / 2 + 0.1]], q, [L], [r],
+                              shapes=["spherocylinder"])
+        vol = np.pi * r * r * (L - 2 * r) + 4.0 / 3.0 * np.pi * r ** 3
+        errs.append(abs((pid == 0).sum() / vol - 1))
+    assert errs[-1] < 0.02 and errs[-1] < errs[0]
+
+
+@pytest.mark.parametrize("shape", ["cylinder", "spherocylinder"])
+def test_body_mass_and_inertia_by_quadrature(shape):
+    """Mass and principal moments of the homogeneous body against a midpoint
+    quadrature of its indicator (axis along x): I_par = int rho (y^2 + z^2),
+    I_perp = int rho (x^2 + z^2) about the centre."""
+    L, r, rho, h = 9.0, 2.0, 1.3, 0.04
+    xs = np.arange(-L / 2 + h / 2, L / 2, h)
+    ys = np.arange(-r + h / 2, r, h)
+    x, y, z = np.meshgrid(xs, ys, ys, indexing="ij")
+    rad2 = y * y + z * z
+    if shape == "cylinder":
+        inside = rad2 <= r * r
+    else:
+        e = np.maximum(np.abs(x) - (L / 2 - r), 0.0)
+        inside = rad2 + e * e <= r * r
+    dv = h ** 3
+    m = rho * inside.sum() * dv
+    ipar = rho * (rad2 * inside).sum() * dv
+    iperp = rho * ((x * x + z * z) * inside).sum() * dv
+    ref = O.body_inertia(shape, L, r, rho)
+    np.testing.assert_allclose(ref, [m, ipar, iperp], rtol=3e-3)
+
+
+def test_external_force_enters_the_momentum_budget():
+    """Eq. ForceDensDiff adds a constant force to the particle.  With the
+    explicit coupling the momentum-exchange force is exactly the momentum its
+    links take from the fluid (Eqs. LBMMovWall and LBMhydrodynForce), so in a
+    fully periodic box fluid plus particle momentum grows by the external
+    force every step, to rounding, while no cell changes owner; an external
+    torque does not enter the linear budget."""
+    n = 24
+    sim = O.Sim(n, n, n, tau=0.8, z_periodic=True, coupling="explicit")
+    Fe = np.array([2e-3, -1e-3, 5e-4])
+    Me = np.array([1e-3, 2e-3, -1e-3])
+    L, r = 10.0, 2.0
+    sim.add_fiber([12.2, 11.7, 12.4], _quat_to(np.array([0.3, 0.8, 0.52]) / np.linalg.norm([0.3, 0.8, 0.52])),
+                  L, r, 1.0, shape="spherocylinder", force=Fe, torque=Me)
+    c = O.lattice()[0].astype(np.float64)
+    mass = O.body_inertia("spherocylinder", L, r, 1.0)[0]
+
+    def total():
+        f = sim.populations()
+        _, _, _, pid = sim.fields()
+        pf = np.einsum("qa,qzyx->a", c, f * (pid < 0)[None])
+        _, _, V, _ = sim.fiber_state()
+        return pf + mass * V[0], pid
+
+    p0, pid0 = total()
+    for s in range(6):
+        sim.step(1)
+        p1, pid1 = total()
+        assert np.array_equal(pid1, pid0), s
+        np.testing.assert_allclose(p1 - p0, Fe, rtol=0, atol=1e-10)
+        p0 = p1
+    _, _, V, W = sim.fiber_state()
+    assert np.linalg.norm(W[0]) > 0.0
+
+
 # ---------------------------------------------------------------- P13 rigid body
 def test_quaternion_update_constant_rotation():
     """Rigid update (Sec. 4.3; integrator is this project's reading): with no
