@@ -74,9 +74,11 @@ double or_omega_odd(double tau, double magic, int srt)
 /* lambda_e = -omega_e, lambda_o = -omega_o.  With a body force g the        */
 /* velocity carries the half-force shift and the odd part receives           */
 /* (1 - omega_o/2) 3 w rho0 c.g; the paper writes no forcing term, this is   */
-/* the reading used for the Poiseuille and drag pins only.                   */
-void or_collide_cell(const double *f, double rho0, double omega_e, double omega_o,
-                     const double g[3], double *fpost)
+/* the reading used for the Poiseuille and drag pins only.  ubar is the      */
+/* momentum stabilization's shift (Sec. 4.1): the equilibrium is evaluated   */
+/* at u - ubar; it is zero without stabilization.                            */
+void or_collide_cell_shift(const double *f, double rho0, double omega_e, double omega_o,
+                           const double g[3], const double ubar[3], double *fpost)
 {
     double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
     for (int q = 0; q < Q; ++q) {
@@ -84,7 +86,7 @@ void or_collide_cell(const double *f, double rho0, double omega_e, double omega_
         for (int k = 0; k < 3; ++k) j[k] += CV[q][k] * f[q];
     }
     double u[3];
-    for (int k = 0; k < 3; ++k) u[k] = j[k] / rho0 + 0.5 * g[k];
+    for (int k = 0; k < 3; ++k) u[k] = j[k] / rho0 + 0.5 * g[k] - ubar[k];
     double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     for (int q = 0; q < Q; ++q) {
         int qb = opposite(q);
@@ -98,6 +100,13 @@ void or_collide_cell(const double *f, double rho0, double omega_e, double omega_
         fpost[q] = f[q] - omega_e * (fe - feq_e) - omega_o * (fo - feq_o)
                  + (1.0 - 0.5 * omega_o) * 3.0 * w * rho0 * cg;
     }
+}
+
+void or_collide_cell(const double *f, double rho0, double omega_e, double omega_o,
+                     const double g[3], double *fpost)
+{
+    const double zero[3] = {0.0, 0.0, 0.0};
+    or_collide_cell_shift(f, rho0, omega_e, omega_o, g, zero, fpost);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -614,11 +623,45 @@ static void record(or_sim *s)
     }
 }
 
+int64_t or_mean_velocity(const or_sim *s, double ubar[3])
+{
+    const or_params *p = &s->p;
+    const int ny = p->ny, nz = p->nz;
+    /* per-plane partial sums, then added over z in order (thread-count independent) */
+    double *part = (double *)calloc((size_t)nz * 4, sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                int64_t c = cidx(s, x, y, z);
+                if (s->flag[c]) continue;
+                double *a = part + 4 * z;
+                for (int q = 0; q < Q; ++q) {
+                    double fq = *slot(s->fa, s, q, c);
+                    for (int k = 0; k < 3; ++k) a[k] += CV[q][k] * fq;
+                }
+                a[3] += 1.0;
+            }
+    double j[3] = {0.0, 0.0, 0.0}, n = 0.0;
+    for (int z = 0; z < nz; ++z) {
+        for (int k = 0; k < 3; ++k) j[k] += part[4 * z + k];
+        n += part[4 * z + 3];
+    }
+    free(part);
+    for (int k = 0; k < 3; ++k) ubar[k] = n > 0.0 ? j[k] / (n * p->rho0) + 0.5 * p->g[k] : 0.0;
+    return (int64_t)n;
+}
+
 static void one_step(or_sim *s)
 {
     const or_params *p = &s->p;
     const int nx = p->nx, ny = p->ny, nz = p->nz;
     const double rho0 = p->rho0;
+
+    /* 0. momentum stabilization (Sec. 4.1): the mean fluid velocity of the */
+    /*    current state, subtracted in every cell's equilibrium below.      */
+    double ubar[3] = {0.0, 0.0, 0.0};
+    if (p->stabilize) or_mean_velocity(s, ubar);
 
     /* 1. collide every fluid cell: fa -> ft */
 #pragma omp parallel for schedule(static)
@@ -626,7 +669,7 @@ static void one_step(or_sim *s)
         if (s->flag[c]) continue;
         double f[Q], fp[Q];
         for (int q = 0; q < Q; ++q) f[q] = *slot(s->fa, s, q, c);
-        or_collide_cell(f, rho0, s->omega_e, s->omega_o, p->g, fp);
+        or_collide_cell_shift(f, rho0, s->omega_e, s->omega_o, p->g, ubar, fp);
         for (int q = 0; q < Q; ++q) *slot(s->ft, s, q, c) = fp[q];
     }
 

@@ -51,6 +51,9 @@ typedef struct {
                              velocity-free part averaged over this and the previous step;
                           1: fully explicit, every term at the old velocity;
                           2: as 0 without the two-step average */
+    int stabilize;     /* 1: momentum stabilization (Sec. 4.1, periodic domains under a
+                          constant particle force): the mean velocity of all fluid cells
+                          is subtracted from the velocity of every cell's equilibrium */
 } or_params;
 
 /* ---- building blocks (exposed so the tests can pin them one by one) ---- */
@@ -59,6 +62,9 @@ void   or_feq(double rho, double rho0, const double u[3], double *feq /*[19]*/);
 double or_omega_odd(double tau, double magic, int srt);
 void   or_collide_cell(const double *f, double rho0, double omega_e, double omega_o,
                        const double g[3], double *fpost);
+/* as or_collide_cell, with the equilibrium taken at the velocity u - ubar */
+void   or_collide_cell_shift(const double *f, double rho0, double omega_e, double omega_o,
+                             const double g[3], const double ubar[3], double *fpost);
 void   or_fiber_axis(const double q[4], double t[3]);
 int    or_cell_inside(const double c[3], const double X[3], const double t[3],
                       double length, double radius, int nx, int ny, int nz, int zper);
@@ -110,6 +116,9 @@ void    or_get_fiber_state(const or_sim *s, double *X, double *q, double *V, dou
 void    or_get_force_torque(const or_sim *s, double *F, double *M);
 int64_t or_get_history(const or_sim *s, int64_t first, int64_t count, double *out);
 int64_t or_overlaps(const or_sim *s);
+/* mean velocity u = sum_q c_q f_q / rho0 + g/2 over the fluid cells of the current state
+   (the quantity the momentum stabilization subtracts); returns the fluid cell count */
+int64_t or_mean_velocity(const or_sim *s, double ubar[3]);
 int64_t or_steps_done(const or_sim *s);
 int     or_nfibers(const or_sim *s);
 

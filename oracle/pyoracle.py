@@ -24,7 +24,7 @@ class Params(C.Structure):
                 ("z_periodic", C.c_int), ("srt", C.c_int),
                 ("tau", C.c_double), ("magic", C.c_double), ("rho0", C.c_double),
                 ("wall_u", C.c_double), ("g", C.c_double * 3), ("init_couette", C.c_int),
-                ("coupling", C.c_int)]
+                ("coupling", C.c_int), ("stabilize", C.c_int)]
 
 
 def lib():
@@ -40,6 +40,9 @@ def lib():
         L.or_omega_odd.argtypes = [C.c_double, C.c_double, C.c_int]
         L.or_omega_odd.restype = C.c_double
         L.or_collide_cell.argtypes = [_dp, C.c_double, C.c_double, C.c_double, _dp, _dp]
+        L.or_collide_cell_shift.argtypes = [_dp, C.c_double, C.c_double, C.c_double, _dp, _dp, _dp]
+        L.or_mean_velocity.argtypes = [C.c_void_p, _dp]
+        L.or_mean_velocity.restype = C.c_int64
         L.or_fiber_axis.argtypes = [_dp, _dp]
         L.or_cell_inside.argtypes = [_dp, _dp, _dp, C.c_double, C.c_double,
                                      C.c_int, C.c_int, C.c_int, C.c_int]
@@ -179,9 +182,9 @@ class Sim:
 
     def __init__(self, nx, ny, nz, tau=0.8, magic=3.0 / 16.0, wall_u=0.0, rho0=1.0,
                  z_periodic=False, srt=False, g=(0.0, 0.0, 0.0), init_couette=False,
-                 coupling="implicit"):
+                 coupling="implicit", stabilize=False):
         p = Params(nx, ny, nz, int(z_periodic), int(srt), tau, magic, rho0, wall_u,
-                   (C.c_double * 3)(*g), int(init_couette), COUPLING[coupling])
+                   (C.c_double * 3)(*g), int(init_couette), COUPLING[coupling], int(stabilize))
         self.shape = (nx, ny, nz)
         self.ncell = nx * ny * nz
         self._h = lib().or_create(C.byref(p))
@@ -226,6 +229,12 @@ class Sim:
     @property
     def overlaps(self):
         return lib().or_overlaps(self._h)
+
+    def mean_velocity(self):
+        """Mean fluid velocity of the current state and the fluid cell count."""
+        u = np.zeros(3)
+        n = lib().or_mean_velocity(self._h, _d(u))
+        return u, int(n)
 
     def populations(self):
         nx, ny, nz = self.shape

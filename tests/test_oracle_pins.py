@@ -409,6 +409,109 @@ def test_external_force_enters_the_momentum_budget():
     assert np.linalg.norm(W[0]) > 0.0
 
 
+# ------------------------------------------------- momentum stabilization (Sec. 4.1)
+def _periodic_random_box(n, tau, seed, srt=False, g=(0.0, 0.0, 0.0)):
+    sim = O.Sim(n, n, n, tau=tau, z_periodic=True, srt=srt, g=g, stabilize=True)
+    c, w, _ = O.lattice()
+    rng = np.random.default_rng(seed)
+    f = w[:, None, None, None] * (1.0 + 0.2 * rng.standard_normal((19, n, n, n)))
+    f += 0.01 * w[:, None, None, None] * 3.0 * np.einsum("qa,a->q", c, [0.8, -0.5, 0.3])[:, None, None, None]
+    sim.set_populations(f)
+    return sim, c.astype(np.float64)
+
+
+@pytest.mark.parametrize("tau,srt", [(6.0, False), (0.8, False), (0.9, True)])
+def test_stabilized_total_momentum_decays_by_one_minus_omega_odd(tau, srt):
+    """Subtracting the mean fluid velocity u_bar from every equilibrium
+    velocity changes each cell's momentum by -omega_o rho0 u_bar in the
+    collision (the odd equilibrium's first moment is rho0 (u - u_bar)), and
+    streaming in a fully periodic box conserves it: the total momentum obeys
+    J' = (1 - omega_o) J exactly.  A mean taken from the previous step would
+    give J'' = J' - omega_o J instead (growing for omega_o > 1, e.g. tau = 6),
+    a wrong normalisation or sign another factor."""
+    n = 8
+    oo = 1.0 / tau if srt else 8.0 * (2.0 - 1.0 / tau) / (8.0 - 1.0 / tau)   # Lambda = 3/16
+    sim, c = _periodic_random_box(n, tau, 5 + int(10 * tau), srt=srt)
+    J = [np.einsum("qa,qzyx->a", c, sim.populations())]
+    for _ in range(5):
+        sim.step(1)
+        J.append(np.einsum("qa,qzyx->a", c, sim.populations()))
+    for a, b in zip(J[:-1], J[1:]):
+        np.testing.assert_allclose(b, (1.0 - oo) * a, rtol=0, atol=1e-12 * np.abs(J[0]).max())
+    assert np.abs(J[0]).max() > 1.0
+
+
+def test_stabilized_momentum_with_body_force_reaches_its_fixed_point():
+    """With a body force g the velocity carries the half-force shift, so
+    u_bar = J / (N rho0) + g/2 and J' = (1 - omega_o) J + N rho0 g (1 - omega_o/2):
+    one step from any state and the fixed point J* = N rho0 g (1 - omega_o/2) / omega_o."""
+    n, tau = 6, 0.8
+    g = np.array([2e-5, -1e-5, 3e-5])
+    sim, c = _periodic_random_box(n, tau, 21, g=g)
+    oo = O.omega_odd(tau, 3.0 / 16.0, False)
+    N = n ** 3
+    J0 = np.einsum("qa,qzyx->a", c, sim.populations())
+    sim.step(1)
+    J1 = np.einsum("qa,qzyx->a", c, sim.populations())
+    np.testing.assert_allclose(J1, (1 - oo) * J0 + N * g * (1 - 0.5 * oo), rtol=0, atol=1e-12)
+    sim.step(200)
+    J = np.einsum("qa,qzyx->a", c, sim.populations())
+    np.testing.assert_allclose(J, N * g * (1 - 0.5 * oo) / oo, rtol=1e-9, atol=0)
+
+
+def test_mean_velocity_is_the_fluid_cell_mean():
+    """The stabilization's u_bar: the mean of sum_q c_q f_q / rho0 over the
+    fluid cells only (particle cells excluded), computed here from the
+    populations and the owner map."""
+    n = 16
+    sim = O.Sim(n, n, n, tau=0.8, z_periodic=True, stabilize=True)
+    c, w, _ = O.lattice()
+    rng = np.random.default_rng(3)
+    sim.add_fiber([7.3, 8.1, 8.4], _quat_to(np.array([0.6, 0.0, 0.8])), 9.0, 2.2, 1.0, V=(0.01, 0, 0))
+    f = w[:, None, None, None] * (1.0 + 0.1 * rng.standard_normal((19, n, n, n)))
+    sim.set_populations(f)
+    _, _, _, pid = sim.fields()
+    fluid = pid < 0
+    ub, nf = sim.mean_velocity()
+    assert nf == int(fluid.sum()) and nf < n ** 3
+    j = np.einsum("qa,qzyx->azyx", c.astype(np.float64), f)
+    np.testing.assert_allclose(ub, j[:, fluid].mean(axis=1), rtol=1e-13, atol=1e-17)
+
+
+def test_stabilized_momentum_budget_with_a_forced_particle():
+    """A spherocylinder under a constant force in a fully periodic box with
+    the explicit coupling: per step, fluid plus particle momentum changes by
+    the external force minus omega_o N_f rho0 u_bar (the stabilization's
+    sink), to rounding, while no cell changes owner."""
+    n, tau = 20, 0.8
+    sim = O.Sim(n, n, n, tau=tau, z_periodic=True, coupling="explicit", stabilize=True)
+    Fe = np.array([1e-3, 5e-4, -2e-3])
+    L, r = 9.0, 2.0
+    sim.add_fiber([10.1, 9.7, 10.3], _quat_to(np.array([0.2, 0.9, 0.39]) / np.linalg.norm([0.2, 0.9, 0.39])),
+                  L, r, 1.0, shape="spherocylinder", force=Fe)
+    c = O.lattice()[0].astype(np.float64)
+    mass = O.body_inertia("spherocylinder", L, r, 1.0)[0]
+    oo = O.omega_odd(tau, 3.0 / 16.0, False)
+
+    def total():
+        f = sim.populations()
+        _, _, _, pid = sim.fields()
+        pf = np.einsum("qa,qzyx->a", c, f * (pid < 0)[None])
+        _, _, V, _ = sim.fiber_state()
+        return pf + mass * V[0], pid
+
+    sim.step(3)
+    p0, pid0 = total()
+    for s in range(5):
+        ub, nf = sim.mean_velocity()
+        sim.step(1)
+        p1, pid1 = total()
+        assert np.array_equal(pid1, pid0), s
+        np.testing.assert_allclose(p1 - p0, Fe - oo * nf * ub, rtol=0, atol=1e-10)
+        assert np.linalg.norm(oo * nf * ub) > 1e-4
+        p0 = p1
+
+
 # ---------------------------------------------------------------- P13 rigid body
 def test_quaternion_update_constant_rotation():
     """Rigid update (Sec. 4.3; integrator is this project's reading): with no
