@@ -96,6 +96,8 @@ typedef struct {
     void *stream;              /* hipStream_t to order work on; NULL: a private stream */
     int32_t sweep_grid;        /* workgroups of the bulk sweep (grid-stride); 0 = automatic */
     int32_t q_pad;             /* extra elements between direction arrays; -1 = automatic */
+    int32_t stabilize;         /* 1: momentum stabilization (see lbm_get_mean_velocity); 0: off */
+    int32_t reserved;          /* 0 */
 } lbm_params;
 
 /* Fiber shapes: a circular cylinder of length L, or a spherocylinder (a
@@ -217,6 +219,18 @@ lbm_status lbm_get_populations(lbm_ctx *ctx, double *f);
 
 /* Overwrite the logical populations (host FP64 [19][z][y][x]). */
 lbm_status lbm_set_populations(lbm_ctx *ctx, const double *f);
+
+/* Momentum stabilization (Sec. 4.1; lbm_params.stabilize = 1), for fully
+ * periodic domains whose particles carry a constant external force: every
+ * collision takes its equilibrium at u - ubar, ubar the mean velocity
+ * sum_q c_q f_q / rho0 (+ g/2 with a body force) over all fluid cells of
+ * the state the step starts from.  The mean is kept up to date by the step
+ * kernels (no extra pass over the lattice); after a state change from the
+ * host it is recomputed by one pass before the next step.  This call
+ * synchronises and returns the mean the next step will subtract and the
+ * number of fluid cells it was taken over (nfluid may be NULL).
+ * LBM_E_STATE when the context was created without stabilization. */
+lbm_status lbm_get_mean_velocity(lbm_ctx *ctx, double ubar[3], int64_t *nfluid);
 
 lbm_status lbm_get_info(lbm_ctx *ctx, lbm_info *info);
 

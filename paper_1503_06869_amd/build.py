@@ -29,6 +29,7 @@ SOURCES = {
     # the sweep part keeps the default contraction of sweep.hip; the particle
     # part and the host code follow a contraction-off pragma in the header
     "batched.hip": [],
+    "stab.hip": [],
     "features.hip": [],
     "mlp.hip": [],
 }

@@ -63,6 +63,11 @@ struct lbm_ctx {
     size_t ev_used = 0;
     int64_t timed_sweeps = 0;
     double timed_ms = 0.0;
+    // momentum stabilization: mean velocity, workgroup sums, changed cells
+    double *stab = nullptr;
+    uint32_t *cov = nullptr;
+    uint32_t cov_cap = 0;
+    bool stab_stale = true;   // state changed from the host: the mean needs a full pass
     // learned closure (not owned)
     lbm_mlp *closure = nullptr;
     double *corr = nullptr;
@@ -118,6 +123,33 @@ static void free_particles(lbm_ctx *c)
     dfree(c->hist);
     dfree(c->list_cell);
     dfree(c->list_mask);
+}
+
+// buffers of the momentum stabilization, sized for the current sweep and
+// boundary grids and boundary list
+static lbm_status alloc_stab(lbm_ctx *c)
+{
+    if (!c->p.stabilize) return LBM_OK;
+    dfree(c->stab);
+    dfree(c->cov);
+    const uint32_t nslot = std::max(STAB_SCAN_GRID, c->sweep_grid + c->bnd_grid);
+    HIPCHK(c, dalloc(c, &c->stab, size_t(STAB_HEAD) + 4 * size_t(nslot)));
+    HIPCHK(c, hipMemsetAsync(c->stab, 0, (size_t(STAB_HEAD) + 4 * size_t(nslot)) * sizeof(double), c->st));
+    // cells changing owner in one remap: fewer than the boundary list holds
+    c->cov_cap = std::max(4096u, c->list_cap);
+    HIPCHK(c, dalloc(c, &c->cov, size_t(c->cov_cap) + 1));
+    HIPCHK(c, hipMemsetAsync(c->cov, 0, (size_t(c->cov_cap) + 1) * sizeof(uint32_t), c->st));
+    c->stab_stale = true;
+    return LBM_OK;
+}
+
+// the mean velocity of the current state by a full pass, when the host has
+// changed the state since the last step
+static hipError_t refresh_stab(lbm_ctx *c)
+{
+    if (!c->p.stabilize || !c->stab_stale) return hipSuccess;
+    c->stab_stale = false;
+    return launch_stab_scan(c->sk, (c->steps & 1) != 0, c->f, c->pid, c->g, c->ph, c->stab, c->cov, c->st);
 }
 
 static void drop_graph(lbm_ctx *c)
@@ -273,12 +305,13 @@ static lbm_status upload_particles(lbm_ctx *c)
     HIPCHK(c, hipMemsetAsync(c->traj_pos, 0, np * sizeof(int64_t), c->st));
     HIPCHK(c, hipMemsetAsync(c->box_cur, 0, np * sizeof(Box), c->st));
     HIPCHK(c, hipMemsetAsync(c->ft, 0, np * 6 * sizeof(double), c->st));
-    return LBM_OK;
+    return alloc_stab(c);
 }
 
 // map all fibers from their current states (cells of the old boxes included)
 static lbm_status setup_mapping(lbm_ctx *c, PState *old_states)
 {
+    c->stab_stale = true;
     if (c->np == 0) return LBM_OK;
     PState *cur = c->ps[c->steps & 1];
     PartData pd = part_data(c, old_states ? old_states : cur, cur);
@@ -305,7 +338,9 @@ static lbm_status check_device_errors(lbm_ctx *c)
     if (h.err_capacity)
         return fail(c, LBM_E_STATE,
                     std::string("internal capacity exceeded (") +
-                        ((h.err_capacity & 2) ? "boundary list" : "neighbour list") + ")");
+                        ((h.err_capacity & 4) ? "changed-cell list"
+                                                  : (h.err_capacity & 2) ? "boundary list" : "neighbour list") +
+                        ")");
     return LBM_OK;
 }
 
@@ -338,9 +373,17 @@ static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hi
     b.mea = c->mea;
     b.ctr = c->ctr;
     hipError_t e = hipSuccess;
+    // momentum stabilization: the sweep kernels read the mean and write their
+    // sums (bulk workgroups first); after the join the next mean is formed
+    const bool stab = c->p.stabilize != 0;
+    const double *su = stab ? c->stab : nullptr;
+    double *sp = stab ? c->stab + STAB_HEAD : nullptr;
+    double *sp_b = stab ? sp + 4 * size_t(c->sweep_grid) : nullptr;
     if (!c->np) {
         e = launch_sweep(c->sk, odd, c->f, c->flags[step_index & 1], c->g, c->ph, c->sweep_grid, c->st,
-                         with_events ? e0 : nullptr, with_events ? e1 : nullptr);
+                         with_events ? e0 : nullptr, with_events ? e1 : nullptr, su, sp);
+        if (e == hipSuccess && stab)
+            e = launch_stab_update(c->sk, !odd, c->f, c->g, c->ph, c->stab, c->sweep_grid, c->cov, c->cov_cap, c->st);
         if (e != hipSuccess && *err == hipSuccess) *err = e;
         return;
     }
@@ -364,19 +407,26 @@ static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hi
     // fibers: the particle branch is the longer one).
     const bool bulk_first = c->sweep_grid <= 1024u && uint64_t(c->g.ncell) >= 32ull * c->list_cap;
     if (e == hipSuccess && !bulk_first)
-        e = launch_boundary(c->sk, odd, c->f, c->g, c->ph, b, link_rho0(c), c->st2);
+        e = launch_boundary(c->sk, odd, c->f, c->g, c->ph, b, link_rho0(c), c->st2, su, sp_b);
     if (e == hipSuccess)
         e = launch_sweep(c->sk, odd, c->f, c->flags[step_index & 1], c->g, c->ph, c->sweep_grid, c->st,
-                         with_events ? e0 : nullptr, with_events ? e1 : nullptr);
+                         with_events ? e0 : nullptr, with_events ? e1 : nullptr, su, sp);
     if (e == hipSuccess && bulk_first)
-        e = launch_boundary(c->sk, odd, c->f, c->g, c->ph, b, link_rho0(c), c->st2);
+        e = launch_boundary(c->sk, odd, c->f, c->g, c->ph, b, link_rho0(c), c->st2, su, sp_b);
     PartData pd = part_data(c, cur, next);
+    if (stab) {
+        pd.cov = c->cov;
+        pd.cov_cap = c->cov_cap;
+    }
     if (e == hipSuccess) e = launch_rigid(pd, c->g, c->st2);
     if (e == hipSuccess) e = launch_remap(c->sk, !odd, c->f, c->pid, pd, c->g, c->p.rho0, c->scale, c->st2);
     if (e == hipSuccess)
         e = launch_near(c->flags[(step_index + 1) & 1], c->pid, c->list_cell, c->list_mask, pd, c->g, c->st2);
     if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->st2);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->st, c->ev_join, 0);
+    if (e == hipSuccess && stab)
+        e = launch_stab_update(c->sk, !odd, c->f, c->g, c->ph, c->stab, c->sweep_grid + c->bnd_grid, c->cov,
+                               c->cov_cap, c->st);
     if (e != hipSuccess && *err == hipSuccess) *err = e;
 }
 
@@ -450,6 +500,9 @@ lbm_status lbm_create(const lbm_params *p, lbm_ctx **out)
     if (p->storage < 0 || p->storage > 3 || p->history_capacity < 1) return LBM_E_ARG;
     if (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 20) return LBM_E_ARG;
     if (p->coupling < LBM_COUPLING_IMPLICIT || p->coupling > LBM_COUPLING_IMPLICIT_PLAIN) return LBM_E_ARG;
+    if (p->stabilize != 0 && p->stabilize != 1) return LBM_E_ARG;
+    // changed-cell entries keep a flag in bit 31
+    if (p->stabilize && ncell >= 2147483648.0) return LBM_E_ARG;
     lbm_ctx *c = new (std::nothrow) lbm_ctx;
     if (!c) return LBM_E_NOMEM;
     c->p = *p;
@@ -523,6 +576,7 @@ lbm_status lbm_create(const lbm_params *p, lbm_ctx **out)
     if (launch_init(c->sk, c->f, g, p->rho0, ph.wall_u, p->init_profile == LBM_INIT_COUETTE, c->scale,
                     c->st) != hipSuccess)
         return bail(LBM_E_HIP, "init");
+    if (alloc_stab(c) != LBM_OK) return bail(LBM_E_NOMEM, "stabilization");
     if (hipStreamSynchronize(c->st) != hipSuccess) return bail(LBM_E_HIP, "sync");
     (void)s;
     *out = c;
@@ -536,6 +590,8 @@ lbm_status lbm_destroy(lbm_ctx *c)
     drop_graph(c);
     for (hipEvent_t e : c->ev) hipEventDestroy(e);
     free_particles(c);
+    dfree(c->stab);
+    dfree(c->cov);
     dfree(c->corr);
     dfree(c->cstats);
     dfree(c->f);
@@ -662,7 +718,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t n)
 {
     if (!c) return LBM_E_ARG;
     if (n < 0) return fail(c, LBM_E_ARG, "negative step count");
-    hipError_t err = hipSuccess;
+    hipError_t err = n > 0 ? refresh_stab(c) : hipSuccess;
     auto direct = [&](void) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (c->timing) {
@@ -856,10 +912,24 @@ lbm_status lbm_set_populations(lbm_ctx *c, const double *f)
     HIPCHK(c, hipMalloc(&d, n * sizeof(double)));
     hipError_t e = hipMemcpyAsync(d, f, n * sizeof(double), hipMemcpyHostToDevice, c->st);
     if (e == hipSuccess) e = launch_encode(c->sk, (c->steps & 1) != 0, c->f, c->g, c->p.rho0, c->scale, d, c->st);
+    c->stab_stale = true;
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     hipFree(d);
     if (e != hipSuccess) return fail(c, LBM_E_HIP, hipGetErrorString(e));
     return LBM_OK;
+}
+
+lbm_status lbm_get_mean_velocity(lbm_ctx *c, double ubar[3], int64_t *nfluid)
+{
+    if (!c || !ubar) return fail(c, LBM_E_ARG, "null argument");
+    if (!c->p.stabilize) return fail(c, LBM_E_STATE, "momentum stabilization is off");
+    HIPCHK(c, refresh_stab(c));
+    double h[4];
+    HIPCHK(c, hipMemcpyAsync(h, c->stab, sizeof h, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    for (int k = 0; k < 3; ++k) ubar[k] = h[k];
+    if (nfluid) *nfluid = int64_t(h[3]);
+    return check_device_errors(c);
 }
 
 lbm_status lbm_get_info(lbm_ctx *c, lbm_info *info)

@@ -15,19 +15,22 @@
 
 namespace lbm {
 
-template <typename S, bool ODD>
+template <typename S, bool ODD, bool STAB>
 __device__ __forceinline__ void bnd_block(S *__restrict__ f, const Geo &g, const Phys<typename St<S>::R> &ph,
-                                          const BndData &b, int blk)
+                                          const BndData &b, int blk, const double *stab, double *part)
 {
     // block (fiber p, part j) of the fiber's list segment
     const int p = blk / b.bpf, j = blk % b.bpf;
     const uint32_t cnt = b.seg_cnt[p], cap = b.seg_cap[p];
     const uint32_t n = cnt < cap ? cnt : cap, off = b.seg_off[p];
     long long acc[6] = {0, 0, 0, 0, 0, 0};
+    StabAcc<typename St<S>::R> sa;
+    if constexpr (STAB) stab_begin(sa, stab);
     for (uint32_t r = j * 256u + threadIdx.x; r < n; r += b.bpf * 256u) {
         const uint32_t e = off + r;
-        update_cell<S, ODD, true, 6>(f, g, ph, b.cell[e], b.mask[e], p, acc, b);
+        update_cell<S, ODD, true, 6, STAB>(f, g, ph, b.cell[e], b.mask[e], p, acc, b, &sa);
     }
+    if constexpr (STAB) stab_flush(sa, part + 4 * size_t(blk));
     // integer sums: exact, so the reduction order does not matter
     __shared__ long long red[4][6];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -144,36 +147,43 @@ __device__ __forceinline__ void abc_block(const BndData &b, const Geo &g, double
 // resident for its whole grid-stride run; this kernel runs beside it with
 // up to 2 waves per SIMD, so it must stay within 176 VGPRs (171 for FP32),
 // or bulk workgroups launched after it start late and the sweep stretches.
-template <typename S, bool ODD>
+// STAB: momentum stabilization (mean velocity stab[0..2]; the boundary-cell
+// workgroup blk writes its sums to part[4 blk .. 4 blk + 3]).
+template <typename S, bool ODD, bool STAB>
 __global__ __launch_bounds__(256) void k_boundary(S *__restrict__ f, Geo g, Phys<typename St<S>::R> ph,
-                                                  BndData b, double r0)
+                                                  BndData b, double r0, const double *stab, double *part)
 {
     const int nb = b.np * b.bpf;   // block-uniform split
-    if (int(blockIdx.x) < nb) bnd_block<S, ODD>(f, g, ph, b, int(blockIdx.x));
+    if (int(blockIdx.x) < nb) bnd_block<S, ODD, STAB>(f, g, ph, b, int(blockIdx.x), stab, part);
     else abc_block(b, g, r0, int(blockIdx.x) - nb);
 }
 
 template <typename S>
 static hipError_t boundary_t(bool odd, void *f, const Geo &g, const Phys<double> &ph, const BndData &b,
-                             double r0, hipStream_t st)
+                             double r0, hipStream_t st, const double *stab, double *part)
 {
     using R = typename St<S>::R;
     const Phys<R> p = cast_phys<R>(ph);
-    const dim3 grid(uint32_t(2 * b.np * b.bpf));
-    if (odd) hipLaunchKernelGGL((k_boundary<S, true>), grid, dim3(256), 0, st, (S *)f, g, p, b, r0);
-    else hipLaunchKernelGGL((k_boundary<S, false>), grid, dim3(256), 0, st, (S *)f, g, p, b, r0);
+    const dim3 grid(uint32_t(2 * b.np * b.bpf)), bl(256);
+    if (stab) {
+        if (odd) hipLaunchKernelGGL((k_boundary<S, true, true>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part);
+        else hipLaunchKernelGGL((k_boundary<S, false, true>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part);
+    } else {
+        if (odd) hipLaunchKernelGGL((k_boundary<S, true, false>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part);
+        else hipLaunchKernelGGL((k_boundary<S, false, false>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_boundary(int sk, bool odd, void *f, const Geo &g, const Phys<double> &ph, const BndData &b,
-                           double r0, hipStream_t st)
+                           double r0, hipStream_t st, const double *stab, double *part)
 {
     if (b.np <= 0 || b.bpf <= 0) return hipSuccess;
     switch (sk) {
-    case S_F32: return boundary_t<float>(odd, f, g, ph, b, r0, st);
-    case S_F16: return boundary_t<_Float16>(odd, f, g, ph, b, r0, st);
-    case S_BF16: return boundary_t<bf16s>(odd, f, g, ph, b, r0, st);
-    default: return boundary_t<double>(odd, f, g, ph, b, r0, st);
+    case S_F32: return boundary_t<float>(odd, f, g, ph, b, r0, st, stab, part);
+    case S_F16: return boundary_t<_Float16>(odd, f, g, ph, b, r0, st, stab, part);
+    case S_BF16: return boundary_t<bf16s>(odd, f, g, ph, b, r0, st, stab, part);
+    default: return boundary_t<double>(odd, f, g, ph, b, r0, st, stab, part);
     }
 }
 

@@ -187,6 +187,8 @@ struct PartData {
     const uint32_t *seg_off;   // [np] list segment of each fiber: start
     const uint32_t *seg_cap;   // [np] capacity
     uint32_t *seg_cnt;         // [np] entries
+    uint32_t *cov;             // cells whose owner changed (stabilization), or null
+    uint32_t cov_cap;
 };
 
 // ---------------------------------------------------------------------------
@@ -196,14 +198,34 @@ enum StorageKind { S_F32 = 0, S_F16 = 1, S_BF16 = 2, S_F64 = 3 };
 
 hipError_t launch_init(int sk, void *f, const Geo &g, double rho0, double wall_u, int couette,
                        double scale, hipStream_t st);
-// bulk sweep on st (bracketed by ev0/ev1 if given); skipped when the grid is 0
+// Momentum stabilization (stab.hip).  Device buffer stab: [0..2] the mean
+// fluid velocity the collisions of the coming step subtract, [3] the fluid
+// cell count, [4..7] unused, then 4 doubles per workgroup of the sweep
+// kernels (bulk workgroups first, then the boundary-cell workgroups).  cov:
+// [0] entries, then cells whose owner changed in the remap (bit 31: fluid
+// again, else newly covered).
+constexpr int STAB_HEAD = 8;
+constexpr uint32_t COV_UNCOVERED = 0x80000000u;
+// the next step's mean from this step's workgroup sums (nslot of them) and
+// the changed cells, read in the layout of the next sweep (swapped: odd)
+hipError_t launch_stab_update(int sk, bool swapped, const void *f, const Geo &g, const Phys<double> &ph,
+                              double *stab, uint32_t nslot, uint32_t *cov, uint32_t cov_cap, hipStream_t st);
+// the mean of the current state by a pass over all cells (after set-up)
+hipError_t launch_stab_scan(int sk, bool swapped, const void *f, const int32_t *pid, const Geo &g,
+                            const Phys<double> &ph, double *stab, uint32_t *cov, hipStream_t st);
+constexpr uint32_t STAB_SCAN_GRID = 1024;
+
+// bulk sweep on st (bracketed by ev0/ev1 if given); skipped when the grid is
+// 0; with stab (else null) the stabilized collision writing its workgroup
+// sums to part
 hipError_t launch_sweep(int sk, bool odd, void *f, const uint8_t *flags, const Geo &g, const Phys<double> &ph,
-                        uint32_t sweep_grid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
+                        uint32_t sweep_grid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, const double *stab,
+                        double *part);
 // boundary cells of the list (update, F0, M0) and the A, B, C sums of their
 // links, one launch (boundary.hip); r0: rho0 as the sweep's collision type
-// holds it (the link terms' k = 6 w rho0)
+// holds it (the link terms' k = 6 w rho0); stab and part as for the sweep
 hipError_t launch_boundary(int sk, bool odd, void *f, const Geo &g, const Phys<double> &ph, const BndData &b,
-                           double r0, hipStream_t st);
+                           double r0, hipStream_t st, const double *stab, double *part);
 hipError_t launch_decode(int sk, bool swapped, const void *f, const uint8_t *flags,
                          const int32_t *pid, const PState *ps, const Geo &g, const Phys<double> &ph,
                          void *rho, void *u, double *fout, hipStream_t st);

@@ -84,14 +84,68 @@ inline Phys<R> cast_phys(const Phys<double> &p)
     return o;
 }
 
+// ------------------------------------------------------------------ stabilization
+// Momentum stabilization (Sec. 4.1): the collisions of a step take their
+// equilibrium at u - ub, ub the mean fluid velocity of the state they read.
+// Each thread also sums, over the cells it updates, the momentum j before
+// collision, the momentum change of its bounce-back links and the cell count;
+// the per-workgroup totals give the next step's mean without a further pass
+// over the lattice (the collision changes each cell's momentum by the uniform
+// rho0 (g - omega_o ub), streaming in the interior conserves it).
+template <typename R>
+struct StabAcc {
+    R ub[3];
+    R j[3];
+    R n;
+};
+
+template <typename R>
+__device__ __forceinline__ void stab_begin(StabAcc<R> &sa, const double *stab)
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        sa.ub[k] = R(stab[k]);
+        sa.j[k] = R(0);
+    }
+    sa.n = R(0);
+}
+
+// Workgroup total (256 threads, every thread calls) of 4 doubles, written to
+// out by thread 0..3: wave sums by shuffles, then the 4 waves in order.
+__device__ __forceinline__ void block_sum4(const double (&v)[4], double *out)
+{
+    __shared__ double red[4][4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double x = v[k];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if (lane == 0) red[wid][k] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        out[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    }
+}
+
+// j and n of a thread's cells into the workgroup's slot
+template <typename R>
+__device__ __forceinline__ void stab_flush(const StabAcc<R> &sa, double *out)
+{
+    const double v[4] = {double(sa.j[0]), double(sa.j[1]), double(sa.j[2]), double(sa.n)};
+    block_sum4(v, out);
+}
+
 // ------------------------------------------------------------------ collision
 // TRT in deviation form: f' = f - w rho0, drho = sum f', j = sum c f'.
 // Even/odd equilibrium parts of Eq. EqPDF_TRT minus w rho0:
 //   feq_e' = w (drho - 3/2 rho0 u.u + 9/2 rho0 (c.u)^2),  feq_o = 3 w rho0 c.u
 // lambda_e = -omega_e, lambda_o = -omega_o (Eq. LBMCollide).  With a body
 // force the velocity carries +g/2 and the odd part gains (1 - omega_o/2) 3 w rho0 c.g.
-template <typename R>
-__device__ __forceinline__ void collide(R (&f)[Q], const Phys<R> &ph, R inv_rho0)
+// STAB: the equilibrium velocity is u - sa.ub, and j and the cell are counted.
+template <typename R, bool STAB = false>
+__device__ __forceinline__ void collide(R (&f)[Q], const Phys<R> &ph, R inv_rho0, StabAcc<R> *sa = nullptr)
 {
     R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
 #pragma unroll
@@ -106,6 +160,15 @@ __device__ __forceinline__ void collide(R (&f)[Q], const Phys<R> &ph, R inv_rho0
         ux += R(0.5) * ph.g[0];
         uy += R(0.5) * ph.g[1];
         uz += R(0.5) * ph.g[2];
+    }
+    if constexpr (STAB) {
+        sa->j[0] += jx;
+        sa->j[1] += jy;
+        sa->j[2] += jz;
+        sa->n += R(1);
+        ux -= sa->ub[0];
+        uy -= sa->ub[1];
+        uz -= sa->ub[2];
     }
     const R r0 = ph.rho0, we = ph.omega_e, wo = ph.omega_o;
     const R base = drho - R(1.5) * r0 * (ux * ux + uy * uy + uz * uz);
@@ -193,10 +256,12 @@ __device__ __forceinline__ void link_terms(long long *acc, double ft, double rx,
 
 // NK: momentum-exchange terms accumulated per link (NACC, or 6 for F0 and
 // M0 only when the population-free terms are summed elsewhere).
-template <typename S, bool ODD, bool BND, int NK = NACC>
+// STAB: momentum stabilization with the accumulator sa (see StabAcc).
+template <typename S, bool ODD, bool BND, int NK = NACC, bool STAB = false>
 __device__ __forceinline__ void update_cell(S *__restrict__ f, const Geo &g,
                                             const Phys<typename St<S>::R> &ph, uint32_t cell,
-                                            uint32_t mask, int home, long long *acc, const BndData &b)
+                                            uint32_t mask, int home, long long *acc, const BndData &b,
+                                            StabAcc<typename St<S>::R> *sa = nullptr)
 {
     using R = typename St<S>::R;
     const uint32_t z = fdiv(cell, g.dnxy);
@@ -228,7 +293,7 @@ __device__ __forceinline__ void update_cell(S *__restrict__ f, const Geo &g,
             fv[q] = St<S>::ld(f, uint64_t(opp(q)) * qs + src, inv);
         }
     }
-    collide<R>(fv, ph, R(1) / ph.rho0);
+    collide<R, STAB>(fv, ph, R(1) / ph.rho0, sa);
 
     const bool wall_lo = !g.zper && z == 0;
     const bool wall_hi = !g.zper && z + 1 == g.nz;
@@ -279,6 +344,16 @@ __device__ __forceinline__ void update_cell(S *__restrict__ f, const Geo &g,
             }
         }
         const bool bounce = to_wall || to_part;
+        if constexpr (STAB) {
+            // a bounced link returns out in direction -c_q instead of
+            // streaming fv[q] along c_q
+            if (bounce) {
+                const R m = fv[q] + out;
+                if (CX[q]) sa->j[0] -= CX[q] > 0 ? m : -m;
+                if (CY[q]) sa->j[1] -= CY[q] > 0 ? m : -m;
+                if (CZ[q]) sa->j[2] -= CZ[q] > 0 ? m : -m;
+            }
+        }
         if (!ODD) {
             if (bounce) St<S>::st(f, uint64_t(q) * qs + nb, out, sc);
             else St<S>::st(f, uint64_t(opp(q)) * qs + own, out, sc);

@@ -279,6 +279,12 @@ __global__ __launch_bounds__(256) void k_remap(S *__restrict__ f, int32_t *__res
             const int old = pid[cell];
             if (old >= 0 && owner < 0)   // uncovered
                 refill_cell<S>(f, g, x, y, z, pd.ps_cur[old], rho0, scale, next_odd);
+            if (pd.cov && (old < 0) != (owner < 0)) {
+                // fluid cell count and momentum change for the stabilization
+                const uint32_t k = atomicAdd(pd.cov, 1u);
+                if (k < pd.cov_cap) pd.cov[1 + k] = cell | (owner < 0 ? COV_UNCOVERED : 0u);
+                else atomicOr(&pd.ctr->err_capacity, 4u);
+            }
             pid[cell] = owner;
         }
     }

@@ -25,16 +25,23 @@ namespace lbm {
 // Grid-stride over 256-cell chunks: at any time the resident workgroups work
 // on one compact band of the lattice, which keeps each of the 38 access
 // streams (19 directions read, 19 written) within a few DRAM pages.
-template <typename S, bool ODD>
+// STAB: momentum stabilization; stab[0..2] is the mean velocity the
+// collisions subtract, and workgroup b writes its sums to part[4 b .. 4 b + 3].
+template <typename S, bool ODD, bool STAB>
 __global__ __launch_bounds__(256) void k_sweep_bulk(S *__restrict__ f, const uint8_t *__restrict__ flags,
-                                                    Geo g, Phys<typename St<S>::R> ph)
+                                                    Geo g, Phys<typename St<S>::R> ph, const double *stab,
+                                                    double *part)
 {
+    using R = typename St<S>::R;
+    StabAcc<R> sa;
+    if constexpr (STAB) stab_begin(sa, stab);
     const uint32_t nchunk = (g.ncell + 255u) >> 8;
     for (uint32_t ch = xcd_block(blockIdx.x, gridDim.x); ch < nchunk; ch += gridDim.x) {
         const uint32_t cell = (ch << 8) + threadIdx.x;
         if (cell < g.ncell && !flags[cell])   // fiber cells idle; boundary cells: k_boundary
-            update_cell<S, ODD, false>(f, g, ph, cell, 0u, -1, nullptr, BndData{});
+            update_cell<S, ODD, false, NACC, STAB>(f, g, ph, cell, 0u, -1, nullptr, BndData{}, &sa);
     }
+    if constexpr (STAB) stab_flush(sa, part + 4 * size_t(blockIdx.x));
 }
 
 // ------------------------------------------------------------------ init
@@ -144,28 +151,34 @@ __global__ __launch_bounds__(256) void k_copy(uint4 *__restrict__ dst, const uin
 // ------------------------------------------------------------------ launchers
 template <typename S>
 static hipError_t sweep_t(bool odd, void *f, const uint8_t *flags, const Geo &g, const Phys<double> &ph,
-                          uint32_t sweep_grid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
+                          uint32_t sweep_grid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+                          const double *stab, double *part)
 {
     using R = typename St<S>::R;
     const Phys<R> p = cast_phys<R>(ph);
     if (!sweep_grid) return hipSuccess;
     if (ev0) hipEventRecord(ev0, st);
-    if (odd)
-        hipLaunchKernelGGL((k_sweep_bulk<S, true>), dim3(sweep_grid), dim3(256), 0, st, (S *)f, flags, g, p);
-    else
-        hipLaunchKernelGGL((k_sweep_bulk<S, false>), dim3(sweep_grid), dim3(256), 0, st, (S *)f, flags, g, p);
+    const dim3 gr(sweep_grid), bl(256);
+    if (stab) {
+        if (odd) hipLaunchKernelGGL((k_sweep_bulk<S, true, true>), gr, bl, 0, st, (S *)f, flags, g, p, stab, part);
+        else hipLaunchKernelGGL((k_sweep_bulk<S, false, true>), gr, bl, 0, st, (S *)f, flags, g, p, stab, part);
+    } else {
+        if (odd) hipLaunchKernelGGL((k_sweep_bulk<S, true, false>), gr, bl, 0, st, (S *)f, flags, g, p, stab, part);
+        else hipLaunchKernelGGL((k_sweep_bulk<S, false, false>), gr, bl, 0, st, (S *)f, flags, g, p, stab, part);
+    }
     if (ev1) hipEventRecord(ev1, st);
     return hipGetLastError();
 }
 
 hipError_t launch_sweep(int sk, bool odd, void *f, const uint8_t *flags, const Geo &g, const Phys<double> &ph,
-                        uint32_t sweep_grid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
+                        uint32_t sweep_grid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, const double *stab,
+                        double *part)
 {
     switch (sk) {
-    case S_F32: return sweep_t<float>(odd, f, flags, g, ph, sweep_grid, st, ev0, ev1);
-    case S_F16: return sweep_t<_Float16>(odd, f, flags, g, ph, sweep_grid, st, ev0, ev1);
-    case S_BF16: return sweep_t<bf16s>(odd, f, flags, g, ph, sweep_grid, st, ev0, ev1);
-    default: return sweep_t<double>(odd, f, flags, g, ph, sweep_grid, st, ev0, ev1);
+    case S_F32: return sweep_t<float>(odd, f, flags, g, ph, sweep_grid, st, ev0, ev1, stab, part);
+    case S_F16: return sweep_t<_Float16>(odd, f, flags, g, ph, sweep_grid, st, ev0, ev1, stab, part);
+    case S_BF16: return sweep_t<bf16s>(odd, f, flags, g, ph, sweep_grid, st, ev0, ev1, stab, part);
+    default: return sweep_t<double>(odd, f, flags, g, ph, sweep_grid, st, ev0, ev1, stab, part);
     }
 }
 

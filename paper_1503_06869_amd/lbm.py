@@ -30,7 +30,7 @@ EXPORTED = [
     "lbm_add_fiber", "lbm_set_fiber_kinematics", "lbm_step", "lbm_sync",
     "lbm_get_force_torque", "lbm_get_fields", "lbm_get_fiber_state", "lbm_set_fiber_state",
     "lbm_get_history", "lbm_get_populations", "lbm_set_populations", "lbm_get_info",
-    "lbm_enable_sweep_timing", "lbm_get_sweep_time", "lbm_copy_bytes",
+    "lbm_enable_sweep_timing", "lbm_get_sweep_time", "lbm_copy_bytes", "lbm_get_mean_velocity",
 ]
 EXPORTED_BATCH = [
     "lbm_batch_params_default", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_last_error",
@@ -55,7 +55,8 @@ class lbm_params(C.Structure):
                 ("rho0", C.c_double), ("body_force", C.c_double * 3),
                 ("storage", C.c_int32), ("init_profile", C.c_int32), ("coupling", C.c_int32),
                 ("fp16_scale_log2", C.c_int32), ("history_capacity", C.c_int64),
-                ("stream", C.c_void_p), ("sweep_grid", C.c_int32), ("q_pad", C.c_int32)]
+                ("stream", C.c_void_p), ("sweep_grid", C.c_int32), ("q_pad", C.c_int32),
+                ("stabilize", C.c_int32), ("reserved", C.c_int32)]
 
 
 class lbm_fiber(C.Structure):
@@ -130,6 +131,7 @@ def load():
         "lbm_get_populations": ([vp, _dp], C.c_int),
         "lbm_set_populations": ([vp, _dp], C.c_int),
         "lbm_get_info": ([vp, C.POINTER(lbm_info)], C.c_int),
+        "lbm_get_mean_velocity": ([vp, _dp, C.POINTER(C.c_int64)], C.c_int),
         "lbm_enable_sweep_timing": ([vp, C.c_int32], C.c_int),
         "lbm_get_sweep_time": ([vp, _dp, C.POINTER(C.c_int64)], C.c_int),
         "lbm_copy_bytes": ([vp, vp, C.c_size_t, vp], C.c_int),
@@ -210,7 +212,9 @@ class Context:
     def __init__(self, nx, ny, nz, tau=0.8, magic=3.0 / 16.0, wall_u=0.0, rho0=1.0,
                  z_periodic=False, collision="trt", storage="f32", init_couette=False,
                  coupling="implicit", body_force=(0.0, 0.0, 0.0), fp16_scale_log2=14,
-                 history_capacity=4096, stream=None, sweep_grid=0, q_pad=-1):
+                 history_capacity=4096, stream=None, sweep_grid=0, q_pad=-1, stabilize=False):
+        """stabilize: momentum stabilization (subtract the mean fluid velocity
+        in every equilibrium), for fully periodic boxes with forced particles."""
         L = load()
         p = lbm_params()
         L.lbm_params_default(C.byref(p))
@@ -227,6 +231,7 @@ class Context:
         p.stream = stream
         p.sweep_grid = sweep_grid
         p.q_pad = q_pad
+        p.stabilize = int(bool(stabilize))
         h = C.c_void_p()
         r = L.lbm_create(C.byref(p), C.byref(h))
         if r != LBM_OK:
@@ -312,6 +317,13 @@ class Context:
 
     def set_populations(self, f):
         self._chk(load().lbm_set_populations(self._h, _d(_f64(f, 19 * self.ncell))))
+
+    def mean_velocity(self):
+        """Mean fluid velocity the next step subtracts, and the fluid cell count
+        (contexts created with stabilize=True)."""
+        u, n = np.zeros(3), C.c_int64()
+        self._chk(load().lbm_get_mean_velocity(self._h, _d(u), C.byref(n)))
+        return u, n.value
 
     def info(self):
         i = lbm_info()

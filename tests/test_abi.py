@@ -54,8 +54,8 @@ def test_lattice_table_needs_no_gpu():
 
 
 def test_struct_layout_matches_header():
-    # lbm_params: 5 int32 (+4 pad), 4 doubles, 3 doubles, 4 int32, int64, pointer, 2 int32
-    assert C.sizeof(lbm.lbm_params) == 5 * 4 + 4 + 4 * 8 + 3 * 8 + 4 * 4 + 8 + 8 + 2 * 4
+    # lbm_params: 5 int32 (+4 pad), 4 doubles, 3 doubles, 4 int32, int64, pointer, 4 int32
+    assert C.sizeof(lbm.lbm_params) == 5 * 4 + 4 + 4 * 8 + 3 * 8 + 4 * 4 + 8 + 8 + 4 * 4
     # centre, quaternion, L, r, density ratio, V, W; shape + reserved; force, torque
     assert C.sizeof(lbm.lbm_fiber) == (3 + 4 + 3 + 3 + 3) * 8 + 2 * 4 + 6 * 8
     assert C.sizeof(lbm.lbm_info) == 8 + 4 + 4 + 8 * 4
