@@ -387,6 +387,78 @@ static void rigid_implicit(const double *s, double mass, double i_par, double i_
 }
 
 /* ------------------------------------------------------------------------ */
+/* Contact between fibers.  The paper's rigid-body engine resolves          */
+/* frictional collisions of the particles (Sec. 4.4); this oracle uses a    */
+/* short-range repulsion instead (this project's reading): each fiber is a  */
+/* segment of its axis swept by its radius (rounded ends), and when the gap */
+/* between two such bodies falls below the range xi, a force               */
+/* K ((xi - gap)/xi)^2 pushes them apart along the line of their closest    */
+/* axis points, applied at the middle of the gap.                           */
+/* ------------------------------------------------------------------------ */
+static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+double or_segment_closest(const double Xp[3], const double tp[3], double hp, const double Xq[3],
+                          const double tq[3], double hq, double *s_out, double *u_out)
+{
+    /* minimise |d + u tq - s tp|^2, d = Xq - Xp, over the two intervals */
+    double d[3] = {Xq[0] - Xp[0], Xq[1] - Xp[1], Xq[2] - Xp[2]};
+    double b = tp[0] * tq[0] + tp[1] * tq[1] + tp[2] * tq[2];
+    double e = d[0] * tp[0] + d[1] * tp[1] + d[2] * tp[2];
+    double f = d[0] * tq[0] + d[1] * tq[1] + d[2] * tq[2];
+    double den = 1.0 - b * b, s;
+    if (den > 1e-12) {
+        s = clampd((e - b * f) / den, -hp, hp);   /* free minimiser in s, clamped */
+    } else {
+        /* parallel: middle of the overlap of the second segment's projection */
+        double lo = e - hq, hi = e + hq;
+        if (lo < -hp) lo = -hp;
+        if (hi > hp) hi = hp;
+        s = lo <= hi ? 0.5 * (lo + hi) : clampd(e, -hp, hp);
+    }
+    double u = clampd(s * b - f, -hq, hq);
+    s = clampd(e + u * b, -hp, hp);
+    double w[3];
+    for (int k = 0; k < 3; ++k) w[k] = d[k] + u * tq[k] - s * tp[k];
+    *s_out = s;
+    *u_out = u;
+    return sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+}
+
+double or_contact_pair(const double tp[3], double hp, double rp,
+                       const double dpq[3], const double tq[3], double hq, double rq, double k,
+                       double range, double Fp[3], double Mp[3], double Fq[3], double Mq[3])
+{
+    const double zero[3] = {0.0, 0.0, 0.0};
+    double s, u;
+    double dist = or_segment_closest(zero, tp, hp, dpq, tq, hq, &s, &u);
+    double gap = dist - rp - rq;
+    for (int i = 0; i < 3; ++i) Fp[i] = Mp[i] = Fq[i] = Mq[i] = 0.0;
+    if (!(k > 0.0) || gap >= range || dist <= 0.0) return gap;
+    double P[3], Qp[3], n[3];   /* closest axis points relative to X_p; n from p to q */
+    for (int i = 0; i < 3; ++i) {
+        P[i] = s * tp[i];
+        Qp[i] = dpq[i] + u * tq[i];
+        n[i] = (Qp[i] - P[i]) / dist;
+    }
+    double x = (range - gap) / range;
+    double mag = k * x * x;
+    double C[3];                 /* middle of the gap, relative to X_p */
+    for (int i = 0; i < 3; ++i) {
+        C[i] = P[i] + (rp + 0.5 * gap) * n[i];
+        Fp[i] = -mag * n[i];
+        Fq[i] = mag * n[i];
+    }
+    double Cq[3] = {C[0] - dpq[0], C[1] - dpq[1], C[2] - dpq[2]};   /* relative to X_q */
+    Mp[0] = C[1] * Fp[2] - C[2] * Fp[1];
+    Mp[1] = C[2] * Fp[0] - C[0] * Fp[2];
+    Mp[2] = C[0] * Fp[1] - C[1] * Fp[0];
+    Mq[0] = Cq[1] * Fq[2] - Cq[2] * Fq[1];
+    Mq[1] = Cq[2] * Fq[0] - Cq[0] * Fq[2];
+    Mq[2] = Cq[0] * Fq[1] - Cq[1] * Fq[0];
+    return gap;
+}
+
+/* ------------------------------------------------------------------------ */
 /* The coupled simulation                                                   */
 /* ------------------------------------------------------------------------ */
 typedef struct {
@@ -780,10 +852,39 @@ static void one_step(or_sim *s)
     /*    step's and the previous step's values: the plain sums let the        */
     /*    torque build a growing oscillation of period two steps at density    */
     /*    ratio 1 and small tau, which the mean removes.                       */
+    /* 2c. contact loads of every pair at the current poses (zero when the */
+    /*     repulsion is off), added to the external load of this step      */
+    double *cl = (double *)calloc((size_t)(s->nf ? s->nf : 1) * 6, sizeof(double));
+    if (p->contact_k > 0.0)
+        for (int i = 0; i < s->nf; ++i)
+            for (int j = i + 1; j < s->nf; ++j) {
+                const fiber *a = &s->fib[i], *b = &s->fib[j];
+                double ta[3], tb[3], d[3], Fa[3], Ma[3], Fb[3], Mb[3];
+                or_fiber_axis(a->st + 3, ta);
+                or_fiber_axis(b->st + 3, tb);
+                d[0] = min_image(b->st[0] - a->st[0], nx, 1);
+                d[1] = min_image(b->st[1] - a->st[1], ny, 1);
+                d[2] = min_image(b->st[2] - a->st[2], nz, p->z_periodic);
+                double ha = 0.5 * a->length - a->radius, hb = 0.5 * b->length - b->radius;
+                or_contact_pair(ta, ha > 0.0 ? ha : 0.0, a->radius, d, tb, hb > 0.0 ? hb : 0.0,
+                                b->radius, p->contact_k, p->contact_range, Fa, Ma, Fb, Mb);
+                for (int k = 0; k < 3; ++k) {
+                    cl[6 * i + k] += Fa[k];
+                    cl[6 * i + 3 + k] += Ma[k];
+                    cl[6 * j + k] += Fb[k];
+                    cl[6 * j + 3 + k] += Mb[k];
+                }
+            }
+
     double *old = (double *)malloc((size_t)(s->nf ? s->nf : 1) * 16 * sizeof(double));
     for (int i = 0; i < s->nf; ++i) {
         fiber *f = &s->fib[i];
         const double *rd = red + 39 * i;
+        double fe[3], me[3];   /* external plus contact load */
+        for (int k = 0; k < 3; ++k) {
+            fe[k] = f->fext[k] + cl[6 * i + k];
+            me[k] = f->mext[k] + cl[6 * i + 3 + k];
+        }
         memcpy(old + 16 * i, f->st, 16 * sizeof(double));
         /* closure correction of this step (zero when none was set) */
         double cF[3] = {0.0, 0.0, 0.0}, cM[3] = {0.0, 0.0, 0.0};
@@ -819,7 +920,7 @@ static void one_step(or_sim *s)
             }
             double out[16];
             rigid_implicit(f->st, f->mass, f->i_par, f->i_perp, F0u, M0u, rd + 12, rd + 21, rd + 30,
-                           f->fext, f->mext, nx, ny, nz, p->z_periodic, out, f->F, f->M);
+                           fe, me, nx, ny, nz, p->z_periodic, out, f->F, f->M);
             memcpy(f->st, out, 16 * sizeof(double));
         } else {
             for (int k = 0; k < 3; ++k) {
@@ -827,9 +928,9 @@ static void one_step(or_sim *s)
                 f->M[k] = f->has_corr ? rd[3 + k] + cM[k] : rd[3 + k];
             }
             double out[16], Ft[3], Mt[3];
-            for (int k = 0; k < 3; ++k) {   /* with the external load */
-                Ft[k] = f->F[k] + f->fext[k];
-                Mt[k] = f->M[k] + f->mext[k];
+            for (int k = 0; k < 3; ++k) {   /* with the external and contact load */
+                Ft[k] = f->F[k] + fe[k];
+                Mt[k] = f->M[k] + me[k];
             }
             or_rigid_step(f->st, f->mass, f->i_par, f->i_perp, Ft, Mt, nx, ny, nz, p->z_periodic,
                           out);
@@ -843,6 +944,7 @@ static void one_step(or_sim *s)
         f->has_corr = 0;
     }
     free(red);
+    free(cl);
 
     /* 4. remap with the new poses; refill uncovered cells with             */
     /*    f_eq(rho0, u_s) of the old owner's previous-step motion.          */

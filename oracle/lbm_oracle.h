@@ -54,6 +54,9 @@ typedef struct {
     int stabilize;     /* 1: momentum stabilization (Sec. 4.1, periodic domains under a
                           constant particle force): the mean velocity of all fluid cells
                           is subtracted from the velocity of every cell's equilibrium */
+    double contact_k;     /* > 0: short-range repulsion between fibers (contact model in place
+                             of the paper's frictional collision handling); 0: off */
+    double contact_range; /* surface gap below which the repulsion acts */
 } or_params;
 
 /* ---- building blocks (exposed so the tests can pin them one by one) ---- */
@@ -116,6 +119,16 @@ void    or_get_fiber_state(const or_sim *s, double *X, double *q, double *V, dou
 void    or_get_force_torque(const or_sim *s, double *F, double *M);
 int64_t or_get_history(const or_sim *s, int64_t first, int64_t count, double *out);
 int64_t or_overlaps(const or_sim *s);
+/* closest points of two axis segments X + s t, |s| <= h (t unit): returns the distance and
+   the parameters s (first segment) and u (second); parallel axes: middle of the overlap */
+double or_segment_closest(const double Xp[3], const double tp[3], double hp, const double Xq[3],
+                          const double tq[3], double hq, double *s, double *u);
+/* contact force and torque of fibers p and q (rounded ends: axis segments of half-length
+   L/2 - r, radius r), torques about their centres; dpq = minimum-image X_q - X_p;
+   returns the surface gap */
+double or_contact_pair(const double tp[3], double hp, double rp,
+                       const double dpq[3], const double tq[3], double hq, double rq, double k,
+                       double range, double Fp[3], double Mp[3], double Fq[3], double Mq[3]);
 /* mean velocity u = sum_q c_q f_q / rho0 + g/2 over the fluid cells of the current state
    (the quantity the momentum stabilization subtracts); returns the fluid cell count */
 int64_t or_mean_velocity(const or_sim *s, double ubar[3]);

@@ -24,7 +24,8 @@ class Params(C.Structure):
                 ("z_periodic", C.c_int), ("srt", C.c_int),
                 ("tau", C.c_double), ("magic", C.c_double), ("rho0", C.c_double),
                 ("wall_u", C.c_double), ("g", C.c_double * 3), ("init_couette", C.c_int),
-                ("coupling", C.c_int), ("stabilize", C.c_int)]
+                ("coupling", C.c_int), ("stabilize", C.c_int),
+                ("contact_k", C.c_double), ("contact_range", C.c_double)]
 
 
 def lib():
@@ -41,6 +42,11 @@ def lib():
         L.or_omega_odd.restype = C.c_double
         L.or_collide_cell.argtypes = [_dp, C.c_double, C.c_double, C.c_double, _dp, _dp]
         L.or_collide_cell_shift.argtypes = [_dp, C.c_double, C.c_double, C.c_double, _dp, _dp, _dp]
+        L.or_segment_closest.argtypes = [_dp, _dp, C.c_double, _dp, _dp, C.c_double, _dp, _dp]
+        L.or_segment_closest.restype = C.c_double
+        L.or_contact_pair.argtypes = [_dp, C.c_double, C.c_double, _dp, _dp, C.c_double, C.c_double,
+                                      C.c_double, C.c_double, _dp, _dp, _dp, _dp]
+        L.or_contact_pair.restype = C.c_double
         L.or_mean_velocity.argtypes = [C.c_void_p, _dp]
         L.or_mean_velocity.restype = C.c_int64
         L.or_fiber_axis.argtypes = [_dp, _dp]
@@ -177,14 +183,33 @@ def rigid_step(state, mass, i_par, i_perp, F, M, shape=(1 << 20, 1 << 20, 1 << 2
 COUPLING = {"implicit": 0, "explicit": 1, "implicit_plain": 2}
 
 
+def segment_closest(Xp, tp, hp, Xq, tq, hq):
+    """Distance of two axis segments X + s t, |s| <= h, and the parameters s, u."""
+    s, u = C.c_double(), C.c_double()
+    d = lib().or_segment_closest(_d(_arr(Xp, 3)), _d(_arr(tp, 3)), float(hp), _d(_arr(Xq, 3)),
+                                 _d(_arr(tq, 3)), float(hq), C.byref(s), C.byref(u))
+    return d, s.value, u.value
+
+
+def contact_pair(tp, hp, rp, dpq, tq, hq, rq, k, rng):
+    """Contact force and torque on p and q (X_p at the origin, X_q at dpq); returns
+    (gap, Fp, Mp, Fq, Mq)."""
+    out = [np.zeros(3) for _ in range(4)]
+    gap = lib().or_contact_pair(_d(_arr(tp, 3)), float(hp), float(rp), _d(_arr(dpq, 3)),
+                                _d(_arr(tq, 3)), float(hq), float(rq), float(k), float(rng),
+                                *[_d(o) for o in out])
+    return (gap, *out)
+
+
 class Sim:
     """One coupled simulation held by the oracle."""
 
     def __init__(self, nx, ny, nz, tau=0.8, magic=3.0 / 16.0, wall_u=0.0, rho0=1.0,
                  z_periodic=False, srt=False, g=(0.0, 0.0, 0.0), init_couette=False,
-                 coupling="implicit", stabilize=False):
+                 coupling="implicit", stabilize=False, contact_k=0.0, contact_range=1.0):
         p = Params(nx, ny, nz, int(z_periodic), int(srt), tau, magic, rho0, wall_u,
-                   (C.c_double * 3)(*g), int(init_couette), COUPLING[coupling], int(stabilize))
+                   (C.c_double * 3)(*g), int(init_couette), COUPLING[coupling], int(stabilize),
+                   float(contact_k), float(contact_range))
         self.shape = (nx, ny, nz)
         self.ncell = nx * ny * nz
         self._h = lib().or_create(C.byref(p))

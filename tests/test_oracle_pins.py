@@ -512,6 +512,98 @@ def test_stabilized_momentum_budget_with_a_forced_particle():
         p0 = p1
 
 
+# --------------------------------------------------- contact between fibers (Sec. 4.4)
+def _rand_unit(rng):
+    v = rng.standard_normal(3)
+    return v / np.linalg.norm(v)
+
+
+def test_segment_closest_points_against_brute_force():
+    """Closest points of two axis segments, against a fine grid over both
+    parameters, for random pairs including parallel, antiparallel and
+    end-to-end ones: the distance is never above the grid minimum and lies
+    within the grid's resolution of it, and the returned parameters give it."""
+    rng = np.random.default_rng(11)
+    cases = []
+    for i in range(40):
+        tp, tq = _rand_unit(rng), _rand_unit(rng)
+        if i % 8 == 1:
+            tq = tp.copy()
+        if i % 8 == 2:
+            tq = -tp
+        Xq = rng.uniform(-6, 6, 3)
+        if i % 8 == 3:
+            Xq = tp * 9.0 + 0.3 * _rand_unit(rng)
+        cases.append((tp, rng.uniform(0.5, 5), Xq, tq, rng.uniform(0.5, 5)))
+    for tp, hp, Xq, tq, hq in cases:
+        d, s, u = O.segment_closest(np.zeros(3), tp, hp, Xq, tq, hq)
+        assert abs(s) <= hp and abs(u) <= hq
+        np.testing.assert_allclose(d, np.linalg.norm(Xq + u * tq - s * tp), rtol=1e-12, atol=1e-12)
+        S = np.linspace(-hp, hp, 801)[:, None, None]
+        U = np.linspace(-hq, hq, 801)[None, :, None]
+        brute = np.linalg.norm(Xq + U * tq - S * tp, axis=2).min()
+        assert d <= brute + 1e-12
+        assert brute - d < 2.5 * (hp + hq) / 800
+
+
+def test_contact_side_by_side_closed_form():
+    """Two parallel rounded fibers side by side, centres D apart across their
+    axes: gap D - 2r, force K ((xi - gap)/xi)^2 pushing them apart along the
+    line of centres, no torque; nothing beyond the range."""
+    t = np.array([0.0, 0.0, 1.0])
+    K, xi, r, h = 0.7, 1.5, 2.0, 4.0
+    for D in (4.3, 4.9, 5.4, 5.6):
+        gap, Fp, Mp, Fq, Mq = O.contact_pair(t, h, r, [D, 0, 0], t, h, r, K, xi)
+        assert abs(gap - (D - 2 * r)) < 1e-14
+        mag = K * ((xi - gap) / xi) ** 2 if gap < xi else 0.0
+        np.testing.assert_allclose(Fp, [-mag, 0, 0], atol=1e-15)
+        np.testing.assert_allclose(Fq, [mag, 0, 0], atol=1e-15)
+        np.testing.assert_allclose(Mp, 0, atol=1e-15)
+        np.testing.assert_allclose(Mq, 0, atol=1e-15)
+
+
+def test_contact_is_a_central_pair_force():
+    """Random close pairs: F_q = -F_p (Newton's third law) and the pair's
+    total torque about X_p vanishes, M_p + M_q + (X_q - X_p) x F_q = 0 (both
+    forces act at one point); the force points from q's axis towards p's."""
+    rng = np.random.default_rng(5)
+    hits = 0
+    for _ in range(60):
+        tp, tq = _rand_unit(rng), _rand_unit(rng)
+        d = rng.uniform(-5, 5, 3)
+        gap, Fp, Mp, Fq, Mq = O.contact_pair(tp, 3.0, 1.5, d, tq, 2.0, 1.0, 0.9, 2.0)
+        np.testing.assert_allclose(Fq, -Fp, atol=1e-15)
+        np.testing.assert_allclose(Mp + Mq + np.cross(d, Fq), 0, atol=1e-13)
+        if gap < 2.0:
+            hits += 1
+            dist, s, u = O.segment_closest(np.zeros(3), tp, 3.0, d, tq, 2.0)
+            n = (d + u * tq - s * tp) / dist
+            assert np.dot(Fp, n) < 0 and np.linalg.norm(np.cross(Fp, n)) < 1e-13
+        else:
+            assert not Fp.any() and not Mp.any()
+    assert hits > 10
+
+
+def test_contact_static_equilibrium_in_fluid():
+    """Two parallel spherocylinders pushed together by opposite external
+    forces +-F in a periodic box settle where the repulsion balances the
+    push: gap = xi (1 - sqrt(F / K)), with the hydrodynamic force gone."""
+    K, xi, F = 0.2, 1.5, 0.05
+    sim = O.Sim(24, 16, 24, tau=0.8, z_periodic=True, contact_k=K, contact_range=xi)
+    q = _quat_to(np.array([0.0, 0.0, 1.0]))
+    sim.add_fiber([9.25, 8.0, 12.0], q, 10.0, 2.0, 1.0, shape="spherocylinder", force=(F, 0, 0))
+    sim.add_fiber([14.75, 8.0, 12.0], q, 10.0, 2.0, 1.0, shape="spherocylinder", force=(-F, 0, 0))
+    sim.step(5000)
+    X, _, V, _ = sim.fiber_state()
+    gap = (X[1, 0] - X[0, 0]) - 4.0
+    Fh, _ = sim.force_torque()
+    print("gap %.5f (equilibrium %.5f), V %.2e, F_h %.2e" % (gap, xi * (1 - np.sqrt(F / K)),
+                                                             np.abs(V).max(), np.abs(Fh).max()))
+    np.testing.assert_allclose(gap, xi * (1.0 - np.sqrt(F / K)), rtol=2e-3)
+    assert np.abs(V).max() < 1e-6 and np.abs(Fh).max() < 1e-3 * F
+    assert sim.overlaps == 0
+
+
 # ---------------------------------------------------------------- P13 rigid body
 def test_quaternion_update_constant_rotation():
     """Rigid update (Sec. 4.3; integrator is this project's reading): with no
