@@ -98,6 +98,17 @@ typedef struct {
     int32_t q_pad;             /* extra elements between direction arrays; -1 = automatic */
     int32_t stabilize;         /* 1: momentum stabilization (see lbm_get_mean_velocity); 0: off */
     int32_t reserved;          /* 0 */
+    /* Contact between fibers (0: off).  The paper's rigid-body engine resolves
+     * frictional collisions of the particles (Sec. 4.4); this library applies
+     * a short-range repulsion instead: each fiber is the segment of its axis
+     * of half-length max(L/2 - r, 0) swept by its radius, and when the gap
+     * between two of them is below contact_range a force
+     * contact_stiffness ((contact_range - gap)/contact_range)^2 pushes them
+     * apart along the line of their closest axis points, applied at the
+     * middle of the gap and added to the external load of the step (lattice
+     * units).  With contacts at most 248 fibers per context. */
+    double contact_stiffness;
+    double contact_range;
 } lbm_params;
 
 /* Fiber shapes: a circular cylinder of length L, or a spherocylinder (a
@@ -143,7 +154,7 @@ typedef struct {
 
 /* Fill *p with defaults: 32^3, walls, TRT, tau 0.8, Lambda 3/16, U 0,
  * rho0 1, F32, rest, implicit coupling, k = 14, history 4096, NULL stream,
- * automatic sweep grid and padding. */
+ * automatic sweep grid and padding, no stabilization, no contacts (range 1). */
 lbm_status lbm_params_default(lbm_params *p);
 
 /* Allocate the lattice and initialise f = f_eq(rho0, u0(z)) (Eq.

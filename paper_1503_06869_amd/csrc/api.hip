@@ -210,6 +210,8 @@ static PartData part_data(lbm_ctx *c, PState *cur, PState *next)
     pd.corr = c->closure ? c->corr : nullptr;
     pd.ctr = c->ctr;
     pd.list_cap = c->list_cap;
+    pd.contact_k = c->p.contact_stiffness;
+    pd.contact_range = c->p.contact_range;
     return pd;
 }
 
@@ -470,6 +472,7 @@ lbm_status lbm_params_default(lbm_params *p)
     p->history_capacity = 4096;
     p->sweep_grid = 0;
     p->q_pad = -1;
+    p->contact_range = 1.0;
     return LBM_OK;
 }
 
@@ -501,6 +504,8 @@ lbm_status lbm_create(const lbm_params *p, lbm_ctx **out)
     if (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 20) return LBM_E_ARG;
     if (p->coupling < LBM_COUPLING_IMPLICIT || p->coupling > LBM_COUPLING_IMPLICIT_PLAIN) return LBM_E_ARG;
     if (p->stabilize != 0 && p->stabilize != 1) return LBM_E_ARG;
+    if (!(p->contact_stiffness >= 0.0) || !std::isfinite(p->contact_stiffness)) return LBM_E_ARG;
+    if (p->contact_stiffness > 0.0 && !(p->contact_range > 0.0 && std::isfinite(p->contact_range))) return LBM_E_ARG;
     // changed-cell entries keep a flag in bit 31
     if (p->stabilize && ncell >= 2147483648.0) return LBM_E_ARG;
     lbm_ctx *c = new (std::nothrow) lbm_ctx;
@@ -644,6 +649,8 @@ lbm_status lbm_add_fiber(lbm_ctx *c, const lbm_fiber *f, int32_t *id)
             return fail(c, LBM_E_GEOM, "fiber within one cell of a wall");
     }
     if ((c->np + 1) * NACC * 8 > 65536) return fail(c, LBM_E_ARG, "at most 302 fibers per context");
+    if (c->p.contact_stiffness > 0.0 && (c->np + 1) * (NACC + 6) * 8 > 65536)
+        return fail(c, LBM_E_ARG, "at most 248 fibers per context with contacts");
     const PConst pc = fiber_constants(f->length, f->radius, f->density_ratio * c->p.rho0, f->shape, f->force,
                                       f->torque);
     c->fib.push_back(*f);

@@ -189,6 +189,8 @@ struct PartData {
     uint32_t *seg_cnt;         // [np] entries
     uint32_t *cov;             // cells whose owner changed (stabilization), or null
     uint32_t cov_cap;
+    double contact_k;          // > 0: repulsion between fibers of stiffness contact_k
+    double contact_range;      // gap below which it acts
 };
 
 // ---------------------------------------------------------------------------

@@ -281,9 +281,69 @@ __device__ __forceinline__ void unpack(const double *acc, double A[3][3], double
 // small tau.  The new state carries this step's F0, M0 forward.  corr
 // (dF[3], dM[3] of a closure, or null) is added to the force and torque
 // (to F0, M0 for the implicit forms).
+// ------------------------------------------------------------------ contact
+// Short-range repulsion between fibers (in place of the collision handling
+// of the paper's rigid-body engine, Sec. 4.4): a fiber is the segment of its
+// axis of half-length max(L/2 - r, 0) swept by its radius.  With the closest
+// axis points P (on a) and Q (on b), dist = |Q - P| and gap = dist - r_a - r_b,
+// a gap below the range xi gives the force k ((xi - gap)/xi)^2 along
+// n = (Q - P)/dist: -that on a, +that on b, both at the middle of the gap.
+
+__device__ __forceinline__ double clamp_d(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Contact load (force, torque about the own centre) on fiber `me` of the pair
+// (a, b), a < b, computed in this orientation for either member so that the
+// two loads are exact opposites.
+__device__ __forceinline__ void contact_load(const PState &sa, const PConst &ca, const PState &sb,
+                                             const PConst &cb, bool me_is_a, double k, double range,
+                                             const Geo &g, double out[6])
+{
+    const double d[3] = {mi(sb.X[0] - sa.X[0], g.nx, true), mi(sb.X[1] - sa.X[1], g.ny, true),
+                         mi(sb.X[2] - sa.X[2], g.nz, g.zper != 0)};
+    const double ha0 = 0.5 * ca.length - ca.radius, hb0 = 0.5 * cb.length - cb.radius;
+    const double ha = ha0 > 0.0 ? ha0 : 0.0, hb = hb0 > 0.0 ? hb0 : 0.0;
+    const double *ta = sa.t, *tb = sb.t;
+    const double bb = ta[0] * tb[0] + ta[1] * tb[1] + ta[2] * tb[2];
+    const double e = d[0] * ta[0] + d[1] * ta[1] + d[2] * ta[2];
+    const double f = d[0] * tb[0] + d[1] * tb[1] + d[2] * tb[2];
+    const double den = 1.0 - bb * bb;
+    double s;
+    if (den > 1e-12) {
+        s = clamp_d((e - bb * f) / den, -ha, ha);
+    } else {   // parallel axes: middle of the overlap
+        const double lo = e - hb < -ha ? -ha : e - hb, hi = e + hb > ha ? ha : e + hb;
+        s = lo <= hi ? 0.5 * (lo + hi) : clamp_d(e, -ha, ha);
+    }
+    const double u = clamp_d(s * bb - f, -hb, hb);
+    s = clamp_d(e + u * bb, -ha, ha);
+    double w[3];
+    for (int i = 0; i < 3; ++i) w[i] = d[i] + u * tb[i] - s * ta[i];
+    const double dist = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    const double gap = dist - ca.radius - cb.radius;
+    for (int i = 0; i < 6; ++i) out[i] = 0.0;
+    if (!(gap < range) || !(dist > 0.0)) return;
+    const double x = (range - gap) / range;
+    const double mag = k * x * x;
+    double P[3], n[3], C[3], F[3];
+    for (int i = 0; i < 3; ++i) {
+        P[i] = s * ta[i];
+        n[i] = ((d[i] + u * tb[i]) - P[i]) / dist;
+    }
+    for (int i = 0; i < 3; ++i) {
+        C[i] = P[i] + (ca.radius + 0.5 * gap) * n[i];   // relative to X_a
+        F[i] = me_is_a ? -mag * n[i] : mag * n[i];
+        if (!me_is_a) C[i] = C[i] - d[i];               // relative to X_b
+    }
+    for (int i = 0; i < 3; ++i) out[i] = F[i];
+    out[3] = C[1] * F[2] - C[2] * F[1];
+    out[4] = C[2] * F[0] - C[0] * F[2];
+    out[5] = C[0] * F[1] - C[1] * F[0];
+}
+
+// fc: contact force and torque added to the external load of this step (or null)
 __device__ __forceinline__ void rigid_update(const PState &s, const PConst &c, const double *acc, int coupling,
                              const double *traj_row, const Geo &g, PState &o, double F[3], double M[3],
-                             const double *corr = nullptr)
+                             const double *corr = nullptr, const double *fc = nullptr)
 {
     double A[3][3], B[3][3], C[3][3];
     unpack(acc, A, B, C);
@@ -336,9 +396,14 @@ __device__ __forceinline__ void rigid_update(const PState &s, const PConst &c, c
                 K[3 + i][j] = B[j][i];
                 K[3 + i][3 + j] = Iw + C[i][j];
             }
+        double fe[3], me[3];
         for (int i = 0; i < 3; ++i) {
-            b[i] = c.mass * s.V[i] + F0u[i] + c.fext[i];
-            b[3 + i] = s.L[i] + M0u[i] + c.mext[i];
+            fe[i] = fc ? c.fext[i] + fc[i] : c.fext[i];
+            me[i] = fc ? c.mext[i] + fc[3 + i] : c.mext[i];
+        }
+        for (int i = 0; i < 3; ++i) {
+            b[i] = c.mass * s.V[i] + F0u[i] + fe[i];
+            b[3 + i] = s.L[i] + M0u[i] + me[i];
         }
         chol6(K, b, x);
         for (int i = 0; i < 3; ++i) {
@@ -354,11 +419,13 @@ __device__ __forceinline__ void rigid_update(const PState &s, const PConst &c, c
             F[i] = f;
             M[i] = m;
         }
-        for (int i = 0; i < 3; ++i) Ln[i] = s.L[i] + M[i] + c.mext[i];
+        for (int i = 0; i < 3; ++i) Ln[i] = s.L[i] + M[i] + me[i];
     } else {
         for (int i = 0; i < 3; ++i) {
-            Vn[i] = s.V[i] + (F[i] + c.fext[i]) / c.mass;
-            Ln[i] = s.L[i] + (M[i] + c.mext[i]);
+            const double fe = fc ? c.fext[i] + fc[i] : c.fext[i];
+            const double me = fc ? c.mext[i] + fc[3 + i] : c.mext[i];
+            Vn[i] = s.V[i] + (F[i] + fe) / c.mass;
+            Ln[i] = s.L[i] + (M[i] + me);
         }
         const double tl = s.t[0] * Ln[0] + s.t[1] * Ln[1] + s.t[2] * Ln[2];
         for (int i = 0; i < 3; ++i)

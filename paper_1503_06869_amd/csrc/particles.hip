@@ -64,8 +64,8 @@ __global__ __launch_bounds__(256) void k_setup_boxes(PartData pd, Geo g)
 
 // ------------------------------------------------------------------ rigid update kernel
 // One block: the momentum-exchange sums of every fiber (accumulated in fixed
-// point by the boundary sweep) back to FP64, the rigid-body update, outputs,
-// the boxes of the remap and the list reset.
+// point by the boundary sweep) back to FP64, the contact loads (when on), the
+// rigid-body update, outputs, the boxes of the remap and the list reset.
 __global__ __launch_bounds__(256) void k_rigid(PartData pd, Geo g)
 {
     extern __shared__ double tot[];   // [np][NACC]
@@ -75,6 +75,23 @@ __global__ __launch_bounds__(256) void k_rigid(PartData pd, Geo g)
         tot[t] = ldexp(double(pd.mea[t]), -fx_shift(k));
         pd.mea[t] = 0;   // cleared for the next step's boundary sweep
     }
+    // contact loads at the current poses, each pair in the orientation (lower
+    // id, higher id) and summed over partners in ascending order
+    double *cl = tot + size_t(np) * NACC;   // [np][6] when contacts are on
+    if (pd.contact_k > 0.0)
+        for (int p = threadIdx.x; p < np; p += blockDim.x) {
+            double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            const PState sp = pd.ps_cur[p];
+            const PConst cp = pd.pc[p];
+            for (int q = 0; q < np; ++q) {
+                if (q == p) continue;
+                double l[6];
+                if (p < q) contact_load(sp, cp, pd.ps_cur[q], pd.pc[q], true, pd.contact_k, pd.contact_range, g, l);
+                else contact_load(pd.ps_cur[q], pd.pc[q], sp, cp, false, pd.contact_k, pd.contact_range, g, l);
+                for (int k = 0; k < 6; ++k) acc[k] += l[k];
+            }
+            for (int k = 0; k < 6; ++k) cl[p * 6 + k] = acc[k];
+        }
     __syncthreads();
     const int64_t step = int64_t(pd.ctr->step);
     for (int p = threadIdx.x; p < np; p += blockDim.x) {
@@ -89,7 +106,8 @@ __global__ __launch_bounds__(256) void k_rigid(PartData pd, Geo g)
         }
         PState o;
         double F[3], M[3];
-        rigid_update(s, c, ac, pd.coupling, row, g, o, F, M, pd.corr ? pd.corr + size_t(p) * 6 : nullptr);
+        rigid_update(s, c, ac, pd.coupling, row, g, o, F, M, pd.corr ? pd.corr + size_t(p) * 6 : nullptr,
+                     pd.contact_k > 0.0 ? cl + size_t(p) * 6 : nullptr);
         bool bad = false;
         for (int k = 0; k < 3; ++k) bad |= !isfinite(F[k]) || !isfinite(M[k]);
         if (bad) atomicOr(&pd.ctr->err_unstable, 1u);
@@ -370,7 +388,8 @@ __global__ __launch_bounds__(256) void k_near(uint8_t *__restrict__ flags, const
 // ------------------------------------------------------------------ launchers
 hipError_t launch_rigid(const PartData &pd, const Geo &g, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_rigid, dim3(1), dim3(256), size_t(pd.np) * NACC * sizeof(double), st, pd, g);
+    const size_t per = NACC + (pd.contact_k > 0.0 ? 6 : 0);
+    hipLaunchKernelGGL(k_rigid, dim3(1), dim3(256), size_t(pd.np) * per * sizeof(double), st, pd, g);
     return hipGetLastError();
 }
 

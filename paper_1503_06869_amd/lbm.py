@@ -56,7 +56,8 @@ class lbm_params(C.Structure):
                 ("storage", C.c_int32), ("init_profile", C.c_int32), ("coupling", C.c_int32),
                 ("fp16_scale_log2", C.c_int32), ("history_capacity", C.c_int64),
                 ("stream", C.c_void_p), ("sweep_grid", C.c_int32), ("q_pad", C.c_int32),
-                ("stabilize", C.c_int32), ("reserved", C.c_int32)]
+                ("stabilize", C.c_int32), ("reserved", C.c_int32),
+                ("contact_stiffness", C.c_double), ("contact_range", C.c_double)]
 
 
 class lbm_fiber(C.Structure):
@@ -212,9 +213,11 @@ class Context:
     def __init__(self, nx, ny, nz, tau=0.8, magic=3.0 / 16.0, wall_u=0.0, rho0=1.0,
                  z_periodic=False, collision="trt", storage="f32", init_couette=False,
                  coupling="implicit", body_force=(0.0, 0.0, 0.0), fp16_scale_log2=14,
-                 history_capacity=4096, stream=None, sweep_grid=0, q_pad=-1, stabilize=False):
+                 history_capacity=4096, stream=None, sweep_grid=0, q_pad=-1, stabilize=False,
+                 contact_k=0.0, contact_range=1.0):
         """stabilize: momentum stabilization (subtract the mean fluid velocity
-        in every equilibrium), for fully periodic boxes with forced particles."""
+        in every equilibrium), for fully periodic boxes with forced particles.
+        contact_k, contact_range: short-range repulsion between fibers (off at 0)."""
         L = load()
         p = lbm_params()
         L.lbm_params_default(C.byref(p))
@@ -232,6 +235,8 @@ class Context:
         p.sweep_grid = sweep_grid
         p.q_pad = q_pad
         p.stabilize = int(bool(stabilize))
+        p.contact_stiffness = float(contact_k)
+        p.contact_range = float(contact_range)
         h = C.c_void_p()
         r = L.lbm_create(C.byref(p), C.byref(h))
         if r != LBM_OK:

@@ -2,6 +2,7 @@
 rotational validation, Sec. 5.1 setup and its appendix table).
 
     python -m paper_1503_06869_amd.validation [--aspect 4] [--n 816] [--steps 40000]
+    python -m paper_1503_06869_amd.validation --case tumbling [--aspect 12] [--dist 14.8] [--n 576]
 
 The paper's setup: spherocylinders of radius r = 4 dx and L = (1/eps) r
 (L including the caps), dx = 1e-5 m, water (nu = 1e-6 m^2/s, rho_f =
@@ -95,15 +96,136 @@ def run(aspect, n, steps, every, log=print):
     }
 
 
+# ---------------------------------------------------------------------------
+# Two tumbling, sedimenting spherocylinders (Sec. 6 setup and results): r = 4
+# dx with dx = 4.98e-6 m, L = (1/eps) r, water, tau = 6, particle density
+# 1492 kg/m^3, side by side in x at centre distance dist, axes along the
+# force (z), in a fully periodic cube with momentum stabilization, pushed
+# along z by the buoyancy-corrected weight of its table of forces.
+TUMBLE_DX = 4.98e-6      # m
+TUMBLE_RHO_P = 1492.0    # kg/m^3
+TUMBLE_FORCE = {10: 1.119e-9, 12: 1.358e-9, 14: 1.598e-9}   # F_z [kg m/s^2]
+# first tumbling period in the 576^3 box (its table of the time evolution):
+# (aspect, dist [dx]) -> D* [m], T* [s], U* [m/s]
+TUMBLE_PERIOD1 = {(10, 16.0): (4.38e-3, 2.71, 1.61e-3), (12, 14.8): (4.18e-3, 2.13, 1.96e-3)}
+
+
+def tumble_dt():
+    """nu = (tau - 1/2)/3 dx^2/dt (Eq. kinVisc) at the tumbling dx."""
+    return (TAU - 0.5) / 3.0 * TUMBLE_DX * TUMBLE_DX / NU
+
+
+def lattice_force(force_si, dx=None, dt_s=None):
+    """kg m/s^2 to lattice units (mass rho_f dx^3, length dx, time dt)."""
+    dx = TUMBLE_DX if dx is None else dx
+    dt_s = tumble_dt() if dt_s is None else dt_s
+    return force_si / (RHO_F * dx ** 4 / dt_s ** 2)
+
+
+def tumbling_periods(steps, axis_xz, z):
+    """Tumbling periods of one particle from samples of its axis (t_x, t_z)
+    and its unwrapped z position: a period ends each time the axis has turned
+    by another half revolution from its start (the shape is symmetric under
+    t -> -t, so the doubled angle is used).  Crossings are interpolated
+    linearly between samples.  Returns [(step_end, z_end)] for the period
+    ends, the start (0, z[0]) first."""
+    t = np.asarray(axis_xz, dtype=np.float64)
+    phi = np.unwrap(np.arctan2(2.0 * t[:, 0] * t[:, 1], t[:, 1] ** 2 - t[:, 0] ** 2))
+    turn = np.abs(phi - phi[0]) / (2.0 * np.pi)
+    ends = [(float(steps[0]), float(z[0]))]
+    k = 1
+    for i in range(1, len(turn)):
+        while turn[i - 1] < k <= turn[i]:
+            w = (k - turn[i - 1]) / (turn[i] - turn[i - 1])
+            ends.append((steps[i - 1] + w * (steps[i] - steps[i - 1]), z[i - 1] + w * (z[i] - z[i - 1])))
+            k += 1
+    return ends
+
+
+def run_tumbling(aspect, n, dist, steps, every, storage="f32", contact_k=0.0, contact_range=2.0, log=print):
+    """contact_k, contact_range: the short-range repulsion standing in for the
+    paper's collision handling (off at 0); the trailing ends of the pair
+    approach each other within the first tenth of a revolution."""
+    from . import lbm
+    L = aspect * R_CELLS
+    F = lattice_force(TUMBLE_FORCE[aspect])
+    g = lbm.Context(n, n, n, tau=TAU, z_periodic=True, stabilize=True, storage=storage, contact_k=contact_k,
+                    contact_range=contact_range)
+    c = 0.5 * (n - 1)
+    q = (math.cos(math.pi / 4), 0.0, -math.sin(math.pi / 4), 0.0)   # axis along +z
+    for s in (-1.0, 1.0):
+        g.add_fiber((c + 0.5 * s * dist, c, c), q, L, R_CELLS, TUMBLE_RHO_P / RHO_F, shape="spherocylinder",
+                    force=(0.0, 0.0, F))
+    rows = []
+    zu, zprev = None, None
+    t0 = time.time()
+    done = 0
+    while done < steps:
+        k = min(every, steps - done)
+        g.step(k)
+        done += k
+        X, qq, V, W = g.fiber_state()
+        t = np.array([1.0 - 2.0 * (qq[0, 2] ** 2 + qq[0, 3] ** 2), 2.0 * (qq[0, 1] * qq[0, 2] + qq[0, 0] * qq[0, 3]),
+                      2.0 * (qq[0, 1] * qq[0, 3] - qq[0, 0] * qq[0, 2])])
+        z = X[0, 2]
+        if zu is None:
+            zu = z
+        else:
+            dz = z - zprev
+            zu += dz - n * round(dz / n)
+        zprev = z
+        sep = (X[1, 0] - X[0, 0]) % n
+        rows.append([done, t[0], t[2], zu, V[0, 0], V[0, 2], sep])
+        if done % (10 * every) == 0 or done == steps:
+            log("step %7d  axis (%.3f, %.3f)  z %.2f  V (%.3e, %.3e)  sep %.2f  %.0f s"
+                % (done, t[0], t[2], zu, V[0, 0], V[0, 2], sep, time.time() - t0))
+    g.close()
+    h = np.asarray(rows)
+    ends = tumbling_periods(np.r_[0.0, h[:, 0]], np.r_[[[0.0, 1.0]], h[:, 1:3]],
+                            np.r_[c, h[:, 3]])
+    dts = tumble_dt()
+    periods = []
+    for (s0, z0), (s1, z1) in zip(ends[:-1], ends[1:]):
+        sel = (h[:, 0] >= s0) & (h[:, 0] <= s1)
+        T = (s1 - s0) * dts
+        D = (z1 - z0) * TUMBLE_DX
+        periods.append({"T_s": T, "D_m": D, "U_m_s": D / T,
+                        "ux_min_m_s": float(h[sel, 4].min() * TUMBLE_DX / dts),
+                        "ux_max_m_s": float(h[sel, 4].max() * TUMBLE_DX / dts),
+                        "uz_min_m_s": float(h[sel, 5].min() * TUMBLE_DX / dts),
+                        "uz_max_m_s": float(h[sel, 5].max() * TUMBLE_DX / dts),
+                        "sep_min_dx": float(h[sel, 6].min()), "sep_max_dx": float(h[sel, 6].max())})
+    ref = TUMBLE_PERIOD1.get((aspect, float(dist)))
+    return {"aspect": aspect, "n": n, "dist_dx": dist, "steps": steps, "storage": storage,
+            "contact_k": contact_k, "contact_range": contact_range,
+            "dt_s": dts, "force_lattice": F, "periods": periods,
+            "paper_period1": {"D_m": ref[0], "T_s": ref[1], "U_m_s": ref[2]} if ref else None,
+            "history": h.tolist()}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--aspect", type=int, default=4, choices=sorted(TORQUE))
-    ap.add_argument("--n", type=int, default=816)
-    ap.add_argument("--steps", type=int, default=40000)
-    ap.add_argument("--every", type=int, default=1000)
+    ap.add_argument("--case", default="rotation", choices=("rotation", "tumbling"))
+    ap.add_argument("--aspect", type=int, default=None)
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--dist", type=float, default=14.8)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--every", type=int, default=None)
+    ap.add_argument("--storage", default="f32")
+    ap.add_argument("--contact-k", type=float, default=0.0)
+    ap.add_argument("--contact-range", type=float, default=2.0)
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
-    res = run(a.aspect, a.n, a.steps, a.every, log=lambda s: print(s, flush=True))
+    if a.case == "tumbling":
+        res = run_tumbling(a.aspect or 12, a.n or 576, a.dist, a.steps or 50000, a.every or 200, a.storage,
+                           a.contact_k, a.contact_range, log=lambda s: print(s, flush=True))
+        line = {k: v for k, v in res.items() if k != "history"}
+        print(json.dumps(line), flush=True)
+        if a.out:
+            with open(a.out, "w") as fh:
+                json.dump(res, fh)
+        return 0
+    res = run(a.aspect or 4, a.n or 816, a.steps or 40000, a.every or 1000, log=lambda s: print(s, flush=True))
     line = {k: v for k, v in res.items() if k != "history"}
     print(json.dumps(line), flush=True)
     if a.out:

@@ -41,3 +41,70 @@ def test_lattice_units_round_trip():
     M = 12.26e-15
     m_lat = V.lattice_torque(M)
     np.testing.assert_allclose(m_lat * V.RHO_F * V.DX ** 5 / V.dt() ** 2, M, rtol=1e-14)
+
+
+# ----------------------------------------------------------- tumbling pair (Sec. 6)
+TUMBLE = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "tumbling_validation.json")))
+
+
+def test_tumbling_parameters_are_the_papers():
+    """dx, density, radius and the forces of the driver are the printed ones;
+    dt from Eq. kinVisc with tau = 6 is the printed 4.55e-5 s."""
+    assert V.TUMBLE_DX == TUMBLE["dx_m"] and V.TUMBLE_RHO_P == TUMBLE["rho_p_kg_m3"]
+    assert V.TAU == TUMBLE["tau"] and V.R_CELLS == TUMBLE["radius_dx"]
+    assert abs(V.tumble_dt() - TUMBLE["dt_s"]) < 0.005e-5
+    for A, F in zip(TUMBLE["aspect_ratios"], TUMBLE["force_z_1e-9_kg_m_s2"]):
+        assert abs(V.TUMBLE_FORCE[A] / (F * 1e-9) - 1) < 1e-12
+    for (A, d), (D, T, U) in V.TUMBLE_PERIOD1.items():
+        ev = TUMBLE["evolution"]["%d_dist%.1f" % (A, d)]
+        assert (D, T, U) == (ev["D_1e-3_m"][0] * 1e-3, ev["T_s"][0], ev["U_1e-3_m_s"][0] * 1e-3)
+
+
+def test_tumbling_force_is_the_buoyancy_corrected_weight_of_a_spherocylinder():
+    """The printed forces are (rho_p - rho_f) V g with V the spherocylinder
+    volume pi r^2 (L - 2r) + 4/3 pi r^3 (L including the caps, L = r/eps) and
+    g = 9.81 m/s^2, to the printed four digits: the reading of the force
+    table and of the particle length used by the driver."""
+    dx, r = TUMBLE["dx_m"], TUMBLE["radius_dx"]
+    for A, F in zip(TUMBLE["aspect_ratios"], TUMBLE["force_z_1e-9_kg_m_s2"]):
+        L = A * r
+        vol = (np.pi * r * r * (L - 2 * r) + 4.0 / 3.0 * np.pi * r ** 3) * dx ** 3
+        Fw = (TUMBLE["rho_p_kg_m3"] - TUMBLE["rho_f_kg_m3"]) * vol * 9.81
+        assert abs(Fw / (F * 1e-9) - 1) < 1e-3, (A, Fw)
+
+
+def test_tumbling_tables_are_consistent():
+    """U* = D*/T* in every printed period within the rounding of the three
+    printed digits; for 1/eps = 10 the terminal table's entry is period 7 of
+    the time-evolution table."""
+    for key, ev in TUMBLE["evolution"].items():
+        for D, T, U in zip(ev["D_1e-3_m"], ev["T_s"], ev["U_1e-3_m_s"]):
+            lo, hi = (D - 0.005) / (T + 0.005), (D + 0.005) / (T - 0.005)
+            assert lo <= U + 0.005 and hi >= U - 0.005, (key, D, T, U)
+    term, ev = TUMBLE["terminal_576"], TUMBLE["evolution"]["10_dist16.0"]
+    assert (term["D_1e-3_m"][0], term["T_s"][0], term["U_1e-3_m_s"][0]) == \
+        (ev["D_1e-3_m"][-1], ev["T_s"][-1], ev["U_1e-3_m_s"][-1])
+
+
+def test_force_in_lattice_units_round_trip():
+    F = 1.358e-9
+    f_lat = V.lattice_force(F)
+    np.testing.assert_allclose(f_lat * V.RHO_F * V.TUMBLE_DX ** 4 / V.tumble_dt() ** 2, F, rtol=1e-14)
+    # the terminal speed of the table in lattice units is far below the lattice sound speed
+    assert TUMBLE["terminal_576"]["uz_max_1e-3_m_s"][3] * 1e-3 * V.tumble_dt() / V.TUMBLE_DX < 0.05
+
+
+def test_period_detection_on_a_uniform_tumble():
+    """Axis turning at a constant rate w (per step) with z rising at speed v:
+    periods end every pi / w steps, each with D = v pi / w; the detection
+    does not depend on the sign of the axis vector."""
+    st = np.arange(0.0, 20001.0, 37.0)
+    w, v = 2.1 * np.pi / 20000.0, 0.013
+    th = w * st
+    sign = np.where((st // 500) % 2 == 0, 1.0, -1.0)[:, None]
+    ax = sign * np.c_[np.sin(th), np.cos(th)]
+    ends = V.tumbling_periods(st, ax, v * st)
+    assert len(ends) == 3
+    for k, (s, z) in enumerate(ends[1:], 1):
+        assert abs(s - k * np.pi / w) < 1e-6 * s
+        assert abs(z - v * k * np.pi / w) < 1e-6 * z
