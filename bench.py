@@ -46,19 +46,19 @@ BYTES_PER_LUP = {"f32": 19 * 4 * 2 + 1, "f16": 19 * 2 * 2 + 1, "bf16": 19 * 2 * 
                  "f64": 19 * 8 * 2 + 1}
 
 
-def build_context(sc, storage, stream):
+def build_context(sc, storage, stream, stabilize=False):
     from paper_1503_06869_amd import lbm
     g = lbm.Context(sc.nx, sc.ny, sc.nz, tau=sc.tau, magic=sc.magic, wall_u=sc.wall_u,
-                    init_couette=True, storage=storage, stream=stream)
+                    init_couette=True, storage=storage, stream=stream, stabilize=stabilize)
     for f in sc.fibers:
         g.add_fiber(f.X, f.q, f.length, f.radius, f.density_ratio, f.V, f.W)
     return g
 
 
-def time_form(sc, storage, steps, warmup, torch):
+def time_form(sc, storage, steps, warmup, torch, stabilize=False):
     """Whole-step throughput and the bulk sweep's live event timing."""
     stream = torch.cuda.Stream()          # default priority; the context runs on it
-    g = build_context(sc, storage, stream.cuda_stream)
+    g = build_context(sc, storage, stream.cuda_stream, stabilize)
     g.step(warmup)
     g.sync()
     t0 = torch.cuda.Event(enable_timing=True)
@@ -204,7 +204,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--forms", default="f16,bf16", help="extra storage forms to time")
+    ap.add_argument("--forms", default="f16,bf16,stab",
+                    help="extra forms to time: storage types, and stab (FP32 with momentum stabilization)")
     ap.add_argument("--batched-steps", type=int, default=200,
                     help="steps of the batched form's timed launch (0: skip it)")
     ap.add_argument("--learned-steps", type=int, default=500,
@@ -245,6 +246,13 @@ def main():
     forms = {"f32": {"mlups": round(main_form["mlups"], 1),
                      "sweep_hbm_frac": round(main_form["sweep_gbs"] / HBM_PEAK_GBS, 4)}}
     for st in [s for s in a.forms.split(",") if s]:
+        if st == "stab":
+            # the same step with the momentum stabilization's bookkeeping
+            r = time_form(sc, "f32", max(100, a.steps // 2), a.warmup, torch, stabilize=True)
+            forms["f32_stabilized"] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                                       "sweep_ms": round(r["sweep_ms"], 4),
+                                       "step_time_vs_f32": round(r["ms_per_step"] / main_form["ms_per_step"], 4)}
+            continue
         r = time_form(sc, st, max(100, a.steps // 2), a.warmup, torch)
         forms[st] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
                      "sweep_gbs": round(r["sweep_gbs"], 1),
