@@ -767,6 +767,12 @@ static void one_step(or_sim *s)
                         *slot(s->fb, s, qb, c) = ft - 6.0 * w * rho0 * (CV[q][0] * uw);
                         continue;
                     }
+                    if ((p->x_walls && (x + CV[q][0] < 0 || x + CV[q][0] >= nx)) ||
+                        (p->y_walls && (y + CV[q][1] < 0 || y + CV[q][1] >= ny))) {
+                        /* resting no-slip wall in x or y, half-way (Eq. BBBC) */
+                        *slot(s->fb, s, qb, c) = ft;
+                        continue;
+                    }
                     yz = wrapi(yz, nz);
                     int64_t cy = cidx(s, yx, yy, yz);
                     if (s->flag[cy]) {
@@ -798,6 +804,9 @@ static void one_step(or_sim *s)
                 for (int q = 1; q < Q; ++q) {
                     int yz = z + CV[q][2];
                     if (!p->z_periodic && (yz < 0 || yz >= nz)) continue;
+                    if ((p->x_walls && (x + CV[q][0] < 0 || x + CV[q][0] >= nx)) ||
+                        (p->y_walls && (y + CV[q][1] < 0 || y + CV[q][1] >= ny)))
+                        continue;
                     int yx = wrapi(x + CV[q][0], nx), yy = wrapi(y + CV[q][1], ny);
                     yz = wrapi(yz, nz);
                     int64_t cy = cidx(s, yx, yy, yz);

@@ -25,7 +25,8 @@ class Params(C.Structure):
                 ("tau", C.c_double), ("magic", C.c_double), ("rho0", C.c_double),
                 ("wall_u", C.c_double), ("g", C.c_double * 3), ("init_couette", C.c_int),
                 ("coupling", C.c_int), ("stabilize", C.c_int),
-                ("contact_k", C.c_double), ("contact_range", C.c_double)]
+                ("contact_k", C.c_double), ("contact_range", C.c_double),
+                ("x_walls", C.c_int), ("y_walls", C.c_int)]
 
 
 def lib():
@@ -206,10 +207,11 @@ class Sim:
 
     def __init__(self, nx, ny, nz, tau=0.8, magic=3.0 / 16.0, wall_u=0.0, rho0=1.0,
                  z_periodic=False, srt=False, g=(0.0, 0.0, 0.0), init_couette=False,
-                 coupling="implicit", stabilize=False, contact_k=0.0, contact_range=1.0):
+                 coupling="implicit", stabilize=False, contact_k=0.0, contact_range=1.0,
+                 x_walls=False, y_walls=False):
         p = Params(nx, ny, nz, int(z_periodic), int(srt), tau, magic, rho0, wall_u,
                    (C.c_double * 3)(*g), int(init_couette), COUPLING[coupling], int(stabilize),
-                   float(contact_k), float(contact_range))
+                   float(contact_k), float(contact_range), int(x_walls), int(y_walls))
         self.shape = (nx, ny, nz)
         self.ncell = nx * ny * nz
         self._h = lib().or_create(C.byref(p))

@@ -195,6 +195,44 @@ def test_poiseuille_closed_form_trt_magic():
     assert np.abs(u[0, :, 0, 0] - exact).max() / exact.max() < 1e-10
 
 
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_poiseuille_between_x_or_y_walls(axis):
+    """Resting no-slip walls half-way outside the x (or y) faces: a body
+    force along z (x) in a box periodic elsewhere drives the same exact
+    parabola u = g (s + 1/2)(n - s - 1/2) / (2 nu) across the walled
+    direction s (TRT magic value, Eq. BBBC)."""
+    n, g, tau = 24, 1e-6, 0.8
+    nu = (tau - 0.5) / 3
+    if axis == "x":
+        sim = O.Sim(n, 4, 4, tau=tau, z_periodic=True, x_walls=True, g=(0, 0, g))
+    else:
+        sim = O.Sim(4, n, 4, tau=tau, z_periodic=True, y_walls=True, g=(g, 0, 0))
+    sim.step(20000)
+    _, u, _, _ = sim.fields()
+    prof = u[2, 0, 0, :] if axis == "x" else u[0, 0, :, 0]
+    s_ = np.arange(n)
+    exact = g * (s_ + 0.5) * (n - s_ - 0.5) / (2 * nu)
+    assert np.abs(prof - exact).max() / exact.max() < 1e-9
+    other = u[[0, 1]] if axis == "x" else u[[1, 2]]
+    assert np.abs(other).max() < 1e-13
+
+
+def test_closed_box_conserves_mass_and_stops():
+    """Walls on all six faces (resting): from a random state the total mass
+    is conserved to rounding and the momentum decays to zero."""
+    n = 10
+    sim = O.Sim(n, n, n, tau=0.8, x_walls=True, y_walls=True)
+    c, w, _ = O.lattice()
+    rng = np.random.default_rng(4)
+    f = w[:, None, None, None] * (1.0 + 0.05 * rng.standard_normal((19, n, n, n)))
+    sim.set_populations(f)
+    m0 = f.sum()
+    sim.step(3000)
+    f1 = sim.populations()
+    assert abs(f1.sum() - m0) < 1e-11 * m0
+    assert np.abs(np.einsum("qa,qzyx->a", c.astype(np.float64), f1)).max() < 1e-9
+
+
 def test_poiseuille_srt_wall_error_is_second_order():
     """With SRT the wall location depends on tau (Sec. 4.1), so the parabola
     carries an error that falls like nz^-2."""
