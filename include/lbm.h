@@ -109,6 +109,14 @@ typedef struct {
      * units).  With contacts at most 248 fibers per context. */
     double contact_stiffness;
     double contact_range;
+    /* 1: resting no-slip walls half-way outside the x faces (below x = 0 and
+     * above x = nx - 1; bounce-back of Eq. BBBC) instead of periodicity in
+     * x; likewise y.  With z walls (z_periodic = 0, wall_u = 0) this closes
+     * the box on all six faces.  Fibers must stay more than one cell from
+     * these walls (LBM_E_GEOM at lbm_add_fiber; LBM_E_STATE at the next sync
+     * if one reaches a wall during the run). */
+    int32_t x_walls;
+    int32_t y_walls;
 } lbm_params;
 
 /* Fiber shapes: a circular cylinder of length L, or a spherocylinder (a

@@ -337,6 +337,7 @@ static lbm_status check_device_errors(lbm_ctx *c)
     HIPCHK(c, hipMemcpyAsync(&h, c->ctr, sizeof h, hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
     if (h.err_unstable) return fail(c, LBM_E_UNSTABLE, "non-finite force or torque on the device");
+    if (h.err_wall) return fail(c, LBM_E_STATE, "a fiber came within one cell of an x or y wall");
     if (h.err_capacity)
         return fail(c, LBM_E_STATE,
                     std::string("internal capacity exceeded (") +
@@ -504,6 +505,7 @@ lbm_status lbm_create(const lbm_params *p, lbm_ctx **out)
     if (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 20) return LBM_E_ARG;
     if (p->coupling < LBM_COUPLING_IMPLICIT || p->coupling > LBM_COUPLING_IMPLICIT_PLAIN) return LBM_E_ARG;
     if (p->stabilize != 0 && p->stabilize != 1) return LBM_E_ARG;
+    if ((p->x_walls != 0 && p->x_walls != 1) || (p->y_walls != 0 && p->y_walls != 1)) return LBM_E_ARG;
     if (!(p->contact_stiffness >= 0.0) || !std::isfinite(p->contact_stiffness)) return LBM_E_ARG;
     if (p->contact_stiffness > 0.0 && !(p->contact_range > 0.0 && std::isfinite(p->contact_range))) return LBM_E_ARG;
     // changed-cell entries keep a flag in bit 31
@@ -552,6 +554,8 @@ lbm_status lbm_create(const lbm_params *p, lbm_ctx **out)
     g.dnx = make_fastdiv(g.nx);
     g.dnxy = make_fastdiv(g.nxy);
     g.zper = p->z_periodic ? 1 : 0;
+    g.xw = p->x_walls ? 1 : 0;
+    g.yw = p->y_walls ? 1 : 0;
     Phys<double> &ph = c->ph;
     ph.rho0 = p->rho0;
     ph.omega_e = 1.0 / p->tau;
@@ -642,7 +646,7 @@ lbm_status lbm_add_fiber(lbm_ctx *c, const lbm_fiber *f, int32_t *id)
                                ? (0.5 * f->length - f->radius) * std::fabs(t[k]) + f->radius
                                : 0.5 * f->length * std::fabs(t[k]) +
                                      f->radius * std::sqrt(std::fmax(0.0, 1.0 - t[k] * t[k]));
-        const bool per = k < 2 || c->p.z_periodic;
+        const bool per = (k == 0 && !c->p.x_walls) || (k == 1 && !c->p.y_walls) || (k == 2 && c->p.z_periodic);
         if (per && !(f->length * 0.5 + f->radius < 0.5 * n[k] - 1.0))
             return fail(c, LBM_E_GEOM, "fiber longer than half the periodic domain");
         if (!per && (f->center[k] - ext < 1.0 || f->center[k] + ext > n[k] - 2.0))
@@ -997,6 +1001,7 @@ lbm_status lbm_set_closure(lbm_ctx *c, lbm_mlp *m)
         c->closure = nullptr;
         return LBM_OK;
     }
+    if (c->g.xw || c->g.yw) return fail(c, LBM_E_STATE, "the closure's features assume periodic x and y");
     if (c->p.z_periodic || c->p.wall_u == 0.0)
         return fail(c, LBM_E_ARG, "the closure needs a shear cell (moving walls, U != 0)");
     if (c->np == 0) return fail(c, LBM_E_STATE, "add the fibers before attaching the closure");

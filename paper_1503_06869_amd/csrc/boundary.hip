@@ -15,7 +15,7 @@
 
 namespace lbm {
 
-template <typename S, bool ODD, bool STAB>
+template <typename S, bool ODD, bool STAB, bool XYW>
 __device__ __forceinline__ void bnd_block(S *__restrict__ f, const Geo &g, const Phys<typename St<S>::R> &ph,
                                           const BndData &b, int blk, const double *stab, double *part)
 {
@@ -28,7 +28,7 @@ __device__ __forceinline__ void bnd_block(S *__restrict__ f, const Geo &g, const
     if constexpr (STAB) stab_begin(sa, stab);
     for (uint32_t r = j * 256u + threadIdx.x; r < n; r += b.bpf * 256u) {
         const uint32_t e = off + r;
-        update_cell<S, ODD, true, 6, STAB>(f, g, ph, b.cell[e], b.mask[e], p, acc, b, &sa);
+        update_cell<S, ODD, true, 6, STAB, XYW>(f, g, ph, b.cell[e], b.mask[e], p, acc, b, &sa);
     }
     if constexpr (STAB) stab_flush(sa, part + 4 * size_t(blk));
     // integer sums: exact, so the reduction order does not matter
@@ -148,13 +148,14 @@ __device__ __forceinline__ void abc_block(const BndData &b, const Geo &g, double
 // up to 2 waves per SIMD, so it must stay within 176 VGPRs (171 for FP32),
 // or bulk workgroups launched after it start late and the sweep stretches.
 // STAB: momentum stabilization (mean velocity stab[0..2]; the boundary-cell
-// workgroup blk writes its sums to part[4 blk .. 4 blk + 3]).
-template <typename S, bool ODD, bool STAB>
+// workgroup blk writes its sums to part[4 blk .. 4 blk + 3]).  XYW: walls on
+// the x and/or y faces.
+template <typename S, bool ODD, bool STAB, bool XYW>
 __global__ __launch_bounds__(256) void k_boundary(S *__restrict__ f, Geo g, Phys<typename St<S>::R> ph,
                                                   BndData b, double r0, const double *stab, double *part)
 {
     const int nb = b.np * b.bpf;   // block-uniform split
-    if (int(blockIdx.x) < nb) bnd_block<S, ODD, STAB>(f, g, ph, b, int(blockIdx.x), stab, part);
+    if (int(blockIdx.x) < nb) bnd_block<S, ODD, STAB, XYW>(f, g, ph, b, int(blockIdx.x), stab, part);
     else abc_block(b, g, r0, int(blockIdx.x) - nb);
 }
 
@@ -165,12 +166,16 @@ static hipError_t boundary_t(bool odd, void *f, const Geo &g, const Phys<double>
     using R = typename St<S>::R;
     const Phys<R> p = cast_phys<R>(ph);
     const dim3 grid(uint32_t(2 * b.np * b.bpf)), bl(256);
-    if (stab) {
-        if (odd) hipLaunchKernelGGL((k_boundary<S, true, true>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part);
-        else hipLaunchKernelGGL((k_boundary<S, false, true>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part);
-    } else {
-        if (odd) hipLaunchKernelGGL((k_boundary<S, true, false>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part);
-        else hipLaunchKernelGGL((k_boundary<S, false, false>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part);
+    const int mode = (odd ? 1 : 0) | (stab ? 2 : 0) | ((g.xw || g.yw) ? 4 : 0);
+    switch (mode) {
+    case 0: hipLaunchKernelGGL((k_boundary<S, false, false, false>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part); break;
+    case 1: hipLaunchKernelGGL((k_boundary<S, true, false, false>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part); break;
+    case 2: hipLaunchKernelGGL((k_boundary<S, false, true, false>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part); break;
+    case 3: hipLaunchKernelGGL((k_boundary<S, true, true, false>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part); break;
+    case 4: hipLaunchKernelGGL((k_boundary<S, false, false, true>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part); break;
+    case 5: hipLaunchKernelGGL((k_boundary<S, true, false, true>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part); break;
+    case 6: hipLaunchKernelGGL((k_boundary<S, false, true, true>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part); break;
+    default: hipLaunchKernelGGL((k_boundary<S, true, true, true>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part); break;
     }
     return hipGetLastError();
 }

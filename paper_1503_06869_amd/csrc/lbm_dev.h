@@ -126,7 +126,7 @@ struct DevCounters {
     uint32_t err_unstable;     // non-finite F/M seen
     uint32_t err_capacity;     // list or neighbour capacity exceeded
     unsigned long long overlaps;
-    uint32_t pad0;
+    uint32_t err_wall;         // a fiber came within one cell of an x or y wall
     uint32_t pad;
     unsigned long long step;   // steps completed by the particle kernel (history index)
 };
@@ -140,6 +140,7 @@ struct Geo {
     uint64_t qstride;          // elements per direction array: (nz+2) * nxy
     FastDiv dnx, dnxy;
     int32_t zper;
+    int32_t xw, yw;            // 1: resting no-slip walls half-way outside the x (y) faces
 };
 
 template <typename R>

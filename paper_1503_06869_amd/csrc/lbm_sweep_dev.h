@@ -84,6 +84,17 @@ inline Phys<R> cast_phys(const Phys<double> &p)
     return o;
 }
 
+// Population q of cell (x, y, z) arrives through a wall on an x or y face
+// (and not through a z wall): in the odd (swapped) layout it sits in the
+// cell's own slot q instead of slot opp(q) of x - c_q.
+__device__ __forceinline__ bool side_in(const Geo &g, uint32_t x, uint32_t y, uint32_t z, int q)
+{
+    const bool sx = g.xw && ((CX[q] > 0 && x == 0) || (CX[q] < 0 && x + 1 == g.nx));
+    const bool sy = g.yw && ((CY[q] > 0 && y == 0) || (CY[q] < 0 && y + 1 == g.ny));
+    const bool sz = !g.zper && ((CZ[q] > 0 && z == 0) || (CZ[q] < 0 && z + 1 == g.nz));
+    return (sx || sy) && !sz;
+}
+
 // ------------------------------------------------------------------ stabilization
 // Momentum stabilization (Sec. 4.1): the collisions of a step take their
 // equilibrium at u - ub, ub the mean fluid velocity of the state they read.
@@ -257,7 +268,13 @@ __device__ __forceinline__ void link_terms(long long *acc, double ft, double rx,
 // NK: momentum-exchange terms accumulated per link (NACC, or 6 for F0 and
 // M0 only when the population-free terms are summed elsewhere).
 // STAB: momentum stabilization with the accumulator sa (see StabAcc).
-template <typename S, bool ODD, bool BND, int NK = NACC, bool STAB = false>
+// XYW: resting no-slip walls on the x and/or y faces (g.xw, g.yw): a link
+// leaving the lattice there bounces back (Eq. BBBC) into the cell's own slot
+// opp(q) in both sweeps (the image cell across the periodic seam is live,
+// so its slots cannot serve as a mailbox), and the odd sweep reads a
+// population that arrives through such a wall from the cell's own slot; a
+// link crossing a z wall as well keeps the z wall's ghost-plane mailbox.
+template <typename S, bool ODD, bool BND, int NK = NACC, bool STAB = false, bool XYW = false>
 __device__ __forceinline__ void update_cell(S *__restrict__ f, const Geo &g,
                                             const Phys<typename St<S>::R> &ph, uint32_t cell,
                                             uint32_t mask, int home, long long *acc, const BndData &b,
@@ -283,21 +300,36 @@ __device__ __forceinline__ void update_cell(S *__restrict__ f, const Geo &g,
     }
     const uint64_t qs = g.qstride;
     const R inv = ph.inv_scale, sc = ph.scale;
+    const bool wall_lo = !g.zper && z == 0;
+    const bool wall_hi = !g.zper && z + 1 == g.nz;
+    bool wx0 = false, wx1 = false, wy0 = false, wy1 = false;
+    if constexpr (XYW) {
+        wx0 = g.xw && x == 0;
+        wx1 = g.xw && x + 1 == g.nx;
+        wy0 = g.yw && y == 0;
+        wy1 = g.yw && y + 1 == g.ny;
+    }
+    const uint32_t own = zo[1] + yo[1] + xo[1];
     R fv[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         if (!ODD) {
-            fv[q] = St<S>::ld(f, uint64_t(q) * qs + zo[1] + yo[1] + xo[1], inv);
+            fv[q] = St<S>::ld(f, uint64_t(q) * qs + own, inv);
         } else {
-            const uint32_t src = zo[1 - CZ[q]] + yo[1 - CY[q]] + xo[1 - CX[q]];
-            fv[q] = St<S>::ld(f, uint64_t(opp(q)) * qs + src, inv);
+            bool side_in = false;   // arrives through a side wall (and not a z wall)
+            if constexpr (XYW)
+                side_in = ((CX[q] > 0 && wx0) || (CX[q] < 0 && wx1) || (CY[q] > 0 && wy0) || (CY[q] < 0 && wy1)) &&
+                          !((CZ[q] > 0 && wall_lo) || (CZ[q] < 0 && wall_hi));
+            if (side_in) {
+                fv[q] = St<S>::ld(f, uint64_t(q) * qs + own, inv);
+            } else {
+                const uint32_t src = zo[1 - CZ[q]] + yo[1 - CY[q]] + xo[1 - CX[q]];
+                fv[q] = St<S>::ld(f, uint64_t(opp(q)) * qs + src, inv);
+            }
         }
     }
     collide<R, STAB>(fv, ph, R(1) / ph.rho0, sa);
 
-    const bool wall_lo = !g.zper && z == 0;
-    const bool wall_hi = !g.zper && z + 1 == g.nz;
-    const uint32_t own = zo[1] + yo[1] + xo[1];
     const R six_r0 = R(6) * ph.rho0;
     const PState *ps = nullptr;
     if (BND) ps = b.ps;
@@ -305,6 +337,10 @@ __device__ __forceinline__ void update_cell(S *__restrict__ f, const Geo &g,
         constexpr int q = decltype(qc)::value;
         const uint32_t nb = zo[1 + CZ[q]] + yo[1 + CY[q]] + xo[1 + CX[q]];
         const bool to_wall = (CZ[q] < 0 && wall_lo) || (CZ[q] > 0 && wall_hi);
+        bool to_side = false;
+        if constexpr (XYW)
+            to_side = ((CX[q] < 0 && wx0) || (CX[q] > 0 && wx1) || (CY[q] < 0 && wy0) || (CY[q] > 0 && wy1)) &&
+                      !to_wall;
         bool to_part = false;
         if (BND) to_part = (mask >> q) & 1u;
         R out = fv[q];
@@ -312,7 +348,7 @@ __device__ __forceinline__ void update_cell(S *__restrict__ f, const Geo &g,
             const R uw = CZ[q] < 0 ? -ph.wall_u : ph.wall_u;
             out -= six_r0 * R(wq(q)) * R(CX[q]) * uw;
         }
-        if (BND && to_part) {
+        if (BND && to_part && !to_side) {
             // moving-obstacle bounce-back (Eq. LBMMovWall) and the link's
             // momentum exchange, from the post-collision value in registers
             const int32_t p = b.pid[nb - g.nxy];
@@ -343,7 +379,7 @@ __device__ __forceinline__ void update_cell(S *__restrict__ f, const Geo &g,
                               (unsigned long long)tmp[k]);
             }
         }
-        const bool bounce = to_wall || to_part;
+        const bool bounce = to_wall || to_side || to_part;
         if constexpr (STAB) {
             // a bounced link returns out in direction -c_q instead of
             // streaming fv[q] along c_q
@@ -355,7 +391,8 @@ __device__ __forceinline__ void update_cell(S *__restrict__ f, const Geo &g,
             }
         }
         if (!ODD) {
-            if (bounce) St<S>::st(f, uint64_t(q) * qs + nb, out, sc);
+            // mailbox for z walls and fibers; normal streaming and side walls: own slot
+            if (to_wall || (to_part && !to_side)) St<S>::st(f, uint64_t(q) * qs + nb, out, sc);
             else St<S>::st(f, uint64_t(opp(q)) * qs + own, out, sc);
         } else {
             if (bounce) St<S>::st(f, uint64_t(opp(q)) * qs + own, out, sc);

@@ -27,7 +27,8 @@ namespace lbm {
 // streams (19 directions read, 19 written) within a few DRAM pages.
 // STAB: momentum stabilization; stab[0..2] is the mean velocity the
 // collisions subtract, and workgroup b writes its sums to part[4 b .. 4 b + 3].
-template <typename S, bool ODD, bool STAB>
+// XYW: walls on the x and/or y faces.
+template <typename S, bool ODD, bool STAB, bool XYW>
 __global__ __launch_bounds__(256) void k_sweep_bulk(S *__restrict__ f, const uint8_t *__restrict__ flags,
                                                     Geo g, Phys<typename St<S>::R> ph, const double *stab,
                                                     double *part)
@@ -39,7 +40,7 @@ __global__ __launch_bounds__(256) void k_sweep_bulk(S *__restrict__ f, const uin
     for (uint32_t ch = xcd_block(blockIdx.x, gridDim.x); ch < nchunk; ch += gridDim.x) {
         const uint32_t cell = (ch << 8) + threadIdx.x;
         if (cell < g.ncell && !flags[cell])   // fiber cells idle; boundary cells: k_boundary
-            update_cell<S, ODD, false, NACC, STAB>(f, g, ph, cell, 0u, -1, nullptr, BndData{}, &sa);
+            update_cell<S, ODD, false, NACC, STAB, XYW>(f, g, ph, cell, 0u, -1, nullptr, BndData{}, &sa);
     }
     if constexpr (STAB) stab_flush(sa, part + 4 * size_t(blockIdx.x));
 }
@@ -81,7 +82,7 @@ __global__ void k_decode(const S *__restrict__ f, const uint8_t *__restrict__ fl
         for (int q = 0; q < Q; ++q) {
             uint32_t src = (z + 1) * g.nxy + y * g.nx + x;
             int qq = q;
-            if (swapped) {
+            if (swapped && !side_in(g, x, y, z, q)) {
                 const uint32_t sx = (x + g.nx - CX[q]) % g.nx, sy = (y + g.ny - CY[q]) % g.ny;
                 const int32_t szi = int32_t(z) - CZ[q];
                 const uint32_t szs = g.zper ? uint32_t((szi + int32_t(g.nz)) % int32_t(g.nz)) + 1
@@ -124,7 +125,7 @@ __global__ void k_encode(S *__restrict__ f, Geo g, double rho0, double scale, in
         for (int q = 0; q < Q; ++q) {
             uint32_t dst = (z + 1) * g.nxy + y * g.nx + x;
             int qq = q;
-            if (swapped) {
+            if (swapped && !side_in(g, x, y, z, q)) {
                 const uint32_t sx = (x + g.nx - CX[q]) % g.nx, sy = (y + g.ny - CY[q]) % g.ny;
                 const int32_t szi = int32_t(z) - CZ[q];
                 const uint32_t szs = g.zper ? uint32_t((szi + int32_t(g.nz)) % int32_t(g.nz)) + 1
@@ -159,12 +160,16 @@ static hipError_t sweep_t(bool odd, void *f, const uint8_t *flags, const Geo &g,
     if (!sweep_grid) return hipSuccess;
     if (ev0) hipEventRecord(ev0, st);
     const dim3 gr(sweep_grid), bl(256);
-    if (stab) {
-        if (odd) hipLaunchKernelGGL((k_sweep_bulk<S, true, true>), gr, bl, 0, st, (S *)f, flags, g, p, stab, part);
-        else hipLaunchKernelGGL((k_sweep_bulk<S, false, true>), gr, bl, 0, st, (S *)f, flags, g, p, stab, part);
-    } else {
-        if (odd) hipLaunchKernelGGL((k_sweep_bulk<S, true, false>), gr, bl, 0, st, (S *)f, flags, g, p, stab, part);
-        else hipLaunchKernelGGL((k_sweep_bulk<S, false, false>), gr, bl, 0, st, (S *)f, flags, g, p, stab, part);
+    const int mode = (odd ? 1 : 0) | (stab ? 2 : 0) | ((g.xw || g.yw) ? 4 : 0);
+    switch (mode) {
+    case 0: hipLaunchKernelGGL((k_sweep_bulk<S, false, false, false>), gr, bl, 0, st, (S *)f, flags, g, p, stab, part); break;
+    case 1: hipLaunchKernelGGL((k_sweep_bulk<S, true, false, false>), gr, bl, 0, st, (S *)f, flags, g, p, stab, part); break;
+    case 2: hipLaunchKernelGGL((k_sweep_bulk<S, false, true, false>), gr, bl, 0, st, (S *)f, flags, g, p, stab, part); break;
+    case 3: hipLaunchKernelGGL((k_sweep_bulk<S, true, true, false>), gr, bl, 0, st, (S *)f, flags, g, p, stab, part); break;
+    case 4: hipLaunchKernelGGL((k_sweep_bulk<S, false, false, true>), gr, bl, 0, st, (S *)f, flags, g, p, stab, part); break;
+    case 5: hipLaunchKernelGGL((k_sweep_bulk<S, true, false, true>), gr, bl, 0, st, (S *)f, flags, g, p, stab, part); break;
+    case 6: hipLaunchKernelGGL((k_sweep_bulk<S, false, true, true>), gr, bl, 0, st, (S *)f, flags, g, p, stab, part); break;
+    default: hipLaunchKernelGGL((k_sweep_bulk<S, true, true, true>), gr, bl, 0, st, (S *)f, flags, g, p, stab, part); break;
     }
     if (ev1) hipEventRecord(ev1, st);
     return hipGetLastError();

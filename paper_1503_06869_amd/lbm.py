@@ -57,7 +57,8 @@ class lbm_params(C.Structure):
                 ("fp16_scale_log2", C.c_int32), ("history_capacity", C.c_int64),
                 ("stream", C.c_void_p), ("sweep_grid", C.c_int32), ("q_pad", C.c_int32),
                 ("stabilize", C.c_int32), ("reserved", C.c_int32),
-                ("contact_stiffness", C.c_double), ("contact_range", C.c_double)]
+                ("contact_stiffness", C.c_double), ("contact_range", C.c_double),
+                ("x_walls", C.c_int32), ("y_walls", C.c_int32)]
 
 
 class lbm_fiber(C.Structure):
@@ -214,10 +215,11 @@ class Context:
                  z_periodic=False, collision="trt", storage="f32", init_couette=False,
                  coupling="implicit", body_force=(0.0, 0.0, 0.0), fp16_scale_log2=14,
                  history_capacity=4096, stream=None, sweep_grid=0, q_pad=-1, stabilize=False,
-                 contact_k=0.0, contact_range=1.0):
+                 contact_k=0.0, contact_range=1.0, x_walls=False, y_walls=False):
         """stabilize: momentum stabilization (subtract the mean fluid velocity
         in every equilibrium), for fully periodic boxes with forced particles.
-        contact_k, contact_range: short-range repulsion between fibers (off at 0)."""
+        contact_k, contact_range: short-range repulsion between fibers (off at 0).
+        x_walls, y_walls: resting no-slip walls on the x (y) faces instead of periodicity."""
         L = load()
         p = lbm_params()
         L.lbm_params_default(C.byref(p))
@@ -237,6 +239,8 @@ class Context:
         p.stabilize = int(bool(stabilize))
         p.contact_stiffness = float(contact_k)
         p.contact_range = float(contact_range)
+        p.x_walls = int(bool(x_walls))
+        p.y_walls = int(bool(y_walls))
         h = C.c_void_p()
         r = L.lbm_create(C.byref(p), C.byref(h))
         if r != LBM_OK:

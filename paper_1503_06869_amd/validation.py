@@ -13,9 +13,8 @@ terminal angular velocity next to the paper's LBM value omega*_LBM and the
 Tirado value omega_Tir,wC (Eq. CapsTheorRotatMotionTirado for a cylinder of
 the full length, with the end correction of Eq. EndeffCorrRotatMotionTirado).
 
-Difference from the paper's setup: its cube has no-slip walls on all six
-faces; this lattice has stationary no-slip walls at the z ends (walls moving
-with U = 0) and is periodic in x and y.
+With --all-walls the cube has resting no-slip walls on all six faces, as in
+the paper; without, at the z ends only, periodic in x and y.
 """
 import argparse
 import json
@@ -60,11 +59,13 @@ def lattice_torque(torque_si):
     return torque_si / (RHO_F * DX ** 3 * DX ** 2 / dt() ** 2)
 
 
-def run(aspect, n, steps, every, log=print):
+def run(aspect, n, steps, every, log=print, walls=False):
+    """walls: resting no-slip walls on all six faces (the paper's cube);
+    otherwise on the z faces only, periodic in x and y."""
     from . import lbm
     L = aspect * R_CELLS
     m_lat = lattice_torque(TORQUE[aspect] * 1e-15)
-    g = lbm.Context(n, n, n, tau=TAU, wall_u=0.0, init_couette=False)
+    g = lbm.Context(n, n, n, tau=TAU, wall_u=0.0, init_couette=False, x_walls=walls, y_walls=walls)
     c = 0.5 * (n - 1)
     q = (math.cos(math.pi / 4), 0.0, 0.0, math.sin(math.pi / 4))   # axis along y
     g.add_fiber((c, c, c), q, L, R_CELLS, RHO_P / RHO_F, shape="spherocylinder", torque=(m_lat, 0.0, 0.0))
@@ -85,7 +86,8 @@ def run(aspect, n, steps, every, log=print):
     w_lat = float(tail.mean())
     w = w_lat / dt()
     return {
-        "aspect": aspect, "n": n, "steps": steps, "length_cells": L, "radius_cells": R_CELLS,
+        "aspect": aspect, "n": n, "steps": steps, "walls": "all six faces" if walls else "z faces",
+        "length_cells": L, "radius_cells": R_CELLS,
         "tau": TAU, "dt_s": dt(), "torque_lattice": m_lat,
         "omega_lattice": w_lat, "omega_per_s": w,
         "omega_spread_pct": float(100.0 * (tail.max() - tail.min()) / abs(w_lat)) if w_lat else None,
@@ -214,6 +216,7 @@ def main(argv=None):
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--contact-k", type=float, default=0.0)
     ap.add_argument("--contact-range", type=float, default=2.0)
+    ap.add_argument("--all-walls", action="store_true", help="rotation: no-slip walls on all six faces")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     if a.case == "tumbling":
@@ -225,7 +228,8 @@ def main(argv=None):
             with open(a.out, "w") as fh:
                 json.dump(res, fh)
         return 0
-    res = run(a.aspect or 4, a.n or 816, a.steps or 40000, a.every or 1000, log=lambda s: print(s, flush=True))
+    res = run(a.aspect or 4, a.n or 816, a.steps or 40000, a.every or 1000, log=lambda s: print(s, flush=True),
+              walls=a.all_walls)
     line = {k: v for k, v in res.items() if k != "history"}
     print(json.dumps(line), flush=True)
     if a.out:

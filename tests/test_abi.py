@@ -54,8 +54,8 @@ def test_lattice_table_needs_no_gpu():
 
 
 def test_struct_layout_matches_header():
-    # lbm_params: 5 int32 (+4 pad), 4 doubles, 3 doubles, 4 int32, int64, pointer, 4 int32, 2 doubles
-    assert C.sizeof(lbm.lbm_params) == 5 * 4 + 4 + 4 * 8 + 3 * 8 + 4 * 4 + 8 + 8 + 4 * 4 + 2 * 8
+    # lbm_params: 5 int32 (+4 pad), 4 doubles, 3 doubles, 4 int32, int64, pointer, 4 int32, 2 doubles, 2 int32
+    assert C.sizeof(lbm.lbm_params) == 5 * 4 + 4 + 4 * 8 + 3 * 8 + 4 * 4 + 8 + 8 + 4 * 4 + 2 * 8 + 2 * 4
     # centre, quaternion, L, r, density ratio, V, W; shape + reserved; force, torque
     assert C.sizeof(lbm.lbm_fiber) == (3 + 4 + 3 + 3 + 3) * 8 + 2 * 4 + 6 * 8
     assert C.sizeof(lbm.lbm_info) == 8 + 4 + 4 + 8 * 4
@@ -85,6 +85,8 @@ def test_params_default_and_argument_errors(libso):
     bad.stabilize, bad.contact_stiffness, bad.contact_range = 0, 1.0, 0.0
     assert L.lbm_create(C.byref(bad), C.byref(h)) == lbm.LBM_E_ARG
     bad.contact_stiffness = -1.0
+    assert L.lbm_create(C.byref(bad), C.byref(h)) == lbm.LBM_E_ARG
+    bad.contact_stiffness, bad.x_walls = 0.0, 2
     assert L.lbm_create(C.byref(bad), C.byref(h)) == lbm.LBM_E_ARG
     assert L.lbm_step(None, 1) == lbm.LBM_E_ARG
 
