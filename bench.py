@@ -37,9 +37,10 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of the FP32 bulk sweep on this workload, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE passes (profiles/sweep_bulk_256cube_64fibers_traffic.md),
 # scaled by the counters' readings for a plain copy of known size.  Valid only
-# for the sweep source it was measured on (SHA-1 below); otherwise reported null.
-SWEEP_TRAFFIC = {"sweep_sha1": "ba6548a6bfe6baca34ba1430b5beef5a089e22b2",
-                 "bytes_per_launch": 2.5725e9}
+# for the sources it was measured on (SHA-1 of sweep.hip followed by
+# lbm_sweep_dev.h, below); otherwise reported null.
+SWEEP_TRAFFIC = {"sweep_sha1": "0fec919608e506aec09f60faf9299d3b7463f3eb",
+                 "bytes_per_launch": 2.5724e+09}
 # algorithmic bytes per lattice update of the bulk sweep: 19 loads + 19
 # stores of the population type + the 1-byte cell flag
 BYTES_PER_LUP = {"f32": 19 * 4 * 2 + 1, "f16": 19 * 2 * 2 + 1, "bf16": 19 * 2 * 2 + 1,
@@ -174,11 +175,16 @@ def time_learned(steps, warmup, torch):
     return out
 
 
-def sweep_traffic():
+def sweep_sources_sha1():
     import hashlib
-    src = os.path.join(ROOT, "paper_1503_06869_amd", "csrc", "sweep.hip")
-    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
-    return SWEEP_TRAFFIC["bytes_per_launch"] if sha == SWEEP_TRAFFIC["sweep_sha1"] else None
+    h = hashlib.sha1()
+    for name in ("sweep.hip", "lbm_sweep_dev.h"):
+        h.update(open(os.path.join(ROOT, "paper_1503_06869_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
+def sweep_traffic():
+    return SWEEP_TRAFFIC["bytes_per_launch"] if sweep_sources_sha1() == SWEEP_TRAFFIC["sweep_sha1"] else None
 
 
 def cpu_baseline(sc, nsteps=2):
