@@ -95,3 +95,31 @@ def test_fiber_next_to_a_side_wall_is_rejected():
         g.add_fiber((8.5, 20.0, 20.0), q, 16.0, 2.0, 1.0)    # reaches x = 0.5
     g.add_fiber((12.0, 20.0, 20.0), q, 16.0, 2.0, 1.0)
     g.close()
+
+
+def test_fiber_driven_into_a_side_wall_is_reported():
+    """A fiber pushed towards an x wall by a constant force: the step kernel
+    flags it once it comes within one cell, and the next sync reports
+    LBM_E_STATE (every kernel still completes normally; the error stays
+    set for the context)."""
+    q = scenarios.quat_from_axis(np.array([0.0, 0.0, 1.0]))
+    g = lbm.Context(32, 32, 40, tau=0.8, x_walls=True, y_walls=True)
+    g.add_fiber((8.0, 16.0, 20.0), q, 12.0, 2.0, 1.0, force=(-0.1, 0.0, 0.0))
+    done = 0
+    with pytest.raises(lbm.LBMError) as ei:
+        for _ in range(400):
+            g.step(10)
+            done += 10
+            g.sync()
+    assert ei.value.code == lbm.LBM_E_STATE and "wall" in str(ei.value)
+    print("reported after %d steps" % done, flush=True)
+    assert done >= 300   # it had to travel about 5 cells first (about 0.005 per step)
+    g.close()
+
+
+def test_closure_is_refused_with_side_walls():
+    g = lbm.Context(24, 24, 24, tau=0.8, x_walls=True)
+    m = lbm.Mlp()
+    with pytest.raises(lbm.LBMError):
+        g.set_closure(m)
+    g.close()
