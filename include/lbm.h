@@ -253,6 +253,23 @@ lbm_status lbm_get_mean_velocity(lbm_ctx *ctx, double ubar[3], int64_t *nfluid);
 
 lbm_status lbm_get_info(lbm_ctx *ctx, lbm_info *info);
 
+/* The parameters ctx was created with. */
+lbm_status lbm_get_params(lbm_ctx *ctx, lbm_params *out);
+
+/* Checkpoint and resume (not part of the paper's method).  lbm_save
+ * synchronises the stream and writes, to the file at path, the parameters,
+ * the fibers (with any prescribed trajectories), every device buffer that
+ * carries state between steps (populations in their AA layout, both flag
+ * buffers, owners, boundary list, particle states and boxes, history ring,
+ * stabilization sums, counters) and the step count.  lbm_load creates a
+ * context from such a file on stream (a hipStream_t, or NULL for a private
+ * one); its steps are bit-identical to those the saved context would have
+ * taken.  An attached closure is not saved (attach it again).  Errors:
+ * LBM_E_ARG for an unreadable, foreign or truncated file (lbm_load returns
+ * no context then), LBM_E_NOMEM, LBM_E_HIP. */
+lbm_status lbm_save(lbm_ctx *ctx, const char *path);
+lbm_status lbm_load(const char *path, void *stream, lbm_ctx **out);
+
 /* Device-event timing of the stream-collide sweep: when enabled, every
  * subsequent lbm_step brackets each sweep launch with HIP events on the
  * context's stream.  lbm_get_sweep_time synchronises and returns the total

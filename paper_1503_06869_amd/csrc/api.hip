@@ -1,6 +1,7 @@
 // api.hip -- host side of the library: context, device buffers, the step
 // scheduler (direct launches or a captured two-step HIP graph) and the C ABI
 // declared in include/lbm.h.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -941,6 +942,194 @@ lbm_status lbm_get_mean_velocity(lbm_ctx *c, double ubar[3], int64_t *nfluid)
     for (int k = 0; k < 3; ++k) ubar[k] = h[k];
     if (nfluid) *nfluid = int64_t(h[3]);
     return check_device_errors(c);
+}
+
+// ---------------------------------------------------------------- checkpoint
+// Every device buffer that carries state between steps, with its size (the
+// same formulas as the allocations in lbm_create, alloc_stab and
+// upload_particles), in a fixed order.
+struct BufRef {
+    void *p;
+    size_t bytes;
+};
+static std::vector<BufRef> state_buffers(lbm_ctx *c)
+{
+    std::vector<BufRef> v;
+    const size_t nc = c->g.ncell;
+    v.push_back({c->f, size_t(Q) * c->g.qstride * c->esz});
+    v.push_back({c->flags[0], nc});
+    v.push_back({c->flags[1], nc});
+    v.push_back({c->pid, nc * sizeof(int32_t)});
+    v.push_back({c->ctr, sizeof(DevCounters)});
+    if (c->p.stabilize) {
+        const uint32_t nslot = std::max(STAB_SCAN_GRID, c->sweep_grid + c->bnd_grid);
+        v.push_back({c->stab, (size_t(STAB_HEAD) + 4 * size_t(nslot)) * sizeof(double)});
+        v.push_back({c->cov, (size_t(c->cov_cap) + 1) * sizeof(uint32_t)});
+    }
+    const size_t np = size_t(c->np);
+    if (np) {
+        size_t ntraj = 13;
+        for (const auto &t : c->traj_h) ntraj += t.size();
+        v.push_back({c->ps[0], np * sizeof(PState)});
+        v.push_back({c->ps[1], np * sizeof(PState)});
+        v.push_back({c->pc, np * sizeof(PConst)});
+        v.push_back({c->ps_prev, np * sizeof(PState)});
+        v.push_back({c->box_cur, np * sizeof(Box)});
+        v.push_back({c->box_prev, np * sizeof(Box)});
+        v.push_back({c->box_remap, np * sizeof(Box)});
+        v.push_back({c->mea, np * NACC * sizeof(long long)});
+        v.push_back({c->seg_off, np * sizeof(uint32_t)});
+        v.push_back({c->seg_cap, np * sizeof(uint32_t)});
+        v.push_back({c->seg_cnt, np * sizeof(uint32_t)});
+        v.push_back({c->traj, ntraj * sizeof(double)});
+        v.push_back({c->traj_pos, np * sizeof(int64_t)});
+        v.push_back({c->ft, np * 6 * sizeof(double)});
+        v.push_back({c->hist, size_t(c->p.history_capacity) * np * 19 * sizeof(double)});
+        v.push_back({c->list_cell, size_t(c->list_cap) * sizeof(uint32_t)});
+        v.push_back({c->list_mask, size_t(c->list_cap) * sizeof(uint32_t)});
+    }
+    return v;
+}
+
+static const char CKPT_MAGIC[8] = {'L', 'B', 'M', 'C', 'K', 'P', 'T', '1'};
+static constexpr size_t CKPT_CHUNK = size_t(64) << 20;
+
+lbm_status lbm_save(lbm_ctx *c, const char *path)
+{
+    if (!c || !path) return fail(c, LBM_E_ARG, "null argument");
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    FILE *fp = std::fopen(path, "wb");
+    if (!fp) return fail(c, LBM_E_ARG, std::string("cannot write ") + path);
+    bool ok = true;
+    auto put = [&](const void *d, size_t n) { ok = ok && std::fwrite(d, 1, n, fp) == n; };
+    lbm_params p = c->p;
+    p.stream = nullptr;
+    const uint64_t psz = sizeof p;
+    const int64_t steps = c->steps;
+    const int32_t np = c->np, stale = c->stab_stale ? 1 : 0;
+    put(CKPT_MAGIC, 8);
+    put(&psz, 8);
+    put(&p, sizeof p);
+    put(&steps, 8);
+    put(&np, 4);
+    put(&stale, 4);
+    if (np) {
+        put(c->fib.data(), size_t(np) * sizeof(lbm_fiber));
+        put(c->pch.data(), size_t(np) * sizeof(PConst));
+        for (const auto &t : c->traj_h) {
+            const uint64_t n = t.size();
+            put(&n, 8);
+            if (n) put(t.data(), n * sizeof(double));
+        }
+    }
+    const std::vector<BufRef> bufs = state_buffers(c);
+    const uint64_t nb = bufs.size();
+    put(&nb, 8);
+    std::vector<char> h(CKPT_CHUNK);
+    for (const BufRef &b : bufs) {
+        const uint64_t n = b.bytes;
+        put(&n, 8);
+        for (size_t o = 0; ok && o < b.bytes; o += CKPT_CHUNK) {
+            const size_t k = std::min(CKPT_CHUNK, b.bytes - o);
+            if (hipMemcpy(h.data(), static_cast<char *>(b.p) + o, k, hipMemcpyDeviceToHost) != hipSuccess) {
+                std::fclose(fp);
+                return fail(c, LBM_E_HIP, "device read for the checkpoint");
+            }
+            put(h.data(), k);
+        }
+    }
+    if (std::fclose(fp) != 0) ok = false;
+    if (!ok) return fail(c, LBM_E_ARG, std::string("short write to ") + path);
+    return LBM_OK;
+}
+
+lbm_status lbm_load(const char *path, void *stream, lbm_ctx **out)
+{
+    if (!path || !out) return LBM_E_ARG;
+    *out = nullptr;
+    FILE *fp = std::fopen(path, "rb");
+    if (!fp) return LBM_E_ARG;
+    bool ok = true;
+    auto get = [&](void *d, size_t n) { ok = ok && std::fread(d, 1, n, fp) == n; };
+    char magic[8] = {0};
+    uint64_t psz = 0;
+    lbm_params p{};
+    get(magic, 8);
+    get(&psz, 8);
+    if (!ok || std::memcmp(magic, CKPT_MAGIC, 8) != 0 || psz != sizeof p) {
+        std::fclose(fp);
+        return LBM_E_ARG;
+    }
+    int64_t steps = 0;
+    int32_t np = 0, stale = 1;
+    get(&p, sizeof p);
+    get(&steps, 8);
+    get(&np, 4);
+    get(&stale, 4);
+    if (!ok || steps < 0 || np < 0 || np > 302) {
+        std::fclose(fp);
+        return LBM_E_ARG;
+    }
+    p.stream = stream;
+    lbm_ctx *c = nullptr;
+    lbm_status s = lbm_create(&p, &c);
+    if (s != LBM_OK) {
+        std::fclose(fp);
+        return s;
+    }
+    auto bail = [&](lbm_status st) {
+        std::fclose(fp);
+        lbm_destroy(c);
+        return st;
+    };
+    if (np) {
+        c->fib.resize(np);
+        c->pch.resize(np);
+        c->traj_h.assign(np, std::vector<double>());
+        get(c->fib.data(), size_t(np) * sizeof(lbm_fiber));
+        get(c->pch.data(), size_t(np) * sizeof(PConst));
+        for (int i = 0; ok && i < np; ++i) {
+            uint64_t n = 0;
+            get(&n, 8);
+            if (!ok || n % 13 != 0 || n > (uint64_t(1) << 32)) return bail(LBM_E_ARG);
+            c->traj_h[i].resize(n);
+            if (n) get(c->traj_h[i].data(), n * sizeof(double));
+        }
+        if (!ok) return bail(LBM_E_ARG);
+        c->np = np;
+        c->steps = steps;
+        if (upload_particles(c) != LBM_OK) return bail(LBM_E_NOMEM);
+    }
+    if (hipStreamSynchronize(c->st) != hipSuccess) return bail(LBM_E_HIP);
+    const std::vector<BufRef> bufs = state_buffers(c);
+    uint64_t nb = 0;
+    get(&nb, 8);
+    if (!ok || nb != bufs.size()) return bail(LBM_E_ARG);
+    std::vector<char> h(CKPT_CHUNK);
+    for (const BufRef &b : bufs) {
+        uint64_t n = 0;
+        get(&n, 8);
+        if (!ok || n != b.bytes) return bail(LBM_E_ARG);
+        for (size_t o = 0; o < b.bytes; o += CKPT_CHUNK) {
+            const size_t k = std::min(CKPT_CHUNK, b.bytes - o);
+            get(h.data(), k);
+            if (!ok) return bail(LBM_E_ARG);
+            if (hipMemcpy(static_cast<char *>(b.p) + o, h.data(), k, hipMemcpyHostToDevice) != hipSuccess)
+                return bail(LBM_E_HIP);
+        }
+    }
+    std::fclose(fp);
+    c->steps = steps;
+    c->stab_stale = stale != 0;
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_params(lbm_ctx *c, lbm_params *out)
+{
+    if (!c || !out) return LBM_E_ARG;
+    *out = c->p;
+    return LBM_OK;
 }
 
 lbm_status lbm_get_info(lbm_ctx *c, lbm_info *info)

@@ -31,6 +31,7 @@ EXPORTED = [
     "lbm_get_force_torque", "lbm_get_fields", "lbm_get_fiber_state", "lbm_set_fiber_state",
     "lbm_get_history", "lbm_get_populations", "lbm_set_populations", "lbm_get_info",
     "lbm_enable_sweep_timing", "lbm_get_sweep_time", "lbm_copy_bytes", "lbm_get_mean_velocity",
+    "lbm_get_params", "lbm_save", "lbm_load",
 ]
 EXPORTED_BATCH = [
     "lbm_batch_params_default", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_last_error",
@@ -134,6 +135,9 @@ def load():
         "lbm_set_populations": ([vp, _dp], C.c_int),
         "lbm_get_info": ([vp, C.POINTER(lbm_info)], C.c_int),
         "lbm_get_mean_velocity": ([vp, _dp, C.POINTER(C.c_int64)], C.c_int),
+        "lbm_get_params": ([vp, C.POINTER(lbm_params)], C.c_int),
+        "lbm_save": ([vp, C.c_char_p], C.c_int),
+        "lbm_load": ([C.c_char_p, vp, C.POINTER(vp)], C.c_int),
         "lbm_enable_sweep_timing": ([vp, C.c_int32], C.c_int),
         "lbm_get_sweep_time": ([vp, _dp, C.POINTER(C.c_int64)], C.c_int),
         "lbm_copy_bytes": ([vp, vp, C.c_size_t, vp], C.c_int),
@@ -326,6 +330,30 @@ class Context:
 
     def set_populations(self, f):
         self._chk(load().lbm_set_populations(self._h, _d(_f64(f, 19 * self.ncell))))
+
+    def save(self, path):
+        """Write a checkpoint of the whole state to path."""
+        self._chk(load().lbm_save(self._h, str(path).encode()))
+
+    @classmethod
+    def load_checkpoint(cls, path, stream=None):
+        """A context restored from a checkpoint written by save()."""
+        L = load()
+        h = C.c_void_p()
+        r = L.lbm_load(str(path).encode(), stream, C.byref(h))
+        if r != LBM_OK:
+            raise LBMError(r, "lbm_load failed for %s" % path)
+        self = cls.__new__(cls)
+        self._h = h
+        p = lbm_params()
+        self._chk(L.lbm_get_params(h, C.byref(p)))
+        self.shape = (p.nx, p.ny, p.nz)
+        self.ncell = p.nx * p.ny * p.nz
+        self.storage = p.storage
+        i = lbm_info()
+        self._chk(L.lbm_get_info(h, C.byref(i)))
+        self.nfibers = i.nfibers
+        return self
 
     def mean_velocity(self):
         """Mean fluid velocity the next step subtracts, and the fluid cell count

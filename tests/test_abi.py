@@ -114,3 +114,18 @@ def test_batch_argument_errors(libso):
     arr[0].fiber = lbm._fiber_struct((15.5, 15.5, 15.5), (1, 0, 0, 0), 30.0, 2.0)
     assert L.lbm_batch_create(C.byref(p), arr, 1, C.byref(h)) == lbm.LBM_E_GEOM
     assert L.lbm_batch_step(None, 1) == lbm.LBM_E_ARG
+
+
+def test_checkpoint_load_rejects_missing_and_foreign_files(libso, tmp_path):
+    """lbm_load refuses a missing file and a file without the checkpoint
+    header before touching the device, and returns no context."""
+    L = lbm.load()
+    h = C.c_void_p(123)
+    assert L.lbm_load(str(tmp_path / "none.ckpt").encode(), None, C.byref(h)) == lbm.LBM_E_ARG
+    assert not h.value
+    bad = tmp_path / "bad.ckpt"
+    bad.write_bytes(b"not a checkpoint at all" * 4)
+    h = C.c_void_p(123)
+    assert L.lbm_load(str(bad).encode(), None, C.byref(h)) == lbm.LBM_E_ARG
+    assert not h.value
+
