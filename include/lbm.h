@@ -200,7 +200,11 @@ lbm_status lbm_set_fiber_kinematics(lbm_ctx *ctx, int32_t id, const double *traj
  * boundary-cell list.  Returns after enqueueing. */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
 
-/* Wait for all enqueued work; report device-side errors. */
+/* Wait for all enqueued work; report device-side errors: LBM_E_UNSTABLE
+ * for a non-finite force or torque seen by a step, or a non-finite stored
+ * population (one read pass over the population array, on the stream,
+ * before waiting); LBM_E_STATE for exceeded internal capacities or a fiber
+ * that reached an x or y wall. */
 lbm_status lbm_sync(lbm_ctx *ctx);
 
 /* Hydrodynamic force and torque of the last completed step, FP64 host

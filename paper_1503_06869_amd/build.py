@@ -30,6 +30,7 @@ SOURCES = {
     # part and the host code follow a contraction-off pragma in the header
     "batched.hip": [],
     "stab.hip": [],
+    "check.hip": [],
     "features.hip": [],
     "mlp.hip": [],
 }

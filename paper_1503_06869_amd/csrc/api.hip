@@ -337,7 +337,9 @@ static lbm_status check_device_errors(lbm_ctx *c)
     DevCounters h;
     HIPCHK(c, hipMemcpyAsync(&h, c->ctr, sizeof h, hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
-    if (h.err_unstable) return fail(c, LBM_E_UNSTABLE, "non-finite force or torque on the device");
+    if (h.err_unstable)
+        return fail(c, LBM_E_UNSTABLE, (h.err_unstable & 1) ? "non-finite force or torque on the device"
+                                                            : "non-finite population on the device");
     if (h.err_wall) return fail(c, LBM_E_STATE, "a fiber came within one cell of an x or y wall");
     if (h.err_capacity)
         return fail(c, LBM_E_STATE,
@@ -773,6 +775,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t n)
 lbm_status lbm_sync(lbm_ctx *c)
 {
     if (!c) return LBM_E_ARG;
+    HIPCHK(c, launch_check_finite(c->sk, c->f, uint64_t(Q) * c->g.qstride, c->ctr, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
     return check_device_errors(c);
 }

@@ -123,7 +123,7 @@ __host__ __device__ constexpr int fx_shift(int k)
 // device-side counters and error flags
 struct DevCounters {
     uint32_t list_count;       // boundary-cell list length
-    uint32_t err_unstable;     // non-finite F/M seen
+    uint32_t err_unstable;     // bit 0: non-finite F/M seen; bit 1: non-finite population
     uint32_t err_capacity;     // list or neighbour capacity exceeded
     unsigned long long overlaps;
     uint32_t err_wall;         // a fiber came within one cell of an x or y wall
@@ -241,6 +241,9 @@ hipError_t launch_remap(int sk, bool next_odd, void *f, int32_t *pid, const Part
 hipError_t launch_near(uint8_t *flags, const int32_t *pid, uint32_t *list_cell, uint32_t *list_mask,
                        const PartData &pd, const Geo &g, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, size_t nbytes, hipStream_t st);
+// non-finite stored populations (n elements of the population array) set
+// bit 1 of ctr->err_unstable (check.hip)
+hipError_t launch_check_finite(int sk, const void *f, uint64_t n, DevCounters *ctr, hipStream_t st);
 
 // closure network (mlp.hip) and feature sampling (features.hip)
 struct MlpDev {

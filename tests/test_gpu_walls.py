@@ -123,3 +123,21 @@ def test_closure_is_refused_with_side_walls():
     with pytest.raises(lbm.LBMError):
         g.set_closure(m)
     g.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_non_finite_population_is_reported_at_sync(storage):
+    """A NaN written into one cell's populations spreads through the
+    collisions; the next sync reports LBM_E_UNSTABLE (no fibers: the
+    force/torque check cannot see it)."""
+    g = lbm.Context(20, 18, 16, tau=0.8, storage=storage)
+    g.step(2)
+    g.sync()
+    f = g.populations()
+    f[3, 8, 9, 10] = np.nan
+    g.set_populations(f)
+    g.step(3)
+    with pytest.raises(lbm.LBMError) as ei:
+        g.sync()
+    assert ei.value.code == lbm.LBM_E_UNSTABLE and "population" in str(ei.value)
+    g.close()
