@@ -220,7 +220,7 @@ def main():
                     help="only run the plain copy kernel (traffic-counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(the slab decomposition over xGMI is a design, not code)", file=sys.stderr)
         sys.exit(2)
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:
