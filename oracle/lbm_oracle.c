@@ -223,6 +223,11 @@ void or_map_shapes(int nx, int ny, int nz, int zper, int np, const double *X, co
 /*   W' = I(q)^-1 Lang'  with I(q)^-1 = 1/I_perp + (1/I_par - 1/I_perp) t t^T */
 /*   q' = normalize(exp(W'/2) (x) q).                                       */
 /* ------------------------------------------------------------------------ */
+/* Planted mistakes for the tests that show each pin can fail (0: none).     */
+/* Only the pins' own tests set this; every other caller leaves it at 0.    */
+static int g_mutation = 0;
+void or_set_mutation(int code) { g_mutation = code; }
+
 static void quat_mul(const double a[4], const double b[4], double out[4])
 {
     double r[4];
@@ -342,8 +347,8 @@ static void rigid_implicit(const double *s, double mass, double i_par, double i_
             double Iw = (i == j ? i_perp : 0.0) + (i_par - i_perp) * t[i] * t[j];
             K[i][j] = (i == j ? mass : 0.0) + A[3 * i + j];
             K[i][3 + j] = B[3 * i + j];
-            K[3 + i][j] = B[3 * j + i];
-            K[3 + i][3 + j] = Iw + Cm[3 * i + j];
+            K[3 + i][j] = g_mutation == 1 ? B[3 * i + j] : B[3 * j + i];
+            K[3 + i][3 + j] = Iw + (g_mutation == 2 ? -Cm[3 * i + j] : Cm[3 * i + j]);
         }
     for (int i = 0; i < 3; ++i) {
         b[i] = mass * V[i] + F0[i] + Fe[i];
@@ -469,6 +474,7 @@ typedef struct {
     double F[3], M[3];
     double F0p[3], M0p[3];  /* velocity-free sums of the previous step */
     int have_prev;
+    double sums[39];        /* last step's momentum-exchange sums (see or_get_exchange_sums) */
     double corr[6];         /* closure correction dF, dM for the next step */
     int has_corr;
     double *traj;           /* prescribed kinematics, 13 per step, or NULL */
@@ -843,7 +849,8 @@ static void one_step(or_sim *s)
                     for (int i = 0; i < 3; ++i)
                         for (int j = 0; j < 3; ++j) {
                             acc[12 + 3 * i + j] += k6 * cq[i] * cq[j];
-                            acc[21 + 3 * i + j] += k6 * cq[i] * rc[j];
+                            acc[21 + 3 * i + j] += g_mutation == 3 ? k6 * rc[i] * cq[j]
+                                                                   : k6 * cq[i] * rc[j];
                             acc[30 + 3 * i + j] += k6 * rc[i] * rc[j];
                         }
                 }
@@ -895,6 +902,7 @@ static void one_step(or_sim *s)
             me[k] = f->mext[k] + cl[6 * i + 3 + k];
         }
         memcpy(old + 16 * i, f->st, 16 * sizeof(double));
+        memcpy(f->sums, rd, 39 * sizeof(double));
         /* closure correction of this step (zero when none was set) */
         double cF[3] = {0.0, 0.0, 0.0}, cM[3] = {0.0, 0.0, 0.0};
         if (f->has_corr)
@@ -920,8 +928,9 @@ static void one_step(or_sim *s)
             double F0u[3], M0u[3];
             for (int k = 0; k < 3; ++k) {
                 const int avg = p->coupling == 0 && f->have_prev;
-                F0u[k] = avg ? 0.5 * (rd[6 + k] + f->F0p[k]) : rd[6 + k];
-                M0u[k] = avg ? 0.5 * (rd[9 + k] + f->M0p[k]) : rd[9 + k];
+                const double h = g_mutation == 4 ? 1.0 : 0.5;
+                F0u[k] = avg ? h * (rd[6 + k] + f->F0p[k]) : rd[6 + k];
+                M0u[k] = avg ? h * (rd[9 + k] + f->M0p[k]) : rd[9 + k];
                 if (f->has_corr) {
                     F0u[k] += cF[k];
                     M0u[k] += cM[k];
@@ -1056,5 +1065,10 @@ int64_t or_get_history(const or_sim *s, int64_t first, int64_t count, double *ou
 }
 
 int64_t or_overlaps(const or_sim *s) { return s->overlaps; }
+
+void or_get_exchange_sums(const or_sim *s, double *out)
+{
+    for (int i = 0; i < s->nf; ++i) memcpy(out + 39 * i, s->fib[i].sums, 39 * sizeof(double));
+}
 int64_t or_steps_done(const or_sim *s) { return s->steps; }
 int or_nfibers(const or_sim *s) { return s->nf; }

@@ -122,6 +122,17 @@ void    or_get_fiber_state(const or_sim *s, double *X, double *q, double *V, dou
 void    or_get_force_torque(const or_sim *s, double *F, double *M);
 int64_t or_get_history(const or_sim *s, int64_t first, int64_t count, double *out);
 int64_t or_overlaps(const or_sim *s);
+/* momentum-exchange sums of the last step per fiber, [nf][39]: the direct
+   force F3 and torque M3 of Eq. LBMhydrodynForce (every term at the velocity
+   of the state the step started from), then the split used by the implicit
+   couplings: velocity-free part F0 3, M0 3 and the row-major 3x3 matrices
+   A, B, C of the part linear in u_s = V + W x r, so that the direct sums are
+   F0 - A V - B W and M0 - B^T V - C W */
+void    or_get_exchange_sums(const or_sim *s, double *out);
+/* test hook: plant a known mistake (1: B instead of B^T in the torque row of
+   the implicit solve; 2: -C instead of C there; 3: B accumulated transposed;
+   4: the two-step mean without its factor 1/2); 0 restores the oracle */
+void    or_set_mutation(int code);
 /* closest points of two axis segments X + s t, |s| <= h (t unit): returns the distance and
    the parameters s (first segment) and u (second); parallel axes: middle of the overlap */
 double or_segment_closest(const double Xp[3], const double tp[3], double hp, const double Xq[3],

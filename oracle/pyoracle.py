@@ -87,6 +87,8 @@ def lib():
         L.or_steps_done.argtypes = [C.c_void_p]
         L.or_steps_done.restype = C.c_int64
         L.or_nfibers.argtypes = [C.c_void_p]
+        L.or_get_exchange_sums.argtypes = [C.c_void_p, _dp]
+        L.or_set_mutation.argtypes = [C.c_int]
         _LIB = L
     return _LIB
 
@@ -167,6 +169,23 @@ def cell_inside(c, X, t, length, radius, shape="cylinder", dims=(1 << 20, 1 << 2
     return bool(lib().or_cell_inside_shape(_d(_arr(c, 3)), _d(_arr(X, 3)), _d(_arr(t, 3)),
                                            float(length), float(radius), code, dims[0], dims[1],
                                            dims[2], int(z_periodic)))
+
+
+def set_mutation(code):
+    """Plant a known mistake in the oracle (tests of the pins only); 0 clears it."""
+    lib().or_set_mutation(int(code))
+
+
+def rigid_step_implicit(state, mass, i_par, i_perp, F0, M0, A, B, Cm,
+                        shape=(1 << 20, 1 << 20, 1 << 20), z_periodic=True):
+    """Implicit step: solves (m + A) V' + B W' = m V + F0, B^T V' + (I + C) W' = Lang + M0.
+    Returns (new state, applied F, applied M)."""
+    out, Fa, Ma = np.zeros(16), np.zeros(3), np.zeros(3)
+    nx, ny, nz = shape
+    lib().or_rigid_step_implicit(_d(_arr(state, 16)), mass, i_par, i_perp, _d(_arr(F0, 3)),
+                                 _d(_arr(M0, 3)), _d(_arr(A, 9)), _d(_arr(B, 9)), _d(_arr(Cm, 9)),
+                                 nx, ny, nz, int(z_periodic), _d(out), _d(Fa), _d(Ma))
+    return out, Fa, Ma
 
 
 def rigid_step(state, mass, i_par, i_perp, F, M, shape=(1 << 20, 1 << 20, 1 << 20),
@@ -294,6 +313,15 @@ class Sim:
         F, M = np.zeros((n, 3)), np.zeros((n, 3))
         lib().or_get_force_torque(self._h, _d(F), _d(M))
         return F, M
+
+    def exchange_sums(self):
+        """Last step's sums per fiber: dict of F, M (direct), F0, M0 [n][3] and A, B, C [n][3][3]."""
+        n = self.nfibers
+        out = np.zeros((n, 39))
+        lib().or_get_exchange_sums(self._h, _d(out))
+        return {"F": out[:, 0:3], "M": out[:, 3:6], "F0": out[:, 6:9], "M0": out[:, 9:12],
+                "A": out[:, 12:21].reshape(n, 3, 3), "B": out[:, 21:30].reshape(n, 3, 3),
+                "C": out[:, 30:39].reshape(n, 3, 3)}
 
     def history(self, first=0, count=None):
         """[steps][nfibers][19]: F3 M3 X3 q4 V3 W3 after each step."""
