@@ -8,6 +8,7 @@
 #include "lbm_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -1065,6 +1066,9 @@ int64_t or_get_history(const or_sim *s, int64_t first, int64_t count, double *ou
 }
 
 int64_t or_overlaps(const or_sim *s) { return s->overlaps; }
+
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int or_get_threads(void) { return omp_get_max_threads(); }
 
 void or_get_exchange_sums(const or_sim *s, double *out)
 {

@@ -133,6 +133,10 @@ void    or_get_exchange_sums(const or_sim *s, double *out);
    the implicit solve; 2: -C instead of C there; 3: B accumulated transposed;
    4: the two-step mean without its factor 1/2); 0 restores the oracle */
 void    or_set_mutation(int code);
+/* OpenMP threads of the following steps (timing on one core or all), and
+   the current count */
+void    or_set_threads(int n);
+int     or_get_threads(void);
 /* closest points of two axis segments X + s t, |s| <= h (t unit): returns the distance and
    the parameters s (first segment) and u (second); parallel axes: middle of the overlap */
 double or_segment_closest(const double Xp[3], const double tp[3], double hp, const double Xq[3],

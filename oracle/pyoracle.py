@@ -89,6 +89,8 @@ def lib():
         L.or_nfibers.argtypes = [C.c_void_p]
         L.or_get_exchange_sums.argtypes = [C.c_void_p, _dp]
         L.or_set_mutation.argtypes = [C.c_int]
+        L.or_set_threads.argtypes = [C.c_int]
+        L.or_get_threads.restype = C.c_int
         _LIB = L
     return _LIB
 
@@ -169,6 +171,15 @@ def cell_inside(c, X, t, length, radius, shape="cylinder", dims=(1 << 20, 1 << 2
     return bool(lib().or_cell_inside_shape(_d(_arr(c, 3)), _d(_arr(X, 3)), _d(_arr(t, 3)),
                                            float(length), float(radius), code, dims[0], dims[1],
                                            dims[2], int(z_periodic)))
+
+
+def set_threads(n):
+    """OpenMP threads used by the following oracle steps."""
+    lib().or_set_threads(int(n))
+
+
+def get_threads():
+    return int(lib().or_get_threads())
 
 
 def set_mutation(code):
