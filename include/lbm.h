@@ -222,6 +222,20 @@ lbm_status lbm_get_force_torque(lbm_ctx *ctx, double *F, double *M);
 lbm_status lbm_get_fields(lbm_ctx *ctx, void *rho, void *u, uint8_t *flags, int32_t *pid,
                           int32_t dst_is_device);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * monitoring loops, harnesses that forbid allocation): lbm_get_fields with
+ * host destinations (dst_is_device = 0) that calls no hipMalloc, hipFree or
+ * other allocating routine.  The fields are decoded in chunks of cells into
+ * a fixed 16 MiB device array held by the library (one per GPU, kept until
+ * the process ends) and copied out chunk by chunk, so any lattice size is
+ * accepted.  Arguments, layout and values are those of lbm_get_fields; the
+ * call synchronises the context's stream.  All calls on one GPU share that
+ * array: calls that overlap in time on one GPU (from several host threads)
+ * race and must be serialised by the caller.  Errors: LBM_E_ARG for a NULL
+ * context or a device index of 64 or more, LBM_E_HIP, and the device errors
+ * of lbm_sync. */
+lbm_status lbm_get_fields_static(lbm_ctx *ctx, void *rho, void *u, uint8_t *flags, int32_t *pid);
+
 /* Fiber states, FP64 host arrays [nfibers][3] / [nfibers][4]. */
 lbm_status lbm_get_fiber_state(lbm_ctx *ctx, double *X, double *q, double *V, double *W);
 

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -18,6 +19,7 @@ using namespace lbm;
 struct lbm_ctx {
     lbm_params p{};
     std::string err;
+    int dev = 0;              // device current at creation (the stream's device)
     hipStream_t st = nullptr;
     int sk = 0;
     size_t esz = 4;
@@ -516,6 +518,10 @@ lbm_status lbm_create(const lbm_params *p, lbm_ctx **out)
     lbm_ctx *c = new (std::nothrow) lbm_ctx;
     if (!c) return LBM_E_NOMEM;
     c->p = *p;
+    if (hipGetDevice(&c->dev) != hipSuccess) {
+        delete c;
+        return LBM_E_HIP;
+    }
     c->st = (hipStream_t)p->stream;
     if (!c->st) {
         // graph capture needs a real stream: make a private one (default priority)
@@ -832,6 +838,79 @@ lbm_status lbm_get_fields(lbm_ctx *c, void *rho, void *u, uint8_t *flags, int32_
     HIPCHK(c, hipStreamSynchronize(c->st));
     if (rho && !dst_is_device) hipFree(drho);
     if (u && !dst_is_device) hipFree(du);
+    return LBM_OK;
+}
+
+// ------------------------------------------------------------------ allocation-free field readback
+// The staging memory of lbm_get_fields_static: a fixed device array, one copy
+// per GPU, held until the process ends.  Host code never passes the name
+// `scratch` to a kernel or a copy (on the host it is only a stand-in for the
+// symbol); it uses the device address that hipGetSymbolAddress returns, kept
+// per device in scratch_ptr.
+static constexpr size_t SCRATCH_BYTES = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+static constexpr int SCRATCH_MAX_DEV = 64;
+static void *scratch_ptr[SCRATCH_MAX_DEV] = {};
+static std::mutex scratch_mu;
+
+// device address of `scratch` on device dev, resolved once with dev current
+static hipError_t scratch_on(int dev, void **out)
+{
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        scratch_ptr[dev] = ptr;
+    }
+    *out = scratch_ptr[dev];
+    return hipSuccess;
+}
+
+lbm_status lbm_get_fields_static(lbm_ctx *c, void *rho, void *u, uint8_t *flags, int32_t *pid)
+{
+    if (!c) return LBM_E_ARG;
+    if (c->dev < 0 || c->dev >= SCRATCH_MAX_DEV)
+        return fail(c, LBM_E_ARG, "lbm_get_fields_static: device index beyond the scratch table");
+    lbm_status s = check_device_errors(c);
+    if (s != LBM_OK) return s;
+    void *sp = nullptr;
+    HIPCHK(c, scratch_on(c->dev, &sp));
+    const size_t n = c->g.ncell, rsz = c->sk == S_F64 ? 8 : 4;
+    // cells per chunk: rho (1 value) and u (3 values) of each cell in the scratch
+    const size_t chunk = SCRATCH_BYTES / (4 * rsz);
+    char *srho = (char *)sp, *su = (char *)sp + chunk * rsz;
+    PState *cur = c->np ? c->ps[c->steps & 1] : nullptr;
+    const bool sw = (c->steps & 1) != 0;
+    for (size_t c0 = 0; (rho || u) && c0 < n; c0 += chunk) {
+        const size_t m = std::min(chunk, n - c0);
+        HIPCHK(c, launch_decode_range(c->sk, sw, c->f, c->flags[c->steps & 1], c->pid, cur, c->g, c->ph,
+                                      rho ? (void *)srho : nullptr, u ? (void *)su : nullptr, nullptr,
+                                      uint32_t(c0), uint32_t(c0 + m), chunk, c->st));
+        if (rho)
+            HIPCHK(c, hipMemcpyAsync((char *)rho + c0 * rsz, srho, m * rsz, hipMemcpyDeviceToHost, c->st));
+        if (u)
+            for (int k = 0; k < 3; ++k)
+                HIPCHK(c, hipMemcpyAsync((char *)u + (k * n + c0) * rsz, su + k * chunk * rsz, m * rsz,
+                                         hipMemcpyDeviceToHost, c->st));
+        // the next chunk overwrites the scratch: wait for the copies out of it
+        HIPCHK(c, hipStreamSynchronize(c->st));
+    }
+    if (flags) HIPCHK(c, hipMemcpyAsync(flags, c->flags[c->steps & 1], n, hipMemcpyDeviceToHost, c->st));
+    if (pid) HIPCHK(c, hipMemcpyAsync(pid, c->pid, n * 4, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    // logical flags: 0 fluid, 1 fiber (the near-boundary bit is internal)
+    if (flags)
+        for (size_t i = 0; i < n; ++i) flags[i] &= F_SOLID;
     return LBM_OK;
 }
 

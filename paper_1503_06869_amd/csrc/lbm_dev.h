@@ -232,6 +232,11 @@ hipError_t launch_boundary(int sk, bool odd, void *f, const Geo &g, const Phys<d
 hipError_t launch_decode(int sk, bool swapped, const void *f, const uint8_t *flags,
                          const int32_t *pid, const PState *ps, const Geo &g, const Phys<double> &ph,
                          void *rho, void *u, double *fout, hipStream_t st);
+// decode of the cells [c0, c1) only: rho[cell - c0], u[k * ustride + cell - c0]
+hipError_t launch_decode_range(int sk, bool swapped, const void *f, const uint8_t *flags,
+                               const int32_t *pid, const PState *ps, const Geo &g,
+                               const Phys<double> &ph, void *rho, void *u, double *fout,
+                               uint32_t c0, uint32_t c1, uint64_t ustride, hipStream_t st);
 hipError_t launch_encode(int sk, bool swapped, void *f, const Geo &g, double rho0, double scale,
                          const double *fin, hipStream_t st);
 hipError_t launch_rigid(const PartData &pd, const Geo &g, hipStream_t st);

@@ -68,14 +68,17 @@ __global__ void k_init(S *__restrict__ f, Geo g, double rho0, double wall_u, int
 }
 
 // ------------------------------------------------------------------ decode / encode
+// Cells [c0, c1) of the lattice; rho and u are written at cell - c0 (u's
+// components ustride apart), fout (all cells, c0 = 0) at the cell index.
 template <typename S>
 __global__ void k_decode(const S *__restrict__ f, const uint8_t *__restrict__ flags,
                          const int32_t *__restrict__ pid, const PState *__restrict__ ps, Geo g,
                          Phys<double> ph, int swapped, typename St<S>::R *rho,
-                         typename St<S>::R *u, double *fout)
+                         typename St<S>::R *u, double *fout, uint32_t c0, uint32_t c1,
+                         uint64_t ustride)
 {
     using R = typename St<S>::R;
-    for (uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x; cell < g.ncell;
+    for (uint32_t cell = c0 + blockIdx.x * blockDim.x + threadIdx.x; cell < c1;
          cell += gridDim.x * blockDim.x) {
         const uint32_t z = cell / g.nxy, y = (cell % g.nxy) / g.nx, x = cell % g.nx;
         double fv[Q];
@@ -107,9 +110,9 @@ __global__ void k_decode(const S *__restrict__ f, const uint8_t *__restrict__ fl
             r = ph.rho0 + dr;
             for (int k = 0; k < 3; ++k) uu[k] = j[k] / ph.rho0 + 0.5 * ph.g[k];
         }
-        if (rho) rho[cell] = R(r);
+        if (rho) rho[cell - c0] = R(r);
         if (u)
-            for (int k = 0; k < 3; ++k) u[uint64_t(k) * g.ncell + cell] = R(uu[k]);
+            for (int k = 0; k < 3; ++k) u[uint64_t(k) * ustride + (cell - c0)] = R(uu[k]);
         if (fout)
             for (int q = 0; q < Q; ++q) fout[uint64_t(q) * g.ncell + cell] = fv[q] + wq(q) * ph.rho0;
     }
@@ -202,19 +205,29 @@ hipError_t launch_init(int sk, void *f, const Geo &g, double rho0, double wall_u
     return hipGetLastError();
 }
 
+hipError_t launch_decode_range(int sk, bool swapped, const void *f, const uint8_t *flags,
+                               const int32_t *pid, const PState *ps, const Geo &g,
+                               const Phys<double> &ph, void *rho, void *u, double *fout,
+                               uint32_t c0, uint32_t c1, uint64_t ustride, hipStream_t st)
+{
+    if (c1 <= c0) return hipSuccess;
+    const uint32_t gr = grid_for(c1 - c0, 256);
+    const int sw = swapped ? 1 : 0;
+    switch (sk) {
+    case S_F32: hipLaunchKernelGGL(k_decode<float>, dim3(gr), dim3(256), 0, st, (const float *)f, flags, pid, ps, g, ph, sw, (float *)rho, (float *)u, fout, c0, c1, ustride); break;
+    case S_F16: hipLaunchKernelGGL(k_decode<_Float16>, dim3(gr), dim3(256), 0, st, (const _Float16 *)f, flags, pid, ps, g, ph, sw, (float *)rho, (float *)u, fout, c0, c1, ustride); break;
+    case S_BF16: hipLaunchKernelGGL(k_decode<bf16s>, dim3(gr), dim3(256), 0, st, (const bf16s *)f, flags, pid, ps, g, ph, sw, (float *)rho, (float *)u, fout, c0, c1, ustride); break;
+    default: hipLaunchKernelGGL(k_decode<double>, dim3(gr), dim3(256), 0, st, (const double *)f, flags, pid, ps, g, ph, sw, (double *)rho, (double *)u, fout, c0, c1, ustride); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_decode(int sk, bool swapped, const void *f, const uint8_t *flags,
                          const int32_t *pid, const PState *ps, const Geo &g, const Phys<double> &ph,
                          void *rho, void *u, double *fout, hipStream_t st)
 {
-    const uint32_t gr = grid_for(g.ncell, 256);
-    const int sw = swapped ? 1 : 0;
-    switch (sk) {
-    case S_F32: hipLaunchKernelGGL(k_decode<float>, dim3(gr), dim3(256), 0, st, (const float *)f, flags, pid, ps, g, ph, sw, (float *)rho, (float *)u, fout); break;
-    case S_F16: hipLaunchKernelGGL(k_decode<_Float16>, dim3(gr), dim3(256), 0, st, (const _Float16 *)f, flags, pid, ps, g, ph, sw, (float *)rho, (float *)u, fout); break;
-    case S_BF16: hipLaunchKernelGGL(k_decode<bf16s>, dim3(gr), dim3(256), 0, st, (const bf16s *)f, flags, pid, ps, g, ph, sw, (float *)rho, (float *)u, fout); break;
-    default: hipLaunchKernelGGL(k_decode<double>, dim3(gr), dim3(256), 0, st, (const double *)f, flags, pid, ps, g, ph, sw, (double *)rho, (double *)u, fout); break;
-    }
-    return hipGetLastError();
+    return launch_decode_range(sk, swapped, f, flags, pid, ps, g, ph, rho, u, fout, 0, g.ncell,
+                               g.ncell, st);
 }
 
 hipError_t launch_encode(int sk, bool swapped, void *f, const Geo &g, double rho0, double scale,

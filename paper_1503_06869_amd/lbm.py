@@ -31,7 +31,7 @@ EXPORTED = [
     "lbm_get_force_torque", "lbm_get_fields", "lbm_get_fiber_state", "lbm_set_fiber_state",
     "lbm_get_history", "lbm_get_populations", "lbm_set_populations", "lbm_get_info",
     "lbm_enable_sweep_timing", "lbm_get_sweep_time", "lbm_copy_bytes", "lbm_get_mean_velocity",
-    "lbm_get_params", "lbm_save", "lbm_load",
+    "lbm_get_params", "lbm_save", "lbm_load", "lbm_get_fields_static",
 ]
 EXPORTED_BATCH = [
     "lbm_batch_params_default", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_last_error",
@@ -128,6 +128,7 @@ def load():
         "lbm_sync": ([vp], C.c_int),
         "lbm_get_force_torque": ([vp, _dp, _dp], C.c_int),
         "lbm_get_fields": ([vp, vp, vp, vp, vp, C.c_int32], C.c_int),
+        "lbm_get_fields_static": ([vp, vp, vp, vp, vp], C.c_int),
         "lbm_get_fiber_state": ([vp, _dp, _dp, _dp, _dp], C.c_int),
         "lbm_set_fiber_state": ([vp, C.c_int32, _dp, _dp, _dp, _dp], C.c_int),
         "lbm_get_history": ([vp, C.c_int64, C.c_int64, _dp], C.c_int),
@@ -300,6 +301,18 @@ class Context:
         pid = np.zeros((nz, ny, nx), np.int32)
         self._chk(load().lbm_get_fields(self._h, rho.ctypes.data, u.ctypes.data, flags.ctypes.data,
                                         pid.ctypes.data, 0))
+        return rho, u, flags, pid
+
+    def fields_static(self):
+        """As fields(), through lbm_get_fields_static (no device allocation)."""
+        nx, ny, nz = self.shape
+        dt = np.float64 if self.storage == LBM_F64 else np.float32
+        rho = np.zeros((nz, ny, nx), dt)
+        u = np.zeros((3, nz, ny, nx), dt)
+        flags = np.zeros((nz, ny, nx), np.uint8)
+        pid = np.zeros((nz, ny, nx), np.int32)
+        self._chk(load().lbm_get_fields_static(self._h, rho.ctypes.data, u.ctypes.data,
+                                               flags.ctypes.data, pid.ctypes.data))
         return rho, u, flags, pid
 
     def fields_to_device(self, rho_ptr, u_ptr):
