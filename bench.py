@@ -12,13 +12,18 @@ rebuild.  Inputs are synthetic and resident in HBM before timing starts.
 
 Prints one JSON line: MLUPS (all cells x steps / s), the roofline of the
 dominant kernel (the bulk stream-collide sweep, timed live with HIP events
-on the stream it runs on), and the FP64 oracle's rate on a bounded sample of
-the same workload on the host cores.  The FP16/BF16 deviation-storage forms
-of the same workload, and the batched form (512 independent one-fiber shear
-cells of uneven size, edges 24..64, in one persistent graph-captured launch
-with autotuned workgroup size and bin count), and the learned-coarse form
-(128^3, 200 under-resolved fibers with the trained closure attached, beside
-the same run without it) are timed too and reported under "forms".
+on the stream it runs on), and the FP64 oracle's rate on bounded samples on
+the host cores (the same workload on all cores; the 32^3 single-fiber cell
+in full on all cores and on one core).  The FP16/BF16 deviation-storage
+forms of the same workload, the batched form (512 independent one-fiber
+shear cells of uneven size, edges 24..64, in one persistent graph-captured
+launch with autotuned workgroup size and bin count), and the learned-coarse
+form (128^3, 200 under-resolved fibers with the trained closure attached,
+beside the same run without it) are timed too and reported under "forms",
+each with its error: the storage forms against the FP64 oracle on the 32^3
+single-fiber cell (velocity, force and torque after 3000 steps; tumbling
+period), the learned form against the resolved fine run (single-fiber
+tumbling period).
 """
 import argparse
 import json
@@ -170,7 +175,21 @@ def time_learned(steps, warmup, torch):
             a, fb = g.closure_stats()
             out[name]["fallback_frac"] = round(fb / max(1, a + fb), 4)
         g.close()
-    out["learned"]["fine_equivalent_mlups"] = round(32 * out["learned"]["mlups"], 1)
+    # error at matched physical time: the free tumbling period of one fiber
+    # (seed 0) coarse, coarse + closure, and resolved (fine twin, diameter 4,
+    # diffusive scaling: 4 fine steps per coarse step)
+    from paper_1503_06869_amd import jeffery
+    pr = closure.tumble_pair(seed=0)
+    nc = 25000
+    per = {}
+    for name, scn, n, m in (("fine", pr.fine, 4 * nc, None), ("plain", pr.coarse, nc, None),
+                            ("learned", pr.coarse, nc, mlp)):
+        h, _ = closure.run_free(scn, n, mlp=m)
+        T, _ = jeffery.period(jeffery.axis_from_quat(h[:, 9:13])[:, 0], min_crossings=3)
+        per[name] = T / (4.0 if name == "fine" else 1.0)
+    for name in ("plain", "learned"):
+        out[name]["single_fiber_period_rel_error_vs_fine"] = float("%.3g" % (per[name] / per["fine"] - 1))
+    out["single_fiber_periods_coarse_steps"] = {k: round(v, 1) for k, v in per.items()}
     mlp.close()
     return out
 
@@ -187,21 +206,111 @@ def sweep_traffic():
     return SWEEP_TRAFFIC["bytes_per_launch"] if sweep_sources_sha1() == SWEEP_TRAFFIC["sweep_sha1"] else None
 
 
-def cpu_baseline(sc, nsteps=2):
-    """FP64 oracle on the host cores: the same 256^3 workload for nsteps steps."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_c1(threads, steps):
+    """The FP64 oracle on the 32^3 single-fiber shear cell (seed 0, U 0.005)
+    on `threads` host threads; returns the sim and the seconds of its step loop."""
     from oracle import pyoracle as O
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    s = O.Sim(sc.nx, sc.ny, sc.nz, tau=sc.tau, magic=sc.magic, wall_u=sc.wall_u,
-              init_couette=True)
+    from paper_1503_06869_amd import scenarios
+    sc = scenarios.single_fiber(seed=0)
+    f = sc.fibers[0]
+    O.set_threads(threads)
+    o = O.Sim(sc.nx, sc.ny, sc.nz, tau=sc.tau, magic=sc.magic, wall_u=sc.wall_u, init_couette=True)
+    o.add_fiber(f.X, f.q, f.length, f.radius, f.density_ratio, f.V, f.W)
+    t = time.perf_counter()
+    o.step(steps)
+    return o, time.perf_counter() - t
+
+
+def cpu_baseline(sc, c1_steps=3000, c1_one_core_steps=300, c2_steps=10):
+    """FP64 oracle on the host: the 256^3 64-fiber workload (value, all
+    cores, c2_steps steps after set-up, per-step rate extrapolated), the
+    32^3 single-fiber cell in full (3000 steps, all cores) and on one core
+    (c1_one_core_steps, extrapolated).  Returns the record and the all-core
+    32^3 oracle run (used for the storage forms' errors)."""
+    from oracle import pyoracle as O
+    threads = O.get_threads()
+    o_c1, t_all = oracle_c1(threads, c1_steps)
+    _, t_one = oracle_c1(1, c1_one_core_steps)
+    O.set_threads(threads)
+    s = O.Sim(sc.nx, sc.ny, sc.nz, tau=sc.tau, magic=sc.magic, wall_u=sc.wall_u, init_couette=True)
     for f in sc.fibers:
         s.add_fiber(f.X, f.q, f.length, f.radius, f.density_ratio, f.V, f.W)
     t = time.perf_counter()
-    s.step(nsteps)
+    s.step(c2_steps)
     dt = time.perf_counter() - t
-    return {"value": sc.ncell * nsteps / dt / 1e6, "unit": "MLUPS", "cores": threads,
-            "kind": "oracle",
-            "sample": "%d steps of the 256^3 64-fiber shear cell (FP64, %d OpenMP threads, %.1f s)"
-                      % (nsteps, threads, dt)}
+    del s
+    c1 = 32 ** 3
+    rec = {"value": round(sc.ncell * c2_steps / dt / 1e6, 2), "unit": "MLUPS", "cores": threads,
+           "kind": "oracle",
+           "sample": "%d steps of the 256^3 64-fiber shear cell after set-up (FP64, %d OpenMP threads, "
+                     "%.1f s; per-step rate extrapolated to the 5000-step run)" % (c2_steps, threads, dt),
+           "cpu_model": cpu_model(),
+           "c1_32cube_all_cores": {"mlups": round(c1 * c1_steps / t_all / 1e6, 3), "steps": c1_steps,
+                                   "seconds": round(t_all, 2), "threads": threads},
+           "c1_32cube_one_core": {"mlups": round(c1 * c1_one_core_steps / t_one / 1e6, 3),
+                                  "steps": c1_one_core_steps, "seconds": round(t_one, 2), "threads": 1,
+                                  "seconds_for_3000_steps_extrapolated": round(t_one * 3000 / c1_one_core_steps, 1)}}
+    return rec, o_c1
+
+
+def _ft_rel(hg, ho, length):
+    """Force and torque errors over a run, max over steps, relative to the
+    fiber's load (F to max(|F|, |M|/L), M to max(|M|, L|F|))."""
+    dF = np.linalg.norm(hg[:, 0:3] - ho[:, 0:3], axis=1).max()
+    dM = np.linalg.norm(hg[:, 3:6] - ho[:, 3:6], axis=1).max()
+    nF = np.linalg.norm(ho[:, 0:3], axis=1).max()
+    nM = np.linalg.norm(ho[:, 3:6], axis=1).max()
+    return float(dF / max(nF, nM / length)), float(dM / max(nM, nF * length))
+
+
+def storage_errors(o_c1, storage, torch, c1_steps=3000, period_steps=124000):
+    """Error of a storage form against the FP64 oracle: the 32^3 single-fiber
+    cell (U 0.005) after 3000 steps (fluid velocity relative L2, force and
+    torque over the run), and its tumbling period over 124,000 steps against
+    the oracle's (tests/golden/jeffery_single_fiber.json, written from the
+    oracle alone)."""
+    from paper_1503_06869_amd import jeffery, lbm, scenarios
+    sc = scenarios.single_fiber(seed=0)
+    f = sc.fibers[0]
+    out = {}
+    if o_c1 is not None:
+        g = lbm.Context(sc.nx, sc.ny, sc.nz, tau=sc.tau, wall_u=sc.wall_u, init_couette=True,
+                        storage=storage, history_capacity=c1_steps)
+        g.add_fiber(f.X, f.q, f.length, f.radius, f.density_ratio, f.V, f.W)
+        g.step(c1_steps)
+        _, ug, flg, _ = g.fields()
+        hg = g.history(0, c1_steps)[:, 0, :]
+        g.close()
+        _, uo, flo, _ = o_c1.fields()
+        fl = (flo == 0) & (flg == 0)
+        eu = float(np.linalg.norm((ug.astype(np.float64) - uo)[:, fl]) / np.linalg.norm(uo[:, fl]))
+        eF, eM = _ft_rel(hg, o_c1.history()[:, 0, :], f.length)
+        out["c1_3000_steps"] = {"velocity_rel_l2": float("%.3g" % eu), "force_rel": float("%.3g" % eF),
+                                "torque_rel": float("%.3g" % eM)}
+    gold_path = os.path.join(ROOT, "tests", "golden", "jeffery_single_fiber.json")
+    if period_steps > 0 and os.path.exists(gold_path):
+        gold = json.load(open(gold_path)).get("U0.005/seed0")
+        if gold:
+            g = lbm.Context(sc.nx, sc.ny, sc.nz, tau=sc.tau, wall_u=sc.wall_u, init_couette=True,
+                            storage=storage, history_capacity=period_steps)
+            g.add_fiber(f.X, f.q, f.length, f.radius, f.density_ratio, f.V, f.W)
+            g.step(period_steps)
+            h = g.history(0, period_steps)
+            g.close()
+            T, _ = jeffery.period(jeffery.axis_from_quat(h[:, 0, 9:13])[:, 0])
+            out["c1_tumbling_period"] = {"steps": round(T, 1), "oracle_steps": round(gold["period"], 1),
+                                         "rel_error": float("%.3g" % (T / gold["period"] - 1))}
+    return out
 
 
 def main():
@@ -216,6 +325,8 @@ def main():
                     help="steps of the batched form's timed launch (0: skip it)")
     ap.add_argument("--learned-steps", type=int, default=500,
                     help="steps of the learned-coarse form (0: skip it)")
+    ap.add_argument("--no-error-checks", dest="error_checks", action="store_false",
+                    help="skip the storage forms' errors against the FP64 oracle")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run the plain copy kernel (traffic-counter calibration)")
     a = ap.parse_args()
@@ -251,6 +362,9 @@ def main():
     main_form = time_form(sc, "f32", a.steps, a.warmup, torch)
     forms = {"f32": {"mlups": round(main_form["mlups"], 1),
                      "sweep_hbm_frac": round(main_form["sweep_gbs"] / HBM_PEAK_GBS, 4)}}
+    cpu, o_c1 = (None, None) if a.no_cpu else cpu_baseline(sc)
+    if a.error_checks:
+        forms["f32"]["error_vs_fp64_oracle"] = storage_errors(o_c1, "f32", torch)
     for st in [s for s in a.forms.split(",") if s]:
         if st == "stab":
             # the same step with the momentum stabilization's bookkeeping
@@ -263,13 +377,12 @@ def main():
         forms[st] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
                      "sweep_gbs": round(r["sweep_gbs"], 1),
                      "sweep_hbm_frac": round(r["sweep_gbs"] / HBM_PEAK_GBS, 4)}
+        if a.error_checks:
+            forms[st]["error_vs_fp64_oracle"] = storage_errors(o_c1, st, torch)
     if a.batched_steps > 0:
         forms["batched_512_cases"] = time_batched(a.batched_steps, 10, torch)
     if a.learned_steps > 0:
         forms["learned_coarse_128cube_200fibers"] = time_learned(a.learned_steps, 20, torch)
-    cpu = None
-    if not a.no_cpu:
-        cpu = cpu_baseline(sc)
     out = {
         "metric": METRIC,
         "value": round(main_form["mlups"], 1),

@@ -1,5 +1,5 @@
-"""Tumbling-period measurement shared by the golden-value script and the
-GPU tests (post-processing only; no simulation arithmetic).
+"""Tumbling-period measurement shared by the golden-value script, the GPU
+tests and the benchmark (post-processing only; no simulation arithmetic).
 
 The period of a Jeffery orbit is measured from the fiber axis history: the
 x component of the axis changes sign each time the fiber passes through the

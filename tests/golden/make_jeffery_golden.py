@@ -22,7 +22,7 @@ sys.path.insert(0, os.path.join(ROOT, "tests"))
 
 from oracle import pyoracle as O          # noqa: E402
 from paper_1503_06869_amd import scenarios  # noqa: E402
-import jeffery                            # noqa: E402
+from paper_1503_06869_amd import jeffery  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "jeffery_single_fiber.json")
 

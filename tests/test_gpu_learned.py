@@ -12,7 +12,6 @@ fiber (fine, coarse, coarse + closure) is reported, not asserted: the
 closure does not yet bring the coarse period reliably closer to the fine
 one."""
 import os
-import sys
 
 import numpy as np
 import pytest
@@ -42,8 +41,7 @@ def test_trained_closure_reduces_held_out_torque_error():
           (Xt.shape[0], inside.mean(), e0[1], e1[1], e1[1] / e0[1]), flush=True)
     assert e1[1] < 0.95 * e0[1]
     # free tumbling of one fiber, reported
-    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-    import jeffery
+    from paper_1503_06869_amd import jeffery
     pr = closure.tumble_pair(seed=0)
     nc = 25000
     res = {}

@@ -21,9 +21,7 @@ import os
 import numpy as np
 import pytest
 
-from paper_1503_06869_amd import lbm, scenarios
-
-import jeffery
+from paper_1503_06869_amd import jeffery, lbm, scenarios
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "jeffery_single_fiber.json")

@@ -826,9 +826,7 @@ def test_oracle_tumbling_period_near_jeffery():
     from the oracle alone) must lie within 15 % of the closed form."""
     import json
     import os
-    import sys
-    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-    import jeffery
+    from paper_1503_06869_amd import jeffery
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
                         "jeffery_single_fiber.json")
     d = json.load(open(path))
