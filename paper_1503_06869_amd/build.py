@@ -21,8 +21,8 @@ ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = {
     "sweep.hip": [],
-    # boundary update with the default contraction of the sweep; the A, B, C
-    # part follows the particle header's contraction-off pragma
+    # boundary update with the default contraction of the sweep (the integer
+    # link sums of the second half do no floating-point arithmetic)
     "boundary.hip": [],
     "particles.hip": ["-ffp-contract=off"],
     "api.hip": ["-ffp-contract=off"],

@@ -187,6 +187,11 @@ static PState make_state(const lbm_fiber &f, const PConst &c)
     return s;
 }
 
+static double link_rho0(const lbm_ctx *c)
+{
+    return c->sk == S_F64 ? c->p.rho0 : double(float(c->p.rho0));
+}
+
 static PartData part_data(lbm_ctx *c, PState *cur, PState *next)
 {
     PartData pd{};
@@ -210,6 +215,7 @@ static PartData part_data(lbm_ctx *c, PState *cur, PState *next)
     pd.hist_cap = c->p.history_capacity;
     pd.coupling = c->p.coupling;
     pd.rho0 = c->p.rho0;
+    pd.rho0_link = link_rho0(c);
     pd.corr = c->closure ? c->corr : nullptr;
     pd.ctr = c->ctr;
     pd.list_cap = c->list_cap;
@@ -219,10 +225,6 @@ static PartData part_data(lbm_ctx *c, PState *cur, PState *next)
 }
 
 // rho0 as the sweep's collision type holds it (float except for FP64 storage)
-static double link_rho0(const lbm_ctx *c)
-{
-    return c->sk == S_F64 ? c->p.rho0 : double(float(c->p.rho0));
-}
 
 static uint32_t grid_cap(uint64_t work, uint32_t lo, uint32_t hi)
 {
@@ -415,12 +417,12 @@ static void launch_one_step(lbm_ctx *c, int64_t step_index, bool with_events, hi
     // fibers: the particle branch is the longer one).
     const bool bulk_first = c->sweep_grid <= 1024u && uint64_t(c->g.ncell) >= 32ull * c->list_cap;
     if (e == hipSuccess && !bulk_first)
-        e = launch_boundary(c->sk, odd, c->f, c->g, c->ph, b, link_rho0(c), c->st2, su, sp_b);
+        e = launch_boundary(c->sk, odd, c->f, c->g, c->ph, b, c->st2, su, sp_b);
     if (e == hipSuccess)
         e = launch_sweep(c->sk, odd, c->f, c->flags[step_index & 1], c->g, c->ph, c->sweep_grid, c->st,
                          with_events ? e0 : nullptr, with_events ? e1 : nullptr, su, sp);
     if (e == hipSuccess && bulk_first)
-        e = launch_boundary(c->sk, odd, c->f, c->g, c->ph, b, link_rho0(c), c->st2, su, sp_b);
+        e = launch_boundary(c->sk, odd, c->f, c->g, c->ph, b, c->st2, su, sp_b);
     PartData pd = part_data(c, cur, next);
     if (stab) {
         pd.cov = c->cov;

@@ -58,7 +58,7 @@ struct BatchDev {
     uint32_t *list_n;          // [ncase] entries found by the last rebuild (may exceed the cap)
     PState *ps;                // [ncase][2]: state at even / odd time levels
     Box *box_cur;              // [ncase]
-    long long *abc;            // [ncase][NABC] population-free sums for the next sweep
+    long long *abc;            // [ncase][NABC] population-free integer sums (SA, SB, SC) for the next step
     long long *foreign;        // [NACC] sink for links to another fiber (none in a one-fiber case)
     double *ft;                // [ncase][6]
     double *hist;              // [ncase][hist_cap][19]
@@ -169,7 +169,8 @@ __device__ __forceinline__ void case_particles(const BatchDev &bd, int c, const 
         if (!setup) {
             double ac[NACC];
             for (int k = 0; k < 6; ++k) ac[k] = ldexp(double(sh.tot[k]), -fx_shift(k));
-            for (int k = 6; k < NACC; ++k) ac[k] = ldexp(double(bd.abc[size_t(c) * NABC + k - 6]), -fx_shift(k));
+            for (int k = 6; k < NACC; ++k) ac[k] = double(bd.abc[size_t(c) * NABC + k - 6]);
+            abc_restore(ac, so.X, double(case_phys<R>(cd).rho0));
             const double *row = nullptr;
             if (cd.pc.traj_off >= 0 && bd.traj_pos[c] < cd.pc.traj_n) {
                 row = bd.traj + (cd.pc.traj_off + bd.traj_pos[c]) * 13;
@@ -275,13 +276,12 @@ __device__ __forceinline__ void case_particles(const BatchDev &bd, int c, const 
     }
     __syncthreads();
     // flags, boundary list, and the population-free link sums at the new pose
-    using RR = typename St<S>::R;
-    const double r0 = double(case_phys<RR>(cd).rho0);
     uint32_t *lc = bd.list_cell + cd.list_off, *lm = bd.list_mask + cd.list_off;
     long long acc[NABC];
 #pragma unroll
     for (int k = 0; k < NABC; ++k) acc[k] = 0;
-    const PState &sp = sh.nxt;
+    int32_t xr[3];
+    fiber_ref(sh.nxt.X, xr);
     for (uint32_t i = threadIdx.x; i < total; i += BS) {
         int32_t x, y, z;
         locate(i, x, y, z);
@@ -312,10 +312,9 @@ __device__ __forceinline__ void case_particles(const BatchDev &bd, int c, const 
                 const uint32_t yy = (uint32_t(y) + g.ny + CY[q]) % g.ny;
                 const int32_t yzi = z + CZ[q];
                 const uint32_t yz = g.zper ? uint32_t((yzi + int32_t(g.nz)) % int32_t(g.nz)) : uint32_t(yzi);
-                const double rx = mi(double(yx) - sp.X[0], g.nx, true);
-                const double ry = mi(double(yy) - sp.X[1], g.ny, true);
-                const double rz = mi(double(yz) - sp.X[2], g.nz, g.zper != 0);
-                link_terms<q, 6, NACC>(acc, 0.0, rx, ry, rz, r0);
+                link_int_terms<q>(acc, mi_i(int32_t(yx) - xr[0], int32_t(g.nx), true),
+                                  mi_i(int32_t(yy) - xr[1], int32_t(g.ny), true),
+                                  mi_i(int32_t(yz) - xr[2], int32_t(g.nz), g.zper != 0));
             }
         });
     }

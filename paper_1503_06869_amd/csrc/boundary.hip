@@ -5,12 +5,12 @@
 //                             and the population-dependent momentum-exchange
 //                             sums F0, M0 of their fiber links (Eq.
 //                             LBMhydrodynForce and the torque after it);
-//   blocks [np*bpf, 2*np*bpf) the population-free sums A, B, C of the same
-//                             links at the current poses (the part of the
-//                             exchange linear in the surface velocity).
+//   blocks [np*bpf, 2*np*bpf) the population-free part of the exchange (A,
+//                             B, C; linear in the surface velocity) of the
+//                             same links as exact integer sums at the
+//                             current poses (see abc_restore).
 // Both halves walk the same list segments (block (fiber p, part j)) and add
-// into disjoint slots of the fixed-point sums, so they run side by side; one
-// launch keeps them concurrent wherever the step's graph puts it.
+// into disjoint slots of the sums, so they run side by side.
 #include "lbm_sweep_dev.h"
 
 namespace lbm {
@@ -51,71 +51,15 @@ __device__ __forceinline__ void bnd_block(S *__restrict__ f, const Geo &g, const
 
 }  // namespace lbm
 
-// the particle-side arithmetic below follows the header's contraction-off
-// pragma, like the rest of the per-fiber code
+// integer index arithmetic of the particle side (shared with the list rebuild)
 #include "lbm_particle_dev.h"
 
 namespace lbm {
 
-// Terms 6..26 of the momentum exchange (A, B, C) of every link of a boundary
-// cell at the poses ps of the sweep, added to acc for links to fiber home and
-// with atomics for links to another fiber.  The neighbour coordinates and
-// lever arm are formed as in the sweep; the owners across all links are
-// loaded together first, the home pose is passed in.
-__device__ __forceinline__ void abc_links(uint32_t cell, uint32_t mask, const int32_t *pid, const PState *ps,
-                                          const double hX[3], long long *mea, const Geo &g, int home, double r0,
-                                          long long (&acc)[NABC])
-{
-    const uint32_t z = cell / g.nxy, rem = cell - z * g.nxy, y = rem / g.nx, x = rem - y * g.nx;
-    // far cell of link q (periodic x, y; z periodic or walled)
-    auto far = [&](auto qc, uint32_t &yx, uint32_t &yy, uint32_t &yz) {
-        constexpr int q = decltype(qc)::value;
-        yx = uint32_t(wrapc(int32_t(x) + CX[q], int32_t(g.nx)));
-        yy = uint32_t(wrapc(int32_t(y) + CY[q], int32_t(g.ny)));
-        const int32_t yzi = int32_t(z) + CZ[q];
-        yz = g.zper ? uint32_t(wrapc(yzi, int32_t(g.nz))) : uint32_t(yzi);
-    };
-    int32_t own[Q];
-    static_for<1, Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        uint32_t yx, yy, yz;
-        far(qc, yx, yy, yz);
-        own[q] = pid[((mask >> q) & 1u) ? (yz * g.ny + yy) * g.nx + yx : cell];
-    });
-    static_for<1, Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        if ((mask >> q) & 1u) {
-            uint32_t yx, yy, yz;
-            far(qc, yx, yy, yz);
-            const int o = own[q];
-            double sX[3];
-            if (o == home) {
-                for (int k = 0; k < 3; ++k) sX[k] = hX[k];
-            } else {
-                for (int k = 0; k < 3; ++k) sX[k] = ps[o].X[k];
-            }
-            const double rx = mi(double(yx) - sX[0], g.nx, true);
-            const double ry = mi(double(yy) - sX[1], g.ny, true);
-            const double rz = mi(double(yz) - sX[2], g.nz, g.zper != 0);
-            if (o == home) {
-                link_terms<q, 6, NACC>(acc, 0.0, rx, ry, rz, r0);
-            } else {
-                long long tmp[NABC];
-#pragma unroll
-                for (int k = 0; k < NABC; ++k) tmp[k] = 0;
-                link_terms<q, 6, NACC>(tmp, 0.0, rx, ry, rz, r0);
-#pragma unroll
-                for (int k = 0; k < NABC; ++k)
-                    atomicAdd(reinterpret_cast<unsigned long long *>(mea + size_t(o) * NACC + 6 + k),
-                              (unsigned long long)tmp[k]);
-            }
-        }
-    });
-}
-
-// A, B, C of the current list at the current poses: block (fiber p, part j)
-// of the fiber's list segment, as in the boundary update.
-__device__ __forceinline__ void abc_block(const BndData &b, const Geo &g, double r0, int blk)
+// The integer sums SA, SB, SC of every link of a list segment's part j at
+// the poses ps (links to fiber p into the block's sums, links to another
+// fiber with atomics into that fiber's): block (fiber p, part j).
+__device__ __forceinline__ void abc_block(const BndData &b, const Geo &g, int blk)
 {
     const int p = blk / b.bpf, j = blk % b.bpf;
     const uint32_t cnt = b.seg_cnt[p], cap = b.seg_cap[p];
@@ -123,9 +67,42 @@ __device__ __forceinline__ void abc_block(const BndData &b, const Geo &g, double
     long long acc[NABC];
 #pragma unroll
     for (int k = 0; k < NABC; ++k) acc[k] = 0;
-    const double hX[3] = {b.ps[p].X[0], b.ps[p].X[1], b.ps[p].X[2]};
-    for (uint32_t r = j * 256u + threadIdx.x; r < n; r += b.bpf * 256u)
-        abc_links(b.cell[off + r], b.mask[off + r], b.pid, b.ps, hX, b.mea, g, p, r0, acc);
+    int32_t hr[3];
+    fiber_ref(b.ps[p].X, hr);
+    for (uint32_t r = j * 256u + threadIdx.x; r < n; r += b.bpf * 256u) {
+        const uint32_t cell = b.cell[off + r], mask = b.mask[off + r];
+        const int32_t z = int32_t(cell / g.nxy), rem = int32_t(cell - uint32_t(z) * g.nxy);
+        const int32_t y = rem / int32_t(g.nx), x = rem - y * int32_t(g.nx);
+        int32_t own[Q];
+        fiber_links(b.pid, g, x, y, z, own);
+        static_for<1, Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            if ((mask >> q) & 1u) {
+                const int o = own[q];
+                int32_t rf[3] = {hr[0], hr[1], hr[2]};
+                if (o != p) fiber_ref(b.ps[o].X, rf);
+                const int32_t yx = wrapc(x + CX[q], int32_t(g.nx)), yy = wrapc(y + CY[q], int32_t(g.ny));
+                const int32_t yz = g.zper ? wrapc(z + CZ[q], int32_t(g.nz)) : z + CZ[q];
+                const int32_t sx = mi_i(yx - rf[0], int32_t(g.nx), true);
+                const int32_t sy = mi_i(yy - rf[1], int32_t(g.ny), true);
+                const int32_t sz = mi_i(yz - rf[2], int32_t(g.nz), g.zper != 0);
+                if (o == p) {
+                    link_int_terms<q>(acc, sx, sy, sz);
+                } else {
+                    // link to another fiber (fibers closer than the region margin)
+                    long long tmp[NABC];
+#pragma unroll
+                    for (int k = 0; k < NABC; ++k) tmp[k] = 0;
+                    link_int_terms<q>(tmp, sx, sy, sz);
+#pragma unroll
+                    for (int k = 0; k < NABC; ++k)
+                        if (tmp[k])
+                            atomicAdd(reinterpret_cast<unsigned long long *>(b.mea + size_t(o) * NACC + 6 + k),
+                                      (unsigned long long)tmp[k]);
+                }
+            }
+        });
+    }
     __shared__ long long red[4][NABC];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -152,43 +129,43 @@ __device__ __forceinline__ void abc_block(const BndData &b, const Geo &g, double
 // the x and/or y faces.
 template <typename S, bool ODD, bool STAB, bool XYW>
 __global__ __launch_bounds__(256) void k_boundary(S *__restrict__ f, Geo g, Phys<typename St<S>::R> ph,
-                                                  BndData b, double r0, const double *stab, double *part)
+                                                  BndData b, const double *stab, double *part)
 {
     const int nb = b.np * b.bpf;   // block-uniform split
     if (int(blockIdx.x) < nb) bnd_block<S, ODD, STAB, XYW>(f, g, ph, b, int(blockIdx.x), stab, part);
-    else abc_block(b, g, r0, int(blockIdx.x) - nb);
+    else abc_block(b, g, int(blockIdx.x) - nb);
 }
 
 template <typename S>
 static hipError_t boundary_t(bool odd, void *f, const Geo &g, const Phys<double> &ph, const BndData &b,
-                             double r0, hipStream_t st, const double *stab, double *part)
+                             hipStream_t st, const double *stab, double *part)
 {
     using R = typename St<S>::R;
     const Phys<R> p = cast_phys<R>(ph);
     const dim3 grid(uint32_t(2 * b.np * b.bpf)), bl(256);
     const int mode = (odd ? 1 : 0) | (stab ? 2 : 0) | ((g.xw || g.yw) ? 4 : 0);
     switch (mode) {
-    case 0: hipLaunchKernelGGL((k_boundary<S, false, false, false>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part); break;
-    case 1: hipLaunchKernelGGL((k_boundary<S, true, false, false>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part); break;
-    case 2: hipLaunchKernelGGL((k_boundary<S, false, true, false>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part); break;
-    case 3: hipLaunchKernelGGL((k_boundary<S, true, true, false>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part); break;
-    case 4: hipLaunchKernelGGL((k_boundary<S, false, false, true>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part); break;
-    case 5: hipLaunchKernelGGL((k_boundary<S, true, false, true>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part); break;
-    case 6: hipLaunchKernelGGL((k_boundary<S, false, true, true>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part); break;
-    default: hipLaunchKernelGGL((k_boundary<S, true, true, true>), grid, bl, 0, st, (S *)f, g, p, b, r0, stab, part); break;
+    case 0: hipLaunchKernelGGL((k_boundary<S, false, false, false>), grid, bl, 0, st, (S *)f, g, p, b, stab, part); break;
+    case 1: hipLaunchKernelGGL((k_boundary<S, true, false, false>), grid, bl, 0, st, (S *)f, g, p, b, stab, part); break;
+    case 2: hipLaunchKernelGGL((k_boundary<S, false, true, false>), grid, bl, 0, st, (S *)f, g, p, b, stab, part); break;
+    case 3: hipLaunchKernelGGL((k_boundary<S, true, true, false>), grid, bl, 0, st, (S *)f, g, p, b, stab, part); break;
+    case 4: hipLaunchKernelGGL((k_boundary<S, false, false, true>), grid, bl, 0, st, (S *)f, g, p, b, stab, part); break;
+    case 5: hipLaunchKernelGGL((k_boundary<S, true, false, true>), grid, bl, 0, st, (S *)f, g, p, b, stab, part); break;
+    case 6: hipLaunchKernelGGL((k_boundary<S, false, true, true>), grid, bl, 0, st, (S *)f, g, p, b, stab, part); break;
+    default: hipLaunchKernelGGL((k_boundary<S, true, true, true>), grid, bl, 0, st, (S *)f, g, p, b, stab, part); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_boundary(int sk, bool odd, void *f, const Geo &g, const Phys<double> &ph, const BndData &b,
-                           double r0, hipStream_t st, const double *stab, double *part)
+                           hipStream_t st, const double *stab, double *part)
 {
     if (b.np <= 0 || b.bpf <= 0) return hipSuccess;
     switch (sk) {
-    case S_F32: return boundary_t<float>(odd, f, g, ph, b, r0, st, stab, part);
-    case S_F16: return boundary_t<_Float16>(odd, f, g, ph, b, r0, st, stab, part);
-    case S_BF16: return boundary_t<bf16s>(odd, f, g, ph, b, r0, st, stab, part);
-    default: return boundary_t<double>(odd, f, g, ph, b, r0, st, stab, part);
+    case S_F32: return boundary_t<float>(odd, f, g, ph, b, st, stab, part);
+    case S_F16: return boundary_t<_Float16>(odd, f, g, ph, b, st, stab, part);
+    case S_BF16: return boundary_t<bf16s>(odd, f, g, ph, b, st, stab, part);
+    default: return boundary_t<double>(odd, f, g, ph, b, st, stab, part);
     }
 }
 

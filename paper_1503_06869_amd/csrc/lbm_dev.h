@@ -107,17 +107,20 @@ struct Box {               // cells lo[k] .. lo[k]+len[k]-1 (wrapped where perio
 };
 constexpr int NBR_CAP = 128;   // neighbours per fiber whose boxes may intersect
 
-// Per-fiber sums of the momentum exchange: F0[3] M0[3] A[6] (symmetric:
-// xx xy xz yy yz zz) B[9] C[6].  They are accumulated as int64 fixed point
-// (each link's FP64 term scaled by 2^FX_k and rounded), so that the sums are
-// exact and do not depend on the order in which links are added; FP64 is
-// restored once per step.  Scales leave ample range for fibers of
-// thousands of links: |F0| < 2^11, |M0| < 2^17, |A|,|B| < 2^23, |C| < 2^37.
+// Per-fiber sums of the momentum exchange: F0[3] M0[3], then the exact
+// integer sums SA[6] (symmetric: xx xy xz yy yz zz) SB[9] SC[6] from which
+// the matrices A, B, C of the part linear in the surface velocity are formed
+// (abc_restore).  F0 and M0 are accumulated as int64 fixed point (each
+// link's FP64 term scaled by 2^FX_k and rounded); SA, SB, SC are integers
+// to begin with.  Either way the sums are exact and do not depend on the
+// order in which links are added; FP64 is restored once per step.  Ranges:
+// |F0| < 2^11, |M0| < 2^17; |SC| stays below 2^53 for fibers of a million
+// links within 2^20 cells of their reference point.
 constexpr int NACC = 27;
-constexpr int NABC = NACC - 6;   // the population-free terms A, B, C
+constexpr int NABC = NACC - 6;   // the population-free sums SA, SB, SC
 __host__ __device__ constexpr int fx_shift(int k)
 {
-    return k < 3 ? 52 : (k < 6 ? 46 : (k < 21 ? 40 : 26));
+    return k < 3 ? 52 : (k < 6 ? 46 : 0);
 }
 
 // device-side counters and error flags
@@ -180,6 +183,7 @@ struct PartData {
     int64_t hist_cap;
     int32_t coupling;          // lbm_coupling
     double rho0;
+    double rho0_link;          // rho0 as the collision type holds it (k = 6 w rho0 of the link sums)
     const double *corr;        // [np][6] closure corrections dF, dM, or null
     DevCounters *ctr;
     uint32_t list_cap;
@@ -224,11 +228,10 @@ constexpr uint32_t STAB_SCAN_GRID = 1024;
 hipError_t launch_sweep(int sk, bool odd, void *f, const uint8_t *flags, const Geo &g, const Phys<double> &ph,
                         uint32_t sweep_grid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, const double *stab,
                         double *part);
-// boundary cells of the list (update, F0, M0) and the A, B, C sums of their
-// links, one launch (boundary.hip); r0: rho0 as the sweep's collision type
-// holds it (the link terms' k = 6 w rho0); stab and part as for the sweep
+// boundary cells of the list (update, F0, M0) and the integer A, B, C sums
+// of their links, one launch (boundary.hip); stab and part as for the sweep
 hipError_t launch_boundary(int sk, bool odd, void *f, const Geo &g, const Phys<double> &ph, const BndData &b,
-                           double r0, hipStream_t st, const double *stab, double *part);
+                           hipStream_t st, const double *stab, double *part);
 hipError_t launch_decode(int sk, bool swapped, const void *f, const uint8_t *flags,
                          const int32_t *pid, const PState *ps, const Geo &g, const Phys<double> &ph,
                          void *rho, void *u, double *fout, hipStream_t st);

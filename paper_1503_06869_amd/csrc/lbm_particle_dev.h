@@ -123,22 +123,27 @@ __device__ __forceinline__ bool boxes_meet(const Box &a, const Box &b, const Geo
 }
 
 // ------------------------------------------------------------------ per-plane rectangles
-// Within a box, plane z is crossed by the capsule of radius r + RECT_MARGIN
-// around the fiber axis segment only in an x/y rectangle; every cell that a
-// fiber can own, or border (fluid neighbours lie within sqrt(2) of owned
-// cell centres), is inside it.  Rectangles are in the unwrapped frame of
-// the box; for boxes narrower than the domain they are clipped to the box.
+// Within a box, plane z is crossed by the capsule of radius r + margin
+// around the fiber axis segment only in an x/y rectangle.  Every cell that a
+// fiber can own lies within r of the segment (REMAP_MARGIN leaves half a
+// cell for rounding); every cell that can border it (fluid neighbours lie
+// within sqrt(2) of owned cell centres) within r + sqrt(2) (NEAR_MARGIN);
+// RECT_MARGIN covers both with room to spare (the batched kernel, which does
+// both in one pass).  Rectangles are in the unwrapped frame of the box; for
+// boxes narrower than the domain they are clipped to the box.
 constexpr double RECT_MARGIN = 2.5;
+constexpr double REMAP_MARGIN = 0.5;
+constexpr double NEAR_MARGIN = 1.5;
 
 struct Rect {
     int32_t x0, x1, y0, y1;   // inclusive; empty when x0 > x1
 };
 
 __device__ __forceinline__ Rect plane_rect(const PState &s, const PConst &c, int32_t z, const Box &b,
-                                           const Geo &g)
+                                           const Geo &g, double margin = RECT_MARGIN)
 {
     Rect r{1, 0, 1, 0};
-    const double R = c.radius + RECT_MARGIN, hl = 0.5 * c.length;
+    const double R = c.radius + margin, hl = 0.5 * c.length;
     const double dz = mi_d(double(z) - s.X[2], g.nz, g.zper != 0);
     const double tz = s.t[2];
     double slo, shi;
@@ -505,6 +510,138 @@ __device__ __forceinline__ uint32_t fiber_mask(const int32_t *pid, const Geo &g,
         else if (zz < 0 || zz >= nz) continue;
         const int32_t xx = wrapc(x + CX[q], nx), yy = wrapc(y + CY[q], ny);
         if (pid[(uint32_t(zz) * g.ny + uint32_t(yy)) * g.nx + uint32_t(xx)] >= 0) mask |= 1u << q;
+    }
+    return mask;
+}
+
+// ------------------------------------------------------------------ population-free link sums
+// The part of Eq. LBMhydrodynForce (and the torque after it) that is linear
+// in the surface velocity u_s = V + W x r has the matrices
+//   A = sum k c c^T,  B = sum k c (r x c)^T,  C = sum k (r x c)(r x c)^T
+// over a fiber's links, k = 6 w_q rho0, r = y - X the lever arm of the solid
+// cell y.  With the reference point Xr = floor(X), s = y - Xr (integer,
+// minimum image) and delta = X - Xr, r = s - delta, so
+//   A = (rho0/6) SA,  B = (rho0/6) (SB - M),  C = (rho0/6) (SC - N - N^T + P)
+// with the integer sums SA = sum kappa c c^T, SB = sum kappa c (s x c)^T,
+// SC = sum kappa (s x c)(s x c)^T (kappa = 36 w_q: 2 for the six axis
+// links, 1 for the twelve diagonals) and
+//   M_ij = eps_jab delta_a SA_ib,  N_ij = eps_jab delta_a SB_bi,
+//   P_ij = eps_iab eps_jcd delta_a delta_c SA_bd.
+// The sums are exact, so they do not depend on the order of the links, and
+// are formed from the list once per step when it is built.
+
+// reference point of a fiber centre: the cell corner floor(X)
+__device__ __forceinline__ void fiber_ref(const double X[3], int32_t r[3])
+{
+    for (int k = 0; k < 3; ++k) r[k] = int32_t(floor(X[k]));
+}
+
+__device__ __forceinline__ int32_t mi_i(int32_t d, int32_t n, bool per)
+{
+    if (!per) return d;
+    if (2 * d > n) return d - n;
+    if (2 * d < -n) return d + n;
+    return d;
+}
+
+// integer terms of link q to the solid cell whose offset from its fiber's
+// reference point is (sx, sy, sz), added to acc[0 .. 20] = SA[6] SB[9] SC[6]
+template <int q>
+__device__ __forceinline__ void link_int_terms(long long *acc, int32_t sx, int32_t sy, int32_t sz)
+{
+    constexpr int32_t c0 = CX[q], c1 = CY[q], c2 = CZ[q];
+    constexpr int32_t kap = (c0 * c0 + c1 * c1 + c2 * c2) == 1 ? 2 : 1;
+    const int32_t sc0 = sy * c2 - sz * c1, sc1 = sz * c0 - sx * c2, sc2 = sx * c1 - sy * c0;
+    acc[0] += kap * c0 * c0;
+    acc[1] += kap * c0 * c1;
+    acc[2] += kap * c0 * c2;
+    acc[3] += kap * c1 * c1;
+    acc[4] += kap * c1 * c2;
+    acc[5] += kap * c2 * c2;
+    acc[6] += kap * c0 * sc0;
+    acc[7] += kap * c0 * sc1;
+    acc[8] += kap * c0 * sc2;
+    acc[9] += kap * c1 * sc0;
+    acc[10] += kap * c1 * sc1;
+    acc[11] += kap * c1 * sc2;
+    acc[12] += kap * c2 * sc0;
+    acc[13] += kap * c2 * sc1;
+    acc[14] += kap * c2 * sc2;
+    acc[15] += (long long)(kap * sc0) * sc0;
+    acc[16] += (long long)(kap * sc0) * sc1;
+    acc[17] += (long long)(kap * sc0) * sc2;
+    acc[18] += (long long)(kap * sc1) * sc1;
+    acc[19] += (long long)(kap * sc1) * sc2;
+    acc[20] += (long long)(kap * sc2) * sc2;
+}
+
+// Levi-Civita symbol
+__device__ __forceinline__ int32_t eps3(int i, int j, int k)
+{
+    return (i == j || j == k || i == k) ? 0 : (((j - i + 3) % 3) == 1 ? 1 : -1);
+}
+
+// A, B, C (packed as the momentum-exchange accumulators 6 .. 26: A[6]
+// symmetric, B[9], C[6] symmetric) from the integer sums S (exact values in
+// FP64) of a fiber centred at X, in place
+__device__ __forceinline__ void abc_restore(double *acc, const double X[3], double rho0)
+{
+    const int si[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+    double SA[3][3], SB[3][3], SC[3][3], d[3];
+    for (int k = 0; k < 6; ++k) {
+        SA[si[k][0]][si[k][1]] = SA[si[k][1]][si[k][0]] = acc[6 + k];
+        SC[si[k][0]][si[k][1]] = SC[si[k][1]][si[k][0]] = acc[21 + k];
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) SB[i][j] = acc[12 + 3 * i + j];
+    for (int k = 0; k < 3; ++k) d[k] = X[k] - floor(X[k]);
+    // (delta x c) components as linear maps of c: E[j][b] = eps_jab delta_a
+    double E[3][3];
+    for (int j = 0; j < 3; ++j)
+        for (int b = 0; b < 3; ++b) {
+            double e = 0.0;
+            for (int a = 0; a < 3; ++a) e += double(eps3(j, a, b)) * d[a];
+            E[j][b] = e;
+        }
+    const double k6 = rho0 / 6.0;
+    double B[3][3], C[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double m = 0.0, nn = 0.0, nt = 0.0;
+            for (int b = 0; b < 3; ++b) {
+                m += E[j][b] * SA[i][b];    // M_ij
+                nn += E[j][b] * SB[b][i];   // N_ij
+                nt += E[i][b] * SB[b][j];   // N_ji
+            }
+            double pp = 0.0;                // P_ij = E[i][b] E[j][e] SA_be
+            for (int b = 0; b < 3; ++b)
+                for (int e = 0; e < 3; ++e) pp += E[i][b] * E[j][e] * SA[b][e];
+            B[i][j] = k6 * (SB[i][j] - m);
+            C[i][j] = k6 * (((SC[i][j] - nn) - nt) + pp);
+        }
+    for (int k = 0; k < 6; ++k) {
+        acc[6 + k] = k6 * SA[si[k][0]][si[k][1]];
+        acc[21 + k] = C[si[k][0]][si[k][1]];
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) acc[12 + 3 * i + j] = B[i][j];
+}
+
+// fiber_mask with the owner of each linked cell: own[q] for the set bits
+__device__ __forceinline__ uint32_t fiber_links(const int32_t *pid, const Geo &g, int32_t x, int32_t y, int32_t z,
+                                                int32_t (&own)[Q])
+{
+    const int32_t nx = g.nx, ny = g.ny, nz = g.nz;
+    uint32_t mask = 0;
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+        own[q] = -1;
+        int32_t zz = z + CZ[q];
+        if (g.zper) zz = wrapc(zz, nz);
+        else if (zz < 0 || zz >= nz) continue;
+        const int32_t xx = wrapc(x + CX[q], nx), yy = wrapc(y + CY[q], ny);
+        own[q] = pid[(uint32_t(zz) * g.ny + uint32_t(yy)) * g.nx + uint32_t(xx)];
+        if (own[q] >= 0) mask |= 1u << q;
     }
     return mask;
 }

@@ -244,29 +244,24 @@ __device__ __forceinline__ long long fx(double v, int k) { return __double2ll_rn
 // split into the velocity-free part F0, M0 and the matrices of the part
 // linear in u_s = V + W x r: A = k c c^T, B = k c (r x c)^T, C = k (r x c)(r x c)^T,
 // k = 6 w_q rho0, so that F = F0 - A V - B W and M = M0 - B^T V - C W.
-// Terms K0 .. K1-1 of that list are added to acc[0 .. K1-K0-1]; terms 6 and
-// up do not depend on the populations.
-template <int q, int K0 = 0, int K1 = NACC>
+// This adds the link's F0, M0 terms to acc[0 .. 5]; A, B, C do not depend
+// on the populations and are summed as integers when the list is built
+// (link_int_terms).
+template <int q>
 __device__ __forceinline__ void link_terms(long long *acc, double ft, double rx, double ry, double rz,
                                            double r0)
 {
     const double m2 = 2.0 * (ft + wq(q) * r0);
     const double c0 = CX[q], c1 = CY[q], c2 = CZ[q];
     const double rc0 = ry * c2 - rz * c1, rc1 = rz * c0 - rx * c2, rc2 = rx * c1 - ry * c0;
-    const double k6 = 6.0 * wq(q) * r0;
-    const double t[NACC] = {m2 * c0, m2 * c1, m2 * c2, m2 * rc0, m2 * rc1, m2 * rc2,
-                            k6 * c0 * c0, k6 * c0 * c1, k6 * c0 * c2, k6 * c1 * c1, k6 * c1 * c2, k6 * c2 * c2,
-                            k6 * c0 * rc0, k6 * c0 * rc1, k6 * c0 * rc2,
-                            k6 * c1 * rc0, k6 * c1 * rc1, k6 * c1 * rc2,
-                            k6 * c2 * rc0, k6 * c2 * rc1, k6 * c2 * rc2,
-                            k6 * rc0 * rc0, k6 * rc0 * rc1, k6 * rc0 * rc2,
-                            k6 * rc1 * rc1, k6 * rc1 * rc2, k6 * rc2 * rc2};
+    const double t[6] = {m2 * c0, m2 * c1, m2 * c2, m2 * rc0, m2 * rc1, m2 * rc2};
 #pragma unroll
-    for (int k = K0; k < K1; ++k) acc[k - K0] += fx(t[k], k);
+    for (int k = 0; k < 6; ++k) acc[k] += fx(t[k], k);
 }
 
-// NK: momentum-exchange terms accumulated per link (NACC, or 6 for F0 and
-// M0 only when the population-free terms are summed elsewhere).
+// BND: a boundary cell of the list, whose fiber links add their F0, M0
+// terms to acc[0 .. 5] (links to fiber `home`) or directly to the sums of
+// another fiber.  NK: length of acc (6).
 // STAB: momentum stabilization with the accumulator sa (see StabAcc).
 // XYW: resting no-slip walls on the x and/or y faces (g.xw, g.yw): a link
 // leaving the lattice there bounces back (Eq. BBBC) into the cell's own slot
@@ -366,15 +361,15 @@ __device__ __forceinline__ void update_cell(S *__restrict__ f, const Geo &g,
             out -= R(6.0 * wq(q) * double(ph.rho0) * cu);
             if (!isfinite(double(fv[q]))) atomicOr(&b.ctr->err_unstable, 1u);
             if (p == home) {
-                link_terms<q, 0, NK>(acc, double(fv[q]), rx, ry, rz, double(ph.rho0));
+                link_terms<q>(acc, double(fv[q]), rx, ry, rz, double(ph.rho0));
             } else {
                 // link to another fiber (fibers closer than the region margin)
-                long long tmp[NK];
+                long long tmp[6];
 #pragma unroll
-                for (int k = 0; k < NK; ++k) tmp[k] = 0;
-                link_terms<q, 0, NK>(tmp, double(fv[q]), rx, ry, rz, double(ph.rho0));
+                for (int k = 0; k < 6; ++k) tmp[k] = 0;
+                link_terms<q>(tmp, double(fv[q]), rx, ry, rz, double(ph.rho0));
 #pragma unroll
-                for (int k = 0; k < NK; ++k)
+                for (int k = 0; k < 6; ++k)
                     atomicAdd(reinterpret_cast<unsigned long long *>(b.mea + size_t(p) * NACC + k),
                               (unsigned long long)tmp[k]);
             }

@@ -18,16 +18,18 @@ namespace lbm {
 #pragma clang fp contract(off)
 
 // Plane rectangle of fiber o's remap region: the current and new poses
-// (where cell owners can change), and with PREV also the previous pose (the
-// flags of the next step are written into the buffer that held those of the
-// previous step, so the flag rebuild covers every cell flagged then).
+// (where cell owners can change; margin for owned cells), and with PREV, for
+// the flag rebuild, also the previous pose (the flags of the next step are
+// written into the buffer that held those of the previous step, so the
+// rebuild covers every cell flagged then; margin for bordering cells).
 template <bool PREV>
 __device__ __forceinline__ Rect remap_rect(const PartData &pd, int o, int32_t z, const Geo &g)
 {
     const Box b = pd.box_remap[o];
     const PConst c = pd.pc[o];
-    const Rect r = rect_union(plane_rect(pd.ps_cur[o], c, z, b, g), plane_rect(pd.ps_next[o], c, z, b, g), g);
-    return PREV ? rect_union(r, plane_rect(pd.ps_prev[o], c, z, b, g), g) : r;
+    const double m = PREV ? NEAR_MARGIN : REMAP_MARGIN;
+    const Rect r = rect_union(plane_rect(pd.ps_cur[o], c, z, b, g, m), plane_rect(pd.ps_next[o], c, z, b, g, m), g);
+    return PREV ? rect_union(r, plane_rect(pd.ps_prev[o], c, z, b, g, m), g) : r;
 }
 
 // ------------------------------------------------------------------ boxes of the remap
@@ -99,6 +101,7 @@ __global__ __launch_bounds__(256) void k_rigid(PartData pd, Geo g)
         for (int k = 0; k < NACC; ++k) ac[k] = tot[p * NACC + k];
         const PConst c = pd.pc[p];
         const PState s = pd.ps_cur[p];
+        abc_restore(ac, s.X, pd.rho0_link);
         const double *row = nullptr;
         if (c.traj_off >= 0 && pd.traj_pos[p] < c.traj_n) {
             row = pd.traj + (c.traj_off + pd.traj_pos[p]) * 13;
