@@ -33,6 +33,7 @@ SOURCES = {
     "check.hip": [],
     "features.hip": [],
     "mlp.hip": [],
+    "sbf.hip": [],
 }
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -224,3 +224,48 @@ def random_populations(seed, shape, weights, amplitude=1e-3, velocity=0.02):
     f = w[:, None, None, None] * (1.0 + 3.0 * cu)
     f += amplitude * w[:, None, None, None] * g.standard_normal(f.shape)
     return f
+
+
+# ------------------------------------------------------------------ slender-body workloads
+@dataclass
+class SbfScenario:
+    name: str
+    length: float
+    eps: float
+    X: np.ndarray          # [m][3] centres
+    p: np.ndarray          # [m][3] unit directions
+    F: np.ndarray          # [m][3] external forces
+    M: np.ndarray          # [m][3] external torques
+    mu: float = 1.0
+
+
+def sbf_cloud(seed=0, m=1024, length=48.0, eps=1.0 / 12.0, spacing=2.0, force=(0.0, 0.0, 1.0)):
+    """m fibers of length L (in units of the fiber radius times 1/eps, the
+    paper's r = 4 dx fibers of 1/eps = 12 by default) in a cubic cloud of
+    mean volume (spacing L)^3 per fiber, centres uniform with a minimum
+    centre distance of L/4, orientations uniform on the sphere, the same
+    force (gravity) on every fiber, no torque: a sedimenting suspension in
+    free space."""
+    g = rng(seed)
+    side = spacing * length * m ** (1.0 / 3.0)
+    X = np.zeros((m, 3))
+    k = 0
+    while k < m:
+        c = g.uniform(0.0, side, 3)
+        if k == 0 or np.min(np.linalg.norm(X[:k] - c, axis=1)) >= 0.25 * length:
+            X[k] = c
+            k += 1
+    p = np.array([axis_uniform_on_sphere(g) for _ in range(m)])
+    F = np.tile(np.asarray(force, dtype=np.float64), (m, 1))
+    return SbfScenario("sbf_cloud_%d" % m, length, eps, X, p, F, np.zeros((m, 3)))
+
+
+def sbf_pair(dist=15.1, aspect=12.0, radius=4.0, tilt=0.0, force=1.0):
+    """The paper's tumbling start for the slender-body model: two fibers of
+    radius r and aspect ratio 1/eps = L/r aligned with gravity (z), centres
+    dist apart along x; tilt rotates both axes about y (opposite senses)."""
+    length = radius * aspect
+    X = np.array([[-0.5 * dist, 0.0, 0.0], [0.5 * dist, 0.0, 0.0]])
+    p = np.array([[np.sin(tilt), 0.0, np.cos(tilt)], [-np.sin(tilt), 0.0, np.cos(tilt)]])
+    F = np.array([[0.0, 0.0, force], [0.0, 0.0, force]])
+    return SbfScenario("sbf_pair", length, 1.0 / aspect, X, p, F, np.zeros((2, 3)))

@@ -20,7 +20,7 @@ def declared_functions(header=None):
             continue
         src = open(os.path.join(inc, h)).read()
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-        names |= set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", src))
+        names |= set(re.findall(r"\b((?:lbm|sbf)_[a-z_]+)\s*\(", src))
     return sorted(names)
 
 
@@ -44,6 +44,8 @@ def test_library_exports_every_declared_symbol(libso):
     assert sorted(lbm.EXPORTED) == declared_functions("lbm.h")
     assert sorted(lbm.EXPORTED_BATCH) == declared_functions("lbm_batch.h")
     assert sorted(lbm.EXPORTED_MLP) == declared_functions("lbm_mlp.h")
+    from paper_1503_06869_amd import sbf
+    assert sorted(sbf.EXPORTED_SBF) == declared_functions("sbf.h")
 
 
 def test_lattice_table_needs_no_gpu():
@@ -129,3 +131,21 @@ def test_checkpoint_load_rejects_missing_and_foreign_files(libso, tmp_path):
     assert L.lbm_load(str(bad).encode(), None, C.byref(h)) == lbm.LBM_E_ARG
     assert not h.value
 
+
+
+def test_sbf_struct_layout_and_argument_errors(libso):
+    """sbf_params matches the header (5 int32 + 1 reserved, 4 doubles, a
+    pointer); invalid parameters are rejected before any device call."""
+    from paper_1503_06869_amd import sbf
+    assert C.sizeof(sbf.sbf_params) == 6 * 4 + 4 * 8 + 8
+    L = sbf._lib()
+    p = sbf.sbf_params()
+    assert L.sbf_params_default(C.byref(p)) == lbm.LBM_OK
+    assert (p.nmodes, p.nq, p.gmres_restart) == (5, 16, 30)
+    h = C.c_void_p()
+    for field, value in (("nmodes", 9), ("nq", 0), ("gmres_restart", 64), ("eps", 0.5), ("length", 0.0)):
+        bad = sbf.sbf_params()
+        L.sbf_params_default(C.byref(bad))
+        setattr(bad, field, value)
+        assert L.sbf_create(C.byref(bad), C.byref(h)) == lbm.LBM_E_ARG, field
+    assert L.sbf_solve(None) == lbm.LBM_E_ARG
