@@ -194,6 +194,48 @@ def time_learned(steps, warmup, torch):
     return out
 
 
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def time_sbf(torch, m=1024, steps=10, warmup=2):
+    """Slender-body form (Sec. 3): a sedimenting cloud of m fibers (1/eps =
+    12, N = 5 Legendre modes, 48 quadrature points per fiber, the paper's
+    parameters) in free space; a step is the moments of every fiber pair,
+    GMRES to 1e-10, the velocities and the Adams-Bashforth-2 update.
+    Roofline of its two kernels: the moments (FP64 ALU: per pair
+    Q^2 (33 + 15 (N + 1)) + 21 Q (N + 1)^2 flops over m (m - 1)/2 pairs) and
+    the product with the moment matrix (HBM: D^2 x 8 bytes, D = 3 m (N + 1))."""
+    from paper_1503_06869_amd import scenarios, sbf
+    N, nq = 5, 16
+    sc = scenarios.sbf_cloud(seed=0, m=m)
+    stream = torch.cuda.Stream()
+    g = sbf.SBF(m, sc.length, sc.eps, nmodes=N, nq=nq, gmres_tol=1e-10, stream=stream.cuda_stream)
+    g.set_fibers(sc.X, sc.p, sc.F, sc.M)
+    dt = 10.0    # relative displacements of a fraction of a fiber radius per step (speeds ~1e-2)
+    g.step(warmup, dt)
+    g.enable_timing(True)
+    t = time.perf_counter()
+    g.step(steps, dt)
+    wall = (time.perf_counter() - t) / steps
+    tm, nm, tg, ng = g.timing()
+    st = g.stats()
+    X, _ = g.state()
+    g.close()
+    Q, NP1 = 3 * nq, N + 1
+    flops = (m * (m - 1) / 2) * (Q * Q * (33 + 15 * NP1) + 21 * Q * NP1 * NP1)
+    D = 3 * m * NP1
+    th_ms, gv_ms = tm / nm, tg / ng
+    return {"fibers": m, "modes": N, "quadrature_points": Q, "ms_per_step": round(wall * 1e3, 3),
+            "steps_per_s": round(1.0 / wall, 1), "gmres_iterations_last_solve": st["iterations"],
+            "finite": bool(np.isfinite(X).all()),
+            "moments": {"bound": "alu", "ms": round(th_ms, 4), "achieved_tflops": round(flops / (th_ms * 1e-3) / 1e12, 2),
+                        "peak_tflops": FP64_VECTOR_PEAK_TFLOPS,
+                        "frac": round(flops / (th_ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS, 4)},
+            "gemv": {"bound": "hbm", "ms": round(gv_ms, 4), "launches_per_step": round(ng / steps, 1),
+                     "achieved_gbs": round(D * D * 8 / (gv_ms * 1e-3) / 1e9, 1),
+                     "frac": round(D * D * 8 / (gv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+
+
 def sweep_sources_sha1():
     import hashlib
     h = hashlib.sha1()
@@ -325,6 +367,8 @@ def main():
                     help="steps of the batched form's timed launch (0: skip it)")
     ap.add_argument("--learned-steps", type=int, default=500,
                     help="steps of the learned-coarse form (0: skip it)")
+    ap.add_argument("--sbf-fibers", type=int, default=1024,
+                    help="fibers of the slender-body form (0: skip it)")
     ap.add_argument("--no-error-checks", dest="error_checks", action="store_false",
                     help="skip the storage forms' errors against the FP64 oracle")
     ap.add_argument("--copy-calib", action="store_true",
@@ -383,6 +427,8 @@ def main():
         forms["batched_512_cases"] = time_batched(a.batched_steps, 10, torch)
     if a.learned_steps > 0:
         forms["learned_coarse_128cube_200fibers"] = time_learned(a.learned_steps, 20, torch)
+    if a.sbf_fibers > 0:
+        forms["slender_body_cloud"] = time_sbf(torch, m=a.sbf_fibers)
     out = {
         "metric": METRIC,
         "value": round(main_form["mlups"], 1),

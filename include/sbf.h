@@ -43,9 +43,9 @@ typedef struct sbf_ctx sbf_ctx;
 
 typedef struct {
     int32_t max_fibers;     /* capacity M (>= 1) */
-    int32_t nmodes;         /* N, Legendre modes of the force expansion (1..12) */
+    int32_t nmodes;         /* N, Legendre modes of the force expansion (1..8) */
     int32_t nq;             /* sub-intervals of the Gauss rule per fiber (1..64) */
-    int32_t gmres_restart;  /* Krylov dimension before a restart (1..64) */
+    int32_t gmres_restart;  /* Krylov dimension before a restart (1..63) */
     int32_t gmres_maxit;    /* iterations per solve, over all restarts (>= 1) */
     int32_t reserved;       /* 0 */
     double length;          /* L (> 0) */
@@ -61,7 +61,9 @@ lbm_status sbf_params_default(sbf_params *p);
 
 /* Allocate a context for up to max_fibers fibers: the moment matrix of
  * (3 M (N + 1))^2 doubles and the GMRES basis.  LBM_E_ARG for invalid
- * parameters, LBM_E_NOMEM when the device memory does not suffice. */
+ * parameters (including nq and N whose moment workgroup would need more
+ * than 64 KiB of LDS: 8 (N + 1)(21 nq + 7 (N + 1)) bytes), LBM_E_NOMEM
+ * when the device memory does not suffice. */
 lbm_status sbf_create(const sbf_params *p, sbf_ctx **out);
 lbm_status sbf_destroy(sbf_ctx *ctx);
 const char *sbf_last_error(const sbf_ctx *ctx);
@@ -96,6 +98,14 @@ lbm_status sbf_get_state(sbf_ctx *ctx, double *X, double *p);
 
 /* Iterations and relative residual of the last solve; steps done. */
 lbm_status sbf_get_stats(sbf_ctx *ctx, int32_t *iterations, double *residual, int64_t *steps);
+
+/* Device-event timing of the following solves (on != 0; 0 stops it):
+ * sbf_get_timing returns the totals since enabling -- milliseconds and
+ * launches of the moment kernel and of the products with the moment matrix
+ * (any pointer may be NULL). */
+lbm_status sbf_enable_timing(sbf_ctx *ctx, int32_t on);
+lbm_status sbf_get_timing(sbf_ctx *ctx, double *moments_ms, int64_t *moments_launches, double *gemv_ms,
+                          int64_t *gemv_launches);
 
 #ifdef __cplusplus
 }

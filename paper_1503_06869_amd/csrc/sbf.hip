@@ -438,6 +438,13 @@ struct sbf_ctx {
     double *nrm = nullptr, *res = nullptr;  // scalars
     double *V = nullptr, *Pd = nullptr, *Vp = nullptr, *Pp = nullptr;
     bool first = true, solved = false;
+    // event timing: pairs recorded around the moment kernel and each GEMV
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+    std::vector<int> ev_kind;    // 0 moments, 1 GEMV
+    double t_theta = 0.0, t_gemv = 0.0;
+    int64_t n_theta = 0, n_gemv = 0;
     int iters = 0;
     double relres = 0.0;
     int64_t steps = 0;
@@ -483,10 +490,49 @@ static hipError_t launch_theta(sbf_ctx *c)
     }
 }
 
+// an event pair around the next launch when timing (kind 0: moments, 1: GEMV)
+static hipError_t mark(sbf_ctx *c, int kind, bool begin)
+{
+    if (!c->timing) return hipSuccess;
+    if (begin) {
+        while (c->ev.size() < c->ev_used + 2) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            c->ev.push_back(e);
+        }
+        c->ev_kind.resize(c->ev.size() / 2 + 1);
+        c->ev_kind[c->ev_used / 2] = kind;
+    }
+    return hipEventRecord(c->ev[c->ev_used++], c->st);
+}
+
+// after a synchronisation: add the recorded pairs to the totals
+static hipError_t collect(sbf_ctx *c)
+{
+    for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+        float ms = 0.0f;
+        hipError_t r = hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]);
+        if (r != hipSuccess) return r;
+        if (c->ev_kind[i / 2] == 0) {
+            c->t_theta += ms;
+            c->n_theta += 1;
+        } else {
+            c->t_gemv += ms;
+            c->n_gemv += 1;
+        }
+    }
+    c->ev_used = 0;
+    return hipSuccess;
+}
+
 static hipError_t gemv(sbf_ctx *c, const double *xin, double *yout)
 {
+    hipError_t e = mark(c, 1, true);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gemv, dim3(unsigned((c->c.D + 3) / 4)), dim3(256), 0, c->st, c->W, xin, yout, c->c.D);
-    return hipGetLastError();
+    e = hipGetLastError();
+    return e != hipSuccess ? e : mark(c, 1, false);
 }
 
 // y = A x (system operator)
@@ -518,6 +564,7 @@ static lbm_status read_scalar(sbf_ctx *c, const double *dptr, double *out)
 {
     SCHK(c, hipMemcpyAsync(out, dptr, sizeof(double), hipMemcpyDeviceToHost, c->st));
     SCHK(c, hipStreamSynchronize(c->st));
+    SCHK(c, collect(c));
     return LBM_OK;
 }
 
@@ -527,7 +574,9 @@ static lbm_status do_solve(sbf_ctx *c)
 {
     const int D = c->c.D;
     const unsigned gd = nblk(size_t(D));
+    SCHK(c, mark(c, 0, true));
     SCHK(c, launch_theta(c));
+    SCHK(c, mark(c, 0, false));
     hipLaunchKernelGGL(k_known, dim3(gd), dim3(256), 0, c->st, c->kn, c->F, c->c);
     SCHK(c, hipGetLastError());
     SCHK(c, gemv(c, c->kn, c->z));
@@ -621,6 +670,8 @@ static hipError_t salloc(T **ptr, size_t n)
 
 static void release(sbf_ctx *c)
 {
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    c->ev.clear();
     double **bufs[] = {&c->X, &c->pd, &c->F, &c->Mt, &c->sq, &c->wq, &c->leg, &c->W, &c->x, &c->b, &c->r,
                        &c->w, &c->y, &c->kn, &c->z, &c->t, &c->u, &c->Vb, &c->H, &c->cs, &c->sn, &c->g, &c->h1, &c->h2,
                        &c->ys, &c->nrm, &c->res, &c->V, &c->Pd, &c->Vp, &c->Pp};
@@ -658,6 +709,8 @@ lbm_status sbf_create(const sbf_params *p, sbf_ctx **out)
         return LBM_E_ARG;
     if (!(p->length > 0.0) || !(p->eps > 0.0 && p->eps < 0.5) || !(p->mu > 0.0) || !(p->gmres_tol > 0.0))
         return LBM_E_ARG;
+    const size_t lds = size_t(p->nmodes + 1) * 7 * (3 * size_t(p->nq) + size_t(p->nmodes + 1)) * sizeof(double);
+    if (lds > 65536) return LBM_E_ARG;
     const double dmax = 3.0 * p->max_fibers * (p->nmodes + 1);
     if (dmax * dmax > 4.0e10) return LBM_E_ARG;   // the moment matrix would exceed 320 GB
     sbf_ctx *c = new (std::nothrow) sbf_ctx;
@@ -848,6 +901,32 @@ lbm_status sbf_get_stats(sbf_ctx *c, int32_t *iterations, double *residual, int6
     if (iterations) *iterations = c->iters;
     if (residual) *residual = c->relres;
     if (steps) *steps = c->steps;
+    return LBM_OK;
+}
+
+lbm_status sbf_enable_timing(sbf_ctx *c, int32_t on)
+{
+    if (!c) return LBM_E_ARG;
+    SCHK(c, hipStreamSynchronize(c->st));
+    SCHK(c, collect(c));
+    c->timing = on != 0;
+    if (c->timing) {
+        c->t_theta = c->t_gemv = 0.0;
+        c->n_theta = c->n_gemv = 0;
+    }
+    return LBM_OK;
+}
+
+lbm_status sbf_get_timing(sbf_ctx *c, double *moments_ms, int64_t *moments_launches, double *gemv_ms,
+                          int64_t *gemv_launches)
+{
+    if (!c) return LBM_E_ARG;
+    SCHK(c, hipStreamSynchronize(c->st));
+    SCHK(c, collect(c));
+    if (moments_ms) *moments_ms = c->t_theta;
+    if (moments_launches) *moments_launches = c->n_theta;
+    if (gemv_ms) *gemv_ms = c->t_gemv;
+    if (gemv_launches) *gemv_launches = c->n_gemv;
     return LBM_OK;
 }
 

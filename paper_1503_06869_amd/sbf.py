@@ -10,7 +10,7 @@ from . import lbm
 EXPORTED_SBF = [
     "sbf_params_default", "sbf_create", "sbf_destroy", "sbf_last_error", "sbf_set_fibers",
     "sbf_solve", "sbf_get_velocities", "sbf_get_coefficients", "sbf_step", "sbf_get_state",
-    "sbf_get_stats",
+    "sbf_get_stats", "sbf_enable_timing", "sbf_get_timing",
 ]
 
 
@@ -43,6 +43,8 @@ def _lib():
             "sbf_get_state": ([vp, _dp, _dp], C.c_int),
             "sbf_get_stats": ([vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_int64)],
                               C.c_int),
+            "sbf_enable_timing": ([vp, C.c_int32], C.c_int),
+            "sbf_get_timing": ([vp, _dp, C.POINTER(C.c_int64), _dp, C.POINTER(C.c_int64)], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -125,3 +127,13 @@ class SBF:
         it, res, st = C.c_int32(), C.c_double(), C.c_int64()
         self._chk(_lib().sbf_get_stats(self._h, C.byref(it), C.byref(res), C.byref(st)))
         return {"iterations": it.value, "residual": res.value, "steps": st.value}
+
+    def enable_timing(self, on=True):
+        self._chk(_lib().sbf_enable_timing(self._h, int(bool(on))))
+
+    def timing(self):
+        """(moment kernel ms, launches, moment-matrix GEMV ms, launches) since enabling."""
+        tm, tg = C.c_double(), C.c_double()
+        nm, ng = C.c_int64(), C.c_int64()
+        self._chk(_lib().sbf_get_timing(self._h, C.byref(tm), C.byref(nm), C.byref(tg), C.byref(ng)))
+        return tm.value, nm.value, tg.value, ng.value

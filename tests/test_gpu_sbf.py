@@ -107,11 +107,15 @@ def test_cloud_beyond_one_restart_cycle():
     _, V_o, W_o = ref.solve(sc.X, sc.p, sc.F, sc.M)
     g = _gpu_sbf(m, L, eps, nmodes=4, nq=8, gmres_restart=8, gmres_maxit=400)
     g.set_fibers(sc.X, sc.p, sc.F, sc.M)
+    g.enable_timing(True)
     g.solve()
     V, W = g.velocities()
     st = g.stats()
+    tm, nm, tg, ng = g.timing()
     g.close()
-    print("cloud of %d: %d iterations, residual %.2e" % (m, st["iterations"], st["residual"]), flush=True)
+    print("cloud of %d: %d iterations, residual %.2e; moments %.3f ms, %d GEMVs %.3f ms" % (
+        m, st["iterations"], st["residual"], tm, ng, tg), flush=True)
     assert st["iterations"] > 8
+    assert nm == 1 and tm > 0.0 and ng >= st["iterations"] and tg > 0.0
     assert np.abs(V - V_o).max() < 1e-10 * np.abs(V_o).max()
     assert np.abs(W - W_o).max() < 1e-10 * np.abs(W_o).max()
