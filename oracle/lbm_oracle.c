@@ -41,6 +41,14 @@ static int opposite(int q)
     return -1;
 }
 
+/* the direction with velocity e, found by search */
+static int direction_of(const int e[3])
+{
+    for (int p = 0; p < Q; ++p)
+        if (CV[p][0] == e[0] && CV[p][1] == e[1] && CV[p][2] == e[2]) return p;
+    return -1;
+}
+
 void or_lattice(int32_t *c, double *w, int32_t *opp)
 {
     for (int q = 0; q < Q; ++q) {
@@ -768,16 +776,30 @@ static void one_step(or_sim *s)
                     double ft = *slot(s->ft, s, q, c);
                     int yx = wrapi(x + CV[q][0], nx), yy = wrapi(y + CV[q][1], ny);
                     int yz = z + CV[q][2];
-                    if (!p->z_periodic && (yz < 0 || yz >= nz)) {
+                    /* walls the link crosses */
+                    int wx = p->x_walls && (x + CV[q][0] < 0 || x + CV[q][0] >= nx);
+                    int wy = p->y_walls && (y + CV[q][1] < 0 || y + CV[q][1] >= ny);
+                    int wz = !p->z_periodic && (yz < 0 || yz >= nz);
+                    if (wz && !p->z_free_slip) {
                         /* moving wall, half-way: bottom -U, top +U along x */
                         double uw = (yz < 0) ? -p->wall_u : p->wall_u;
                         *slot(s->fb, s, qb, c) = ft - 6.0 * w * rho0 * (CV[q][0] * uw);
                         continue;
                     }
-                    if ((p->x_walls && (x + CV[q][0] < 0 || x + CV[q][0] >= nx)) ||
-                        (p->y_walls && (y + CV[q][1] < 0 || y + CV[q][1] >= ny))) {
+                    if ((wx && p->x_walls == 1) || (wy && p->y_walls == 1)) {
                         /* resting no-slip wall in x or y, half-way (Eq. BBBC) */
                         *slot(s->fb, s, qb, c) = ft;
+                        continue;
+                    }
+                    if (wx || wy || wz) {
+                        /* free-slip walls only (Eq. FreeSlipBC): the normal components
+                           of the crossed walls reverse, the population lands on the
+                           neighbour along the remaining components */
+                        int e[3] = {wx ? -CV[q][0] : CV[q][0], wy ? -CV[q][1] : CV[q][1],
+                                    wz ? -CV[q][2] : CV[q][2]};
+                        int qr = direction_of(e);
+                        int dx = wx ? x : yx, dy = wy ? y : yy, dz = wz ? z : wrapi(yz, nz);
+                        *slot(s->fb, s, qr, cidx(s, dx, dy, dz)) = ft;
                         continue;
                     }
                     yz = wrapi(yz, nz);

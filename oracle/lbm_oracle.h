@@ -57,9 +57,12 @@ typedef struct {
     double contact_k;     /* > 0: short-range repulsion between fibers (contact model in place
                              of the paper's frictional collision handling); 0: off */
     double contact_range; /* surface gap below which the repulsion acts */
-    int x_walls;          /* 1: stationary no-slip walls half-way below x = 0 and above
-                             x = nx - 1 (Eq. BBBC); 0: periodic in x */
+    int x_walls;          /* walls half-way below x = 0 and above x = nx - 1 instead of
+                             periodicity in x: 1 stationary no-slip (Eq. BBBC), 2 free-slip
+                             (specular reflection, Eq. FreeSlipBC); 0: periodic in x */
     int y_walls;          /* the same for y */
+    int z_free_slip;      /* 1 (with z_periodic = 0 and wall_u = 0): the z walls reflect
+                             specularly instead of bouncing back */
 } or_params;
 
 /* ---- building blocks (exposed so the tests can pin them one by one) ---- */

@@ -26,7 +26,7 @@ class Params(C.Structure):
                 ("wall_u", C.c_double), ("g", C.c_double * 3), ("init_couette", C.c_int),
                 ("coupling", C.c_int), ("stabilize", C.c_int),
                 ("contact_k", C.c_double), ("contact_range", C.c_double),
-                ("x_walls", C.c_int), ("y_walls", C.c_int)]
+                ("x_walls", C.c_int), ("y_walls", C.c_int), ("z_free_slip", C.c_int)]
 
 
 def lib():
@@ -232,16 +232,27 @@ def contact_pair(tp, hp, rp, dpq, tq, hq, rq, k, rng):
     return (gap, *out)
 
 
+WALL_KINDS = {"periodic": 0, "no-slip": 1, "free-slip": 2}
+
+
+def wall_kind(v):
+    """x/y wall argument: False (periodic), True or "no-slip", "free-slip"."""
+    if isinstance(v, str):
+        return WALL_KINDS[v]
+    return 1 if v else 0
+
+
 class Sim:
     """One coupled simulation held by the oracle."""
 
     def __init__(self, nx, ny, nz, tau=0.8, magic=3.0 / 16.0, wall_u=0.0, rho0=1.0,
                  z_periodic=False, srt=False, g=(0.0, 0.0, 0.0), init_couette=False,
                  coupling="implicit", stabilize=False, contact_k=0.0, contact_range=1.0,
-                 x_walls=False, y_walls=False):
+                 x_walls=False, y_walls=False, z_free_slip=False):
         p = Params(nx, ny, nz, int(z_periodic), int(srt), tau, magic, rho0, wall_u,
                    (C.c_double * 3)(*g), int(init_couette), COUPLING[coupling], int(stabilize),
-                   float(contact_k), float(contact_range), int(x_walls), int(y_walls))
+                   float(contact_k), float(contact_range), wall_kind(x_walls), wall_kind(y_walls),
+                   int(bool(z_free_slip)))
         self.shape = (nx, ny, nz)
         self.ncell = nx * ny * nz
         self._h = lib().or_create(C.byref(p))
