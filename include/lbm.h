@@ -97,7 +97,8 @@ typedef struct {
     int32_t sweep_grid;        /* workgroups of the bulk sweep (grid-stride); 0 = automatic */
     int32_t q_pad;             /* extra elements between direction arrays; -1 = automatic */
     int32_t stabilize;         /* 1: momentum stabilization (see lbm_get_mean_velocity); 0: off */
-    int32_t reserved;          /* 0 */
+    int32_t z_free_slip;       /* 1: the z walls (z_periodic = 0, wall_u = 0) are free-slip
+                                  (specular reflection, Eq. FreeSlipBC) instead of no-slip; 0 */
     /* Contact between fibers (0: off).  The paper's rigid-body engine resolves
      * frictional collisions of the particles (Sec. 4.4); this library applies
      * a short-range repulsion instead: each fiber is the segment of its axis
@@ -109,12 +110,16 @@ typedef struct {
      * units).  With contacts at most 248 fibers per context. */
     double contact_stiffness;
     double contact_range;
-    /* 1: resting no-slip walls half-way outside the x faces (below x = 0 and
-     * above x = nx - 1; bounce-back of Eq. BBBC) instead of periodicity in
-     * x; likewise y.  With z walls (z_periodic = 0, wall_u = 0) this closes
-     * the box on all six faces.  Fibers must stay more than one cell from
-     * these walls (LBM_E_GEOM at lbm_add_fiber; LBM_E_STATE at the next sync
-     * if one reaches a wall during the run). */
+    /* Walls half-way outside the x faces (below x = 0 and above x = nx - 1)
+     * instead of periodicity in x: 1 resting no-slip (bounce-back, Eq.
+     * BBBC), 2 free-slip (specular reflection, Eq. FreeSlipBC: a population
+     * leaving through the wall returns with its normal component reversed,
+     * on the neighbour along the wall); 0 periodic.  Likewise y.  With z
+     * walls this closes the box on all six faces (the paper's sedimentation
+     * box: free-slip everywhere).  A link that crosses walls of both kinds
+     * (an edge) bounces back.  Fibers must stay more than one cell from
+     * these walls and from free-slip z walls (LBM_E_GEOM at lbm_add_fiber;
+     * LBM_E_STATE at the next sync if one reaches a wall during the run). */
     int32_t x_walls;
     int32_t y_walls;
 } lbm_params;

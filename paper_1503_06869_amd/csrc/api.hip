@@ -512,7 +512,8 @@ lbm_status lbm_create(const lbm_params *p, lbm_ctx **out)
     if (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 20) return LBM_E_ARG;
     if (p->coupling < LBM_COUPLING_IMPLICIT || p->coupling > LBM_COUPLING_IMPLICIT_PLAIN) return LBM_E_ARG;
     if (p->stabilize != 0 && p->stabilize != 1) return LBM_E_ARG;
-    if ((p->x_walls != 0 && p->x_walls != 1) || (p->y_walls != 0 && p->y_walls != 1)) return LBM_E_ARG;
+    if (p->x_walls < 0 || p->x_walls > 2 || p->y_walls < 0 || p->y_walls > 2) return LBM_E_ARG;
+    if (p->z_free_slip != 0 && (p->z_free_slip != 1 || p->z_periodic || p->wall_u != 0.0)) return LBM_E_ARG;
     if (!(p->contact_stiffness >= 0.0) || !std::isfinite(p->contact_stiffness)) return LBM_E_ARG;
     if (p->contact_stiffness > 0.0 && !(p->contact_range > 0.0 && std::isfinite(p->contact_range))) return LBM_E_ARG;
     // changed-cell entries keep a flag in bit 31
@@ -565,8 +566,9 @@ lbm_status lbm_create(const lbm_params *p, lbm_ctx **out)
     g.dnx = make_fastdiv(g.nx);
     g.dnxy = make_fastdiv(g.nxy);
     g.zper = p->z_periodic ? 1 : 0;
-    g.xw = p->x_walls ? 1 : 0;
-    g.yw = p->y_walls ? 1 : 0;
+    g.xw = p->x_walls;
+    g.yw = p->y_walls;
+    g.zs = p->z_free_slip;
     Phys<double> &ph = c->ph;
     ph.rho0 = p->rho0;
     ph.omega_e = 1.0 / p->tau;
@@ -1274,7 +1276,8 @@ lbm_status lbm_set_closure(lbm_ctx *c, lbm_mlp *m)
         c->closure = nullptr;
         return LBM_OK;
     }
-    if (c->g.xw || c->g.yw) return fail(c, LBM_E_STATE, "the closure's features assume periodic x and y");
+    if (c->g.xw || c->g.yw || c->g.zs)
+        return fail(c, LBM_E_STATE, "the closure's features assume periodic x and y and no free-slip walls");
     if (c->p.z_periodic || c->p.wall_u == 0.0)
         return fail(c, LBM_E_ARG, "the closure needs a shear cell (moving walls, U != 0)");
     if (c->np == 0) return fail(c, LBM_E_STATE, "add the fibers before attaching the closure");

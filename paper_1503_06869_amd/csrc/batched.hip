@@ -750,7 +750,7 @@ lbm_status lbm_batch_create(const lbm_batch_params *p, const lbm_batch_case *cas
         g.dnx = make_fastdiv(g.nx);
         g.dnxy = make_fastdiv(g.nxy);
         g.zper = 0;
-        g.xw = g.yw = 0;
+        g.xw = g.yw = g.zs = 0;
         Phys<double> &ph = cd.pd;
         ph.rho0 = p->rho0;
         ph.omega_e = 1.0 / k.tau;

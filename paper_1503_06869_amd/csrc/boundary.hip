@@ -143,7 +143,7 @@ static hipError_t boundary_t(bool odd, void *f, const Geo &g, const Phys<double>
     using R = typename St<S>::R;
     const Phys<R> p = cast_phys<R>(ph);
     const dim3 grid(uint32_t(2 * b.np * b.bpf)), bl(256);
-    const int mode = (odd ? 1 : 0) | (stab ? 2 : 0) | ((g.xw || g.yw) ? 4 : 0);
+    const int mode = (odd ? 1 : 0) | (stab ? 2 : 0) | ((g.xw || g.yw || g.zs) ? 4 : 0);
     switch (mode) {
     case 0: hipLaunchKernelGGL((k_boundary<S, false, false, false>), grid, bl, 0, st, (S *)f, g, p, b, stab, part); break;
     case 1: hipLaunchKernelGGL((k_boundary<S, true, false, false>), grid, bl, 0, st, (S *)f, g, p, b, stab, part); break;

@@ -20,6 +20,29 @@ constexpr int CX[Q] = {0, 1, 0, 0, 1, 1, 1, 1, 0, 0, -1, 0, 0, -1, -1, -1, -1, 0
 constexpr int CY[Q] = {0, 0, 1, 0, 1, -1, 0, 0, 1, 1, 0, -1, 0, -1, 1, 0, 0, -1, -1};
 constexpr int CZ[Q] = {0, 0, 0, 1, 0, 0, 1, -1, 1, -1, 0, 0, -1, 0, 0, -1, 1, -1, 1};
 __host__ __device__ constexpr int opp(int q) { return q == 0 ? 0 : (q <= 9 ? q + 9 : q - 9); }
+// Specular reflection (Sec. 4.1, Eq. FreeSlipBC): the direction with the
+// components of c_q selected by m (bit 0: x, 1: y, 2: z) reversed.
+__host__ __device__ constexpr int refl(int q, int m)
+{
+    const int ex = (m & 1) ? -CX[q] : CX[q], ey = (m & 2) ? -CY[q] : CY[q], ez = (m & 4) ? -CZ[q] : CZ[q];
+    int r = q;
+    for (int k = 0; k < Q; ++k)
+        if (CX[k] == ex && CY[k] == ey && CZ[k] == ez) r = k;
+    return r;
+}
+// the same as a choice among the eight reflections of q, which fold to
+// constants where q is known at compile time (unrolled loops over q)
+__host__ __device__ __forceinline__ int refl_sel(int q, int m)
+{
+    return m == 0 ? q
+         : m == 1 ? refl(q, 1)
+         : m == 2 ? refl(q, 2)
+         : m == 3 ? refl(q, 3)
+         : m == 4 ? refl(q, 4)
+         : m == 5 ? refl(q, 5)
+         : m == 6 ? refl(q, 6)
+                  : refl(q, 7);
+}
 __host__ __device__ constexpr double wq(int q)
 {
     return q == 0 ? 1.0 / 3.0 : ((q <= 3 || (q >= 10 && q <= 12)) ? 1.0 / 18.0 : 1.0 / 36.0);
@@ -143,7 +166,9 @@ struct Geo {
     uint64_t qstride;          // elements per direction array: (nz+2) * nxy
     FastDiv dnx, dnxy;
     int32_t zper;
-    int32_t xw, yw;            // 1: resting no-slip walls half-way outside the x (y) faces
+    int32_t xw, yw;            // walls half-way outside the x (y) faces: 0 none (periodic),
+                               // 1 resting no-slip, 2 free-slip
+    int32_t zs;                // 1: the z walls (zper = 0) are free-slip, not moving no-slip
 };
 
 template <typename R>

@@ -84,15 +84,31 @@ inline Phys<R> cast_phys(const Phys<double> &p)
     return o;
 }
 
-// Population q of cell (x, y, z) arrives through a wall on an x or y face
-// (and not through a z wall): in the odd (swapped) layout it sits in the
-// cell's own slot q instead of slot opp(q) of x - c_q.
-__device__ __forceinline__ bool side_in(const Geo &g, uint32_t x, uint32_t y, uint32_t z, int q)
+// Where population q of cell (x, y, z) sits in the swapped layout (between
+// the even and the odd sweep of a pair), i.e. where the odd sweep gathers
+// it: slot opp(q) of x - c_q; through a no-slip x or y wall (and not a
+// no-slip z wall), the cell's own slot q; through free-slip walls only,
+// slot opp(refl(q)) of x - t, refl(q) the direction it had before the
+// reflection and t the components of c_q along the walls it did not cross.
+// Returns the plane-shifted cell index, the slot's direction in qq.
+__device__ __forceinline__ uint32_t swapped_src(const Geo &g, uint32_t x, uint32_t y, uint32_t z, int q, int &qq)
 {
-    const bool sx = g.xw && ((CX[q] > 0 && x == 0) || (CX[q] < 0 && x + 1 == g.nx));
-    const bool sy = g.yw && ((CY[q] > 0 && y == 0) || (CY[q] < 0 && y + 1 == g.ny));
-    const bool sz = !g.zper && ((CZ[q] > 0 && z == 0) || (CZ[q] < 0 && z + 1 == g.nz));
-    return (sx || sy) && !sz;
+    bool ix = g.xw && ((CX[q] > 0 && x == 0) || (CX[q] < 0 && x + 1 == g.nx));
+    bool iy = g.yw && ((CY[q] > 0 && y == 0) || (CY[q] < 0 && y + 1 == g.ny));
+    bool iz = !g.zper && ((CZ[q] > 0 && z == 0) || (CZ[q] < 0 && z + 1 == g.nz));
+    if (iz && !g.zs) {
+        ix = iy = iz = false;      // the z wall's ghost-plane mailbox
+    } else if ((ix && g.xw == 1) || (iy && g.yw == 1)) {
+        qq = q;
+        return (z + 1) * g.nxy + y * g.nx + x;
+    }
+    const int m = (ix ? 1 : 0) | (iy ? 2 : 0) | (iz ? 4 : 0);
+    qq = opp(refl_sel(q, m));
+    const int tx = ix ? 0 : CX[q], ty = iy ? 0 : CY[q], tz = iz ? 0 : CZ[q];
+    const uint32_t sx = (x + g.nx - tx) % g.nx, sy = (y + g.ny - ty) % g.ny;
+    const int32_t szi = int32_t(z) - tz;
+    const uint32_t szs = g.zper ? uint32_t((szi + int32_t(g.nz)) % int32_t(g.nz)) + 1 : uint32_t(szi + 1);
+    return szs * g.nxy + sy * g.nx + sx;
 }
 
 // ------------------------------------------------------------------ stabilization
@@ -263,12 +279,21 @@ __device__ __forceinline__ void link_terms(long long *acc, double ft, double rx,
 // terms to acc[0 .. 5] (links to fiber `home`) or directly to the sums of
 // another fiber.  NK: length of acc (6).
 // STAB: momentum stabilization with the accumulator sa (see StabAcc).
-// XYW: resting no-slip walls on the x and/or y faces (g.xw, g.yw): a link
-// leaving the lattice there bounces back (Eq. BBBC) into the cell's own slot
-// opp(q) in both sweeps (the image cell across the periodic seam is live,
-// so its slots cannot serve as a mailbox), and the odd sweep reads a
-// population that arrives through such a wall from the cell's own slot; a
-// link crossing a z wall as well keeps the z wall's ghost-plane mailbox.
+// XYW: walls on the x and/or y faces (g.xw, g.yw) or free-slip z walls
+// (g.zs).  A link leaving the lattice through a resting no-slip x or y wall
+// bounces back (Eq. BBBC) into the cell's own slot opp(q) in both sweeps
+// (the image cell across the periodic seam is live, so its slots cannot
+// serve as a mailbox), and the odd sweep reads a population that arrives
+// through such a wall from the cell's own slot; a link crossing a no-slip z
+// wall as well keeps the z wall's ghost-plane mailbox.  A link that crosses
+// free-slip walls only is reflected (Eq. FreeSlipBC): the components normal
+// to the crossed walls reverse and the population lands on the neighbour
+// along the other components, x + t.  The even sweep stores it in its own
+// slot opp(q) like a streaming population; the odd sweep gathers it there
+// from x + t and scatters its own reflected populations into the slot
+// refl(q) of x + t, which no other cell touches in that sweep (the slot it
+// gathered from for the reverse link), so both sweeps stay in place.  A
+// link that crosses walls of both kinds bounces back.
 template <typename S, bool ODD, bool BND, int NK = NACC, bool STAB = false, bool XYW = false>
 __device__ __forceinline__ void update_cell(S *__restrict__ f, const Geo &g,
                                             const Phys<typename St<S>::R> &ph, uint32_t cell,
@@ -297,12 +322,13 @@ __device__ __forceinline__ void update_cell(S *__restrict__ f, const Geo &g,
     const R inv = ph.inv_scale, sc = ph.scale;
     const bool wall_lo = !g.zper && z == 0;
     const bool wall_hi = !g.zper && z + 1 == g.nz;
-    bool wx0 = false, wx1 = false, wy0 = false, wy1 = false;
+    bool wx0 = false, wx1 = false, wy0 = false, wy1 = false, zs = false;
     if constexpr (XYW) {
         wx0 = g.xw && x == 0;
         wx1 = g.xw && x + 1 == g.nx;
         wy0 = g.yw && y == 0;
         wy1 = g.yw && y + 1 == g.ny;
+        zs = g.zs != 0;
     }
     const uint32_t own = zo[1] + yo[1] + xo[1];
     R fv[Q];
@@ -311,12 +337,22 @@ __device__ __forceinline__ void update_cell(S *__restrict__ f, const Geo &g,
         if (!ODD) {
             fv[q] = St<S>::ld(f, uint64_t(q) * qs + own, inv);
         } else {
-            bool side_in = false;   // arrives through a side wall (and not a z wall)
-            if constexpr (XYW)
-                side_in = ((CX[q] > 0 && wx0) || (CX[q] < 0 && wx1) || (CY[q] > 0 && wy0) || (CY[q] < 0 && wy1)) &&
-                          !((CZ[q] > 0 && wall_lo) || (CZ[q] < 0 && wall_hi));
+            // walls crossed on the way in (a no-slip z wall: its mailbox, a normal read)
+            bool ix = false, iy = false, iz = false, side_in = false;
+            if constexpr (XYW) {
+                ix = (CX[q] > 0 && wx0) || (CX[q] < 0 && wx1);
+                iy = (CY[q] > 0 && wy0) || (CY[q] < 0 && wy1);
+                iz = zs && ((CZ[q] > 0 && wall_lo) || (CZ[q] < 0 && wall_hi));
+                const bool nsz = !zs && ((CZ[q] > 0 && wall_lo) || (CZ[q] < 0 && wall_hi));
+                if (nsz) ix = iy = false;
+                side_in = (ix && g.xw == 1) || (iy && g.yw == 1);
+            }
             if (side_in) {
                 fv[q] = St<S>::ld(f, uint64_t(q) * qs + own, inv);
+            } else if (ix || iy || iz) {
+                const int m = (ix ? 1 : 0) | (iy ? 2 : 0) | (iz ? 4 : 0);
+                const uint32_t src = zo[1 - (iz ? 0 : CZ[q])] + yo[1 - (iy ? 0 : CY[q])] + xo[1 - (ix ? 0 : CX[q])];
+                fv[q] = St<S>::ld(f, uint64_t(opp(refl_sel(q, m))) * qs + src, inv);
             } else {
                 const uint32_t src = zo[1 - CZ[q]] + yo[1 - CY[q]] + xo[1 - CX[q]];
                 fv[q] = St<S>::ld(f, uint64_t(opp(q)) * qs + src, inv);
@@ -331,19 +367,25 @@ __device__ __forceinline__ void update_cell(S *__restrict__ f, const Geo &g,
     static_for<0, Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         const uint32_t nb = zo[1 + CZ[q]] + yo[1 + CY[q]] + xo[1 + CX[q]];
-        const bool to_wall = (CZ[q] < 0 && wall_lo) || (CZ[q] > 0 && wall_hi);
-        bool to_side = false;
-        if constexpr (XYW)
-            to_side = ((CX[q] < 0 && wx0) || (CX[q] > 0 && wx1) || (CY[q] < 0 && wy0) || (CY[q] > 0 && wy1)) &&
-                      !to_wall;
+        const bool oz = (CZ[q] < 0 && wall_lo) || (CZ[q] > 0 && wall_hi);
+        const bool to_wall = oz && !zs;
+        bool to_side = false, to_slip = false;
+        int slip_m = 0;
+        if constexpr (XYW) {
+            const bool ox = (CX[q] < 0 && wx0) || (CX[q] > 0 && wx1);
+            const bool oy = (CY[q] < 0 && wy0) || (CY[q] > 0 && wy1);
+            to_side = !to_wall && ((ox && g.xw == 1) || (oy && g.yw == 1));
+            to_slip = !to_wall && !to_side && (ox || oy || oz);
+            slip_m = (ox ? 1 : 0) | (oy ? 2 : 0) | (oz ? 4 : 0);
+        }
         bool to_part = false;
-        if (BND) to_part = (mask >> q) & 1u;
+        if (BND) to_part = ((mask >> q) & 1u) && !to_slip;
         R out = fv[q];
         if (CX[q] != 0 && to_wall) {
             const R uw = CZ[q] < 0 ? -ph.wall_u : ph.wall_u;
             out -= six_r0 * R(wq(q)) * R(CX[q]) * uw;
         }
-        if (BND && to_part && !to_side) {
+        if (BND && to_part && !to_side) {   // (to_part excludes reflected links)
             // moving-obstacle bounce-back (Eq. LBMMovWall) and the link's
             // momentum exchange, from the post-collision value in registers
             const int32_t p = b.pid[nb - g.nxy];
@@ -377,21 +419,35 @@ __device__ __forceinline__ void update_cell(S *__restrict__ f, const Geo &g,
         const bool bounce = to_wall || to_side || to_part;
         if constexpr (STAB) {
             // a bounced link returns out in direction -c_q instead of
-            // streaming fv[q] along c_q
+            // streaming fv[q] along c_q; a reflected one reverses the
+            // components normal to the crossed walls
             if (bounce) {
                 const R m = fv[q] + out;
                 if (CX[q]) sa->j[0] -= CX[q] > 0 ? m : -m;
                 if (CY[q]) sa->j[1] -= CY[q] > 0 ? m : -m;
                 if (CZ[q]) sa->j[2] -= CZ[q] > 0 ? m : -m;
+            } else if (to_slip) {
+                const R m = fv[q] + fv[q];
+                if (slip_m & 1) sa->j[0] -= CX[q] > 0 ? m : -m;
+                if (slip_m & 2) sa->j[1] -= CY[q] > 0 ? m : -m;
+                if (slip_m & 4) sa->j[2] -= CZ[q] > 0 ? m : -m;
             }
         }
         if (!ODD) {
-            // mailbox for z walls and fibers; normal streaming and side walls: own slot
+            // mailbox for z walls and fibers; normal streaming, side walls
+            // and reflections: own slot
             if (to_wall || (to_part && !to_side)) St<S>::st(f, uint64_t(q) * qs + nb, out, sc);
             else St<S>::st(f, uint64_t(opp(q)) * qs + own, out, sc);
         } else {
-            if (bounce) St<S>::st(f, uint64_t(opp(q)) * qs + own, out, sc);
-            else St<S>::st(f, uint64_t(q) * qs + nb, out, sc);
+            if (to_slip) {
+                const uint32_t dst = zo[1 + ((slip_m & 4) ? 0 : CZ[q])] + yo[1 + ((slip_m & 2) ? 0 : CY[q])] +
+                                     xo[1 + ((slip_m & 1) ? 0 : CX[q])];
+                St<S>::st(f, uint64_t(refl_sel(q, slip_m)) * qs + dst, out, sc);
+            } else if (bounce) {
+                St<S>::st(f, uint64_t(opp(q)) * qs + own, out, sc);
+            } else {
+                St<S>::st(f, uint64_t(q) * qs + nb, out, sc);
+            }
         }
     });
     (void)six_r0;

@@ -116,15 +116,17 @@ __global__ __launch_bounds__(256) void k_rigid(PartData pd, Geo g)
         if (bad) atomicOr(&pd.ctr->err_unstable, 1u);
         pd.ps_prev[p] = pd.ps_next[p];   // the pose of the previous step, about to be overwritten
         pd.ps_next[p] = o;
-        if (g.xw || g.yw) {
+        if (g.xw || g.yw || g.zs) {
             // fibers keep more than one cell from x and y walls (the mapping
-            // and momentum exchange take x and y as periodic)
-            for (int k = 0; k < 2; ++k) {
-                if (!(k == 0 ? g.xw : g.yw)) continue;
+            // and momentum exchange take x and y as periodic) and from
+            // free-slip z walls (a reflected population lands on a cell of
+            // the wall layer, which must be fluid)
+            for (int k = 0; k < 3; ++k) {
+                if (!(k == 0 ? g.xw : (k == 1 ? g.yw : g.zs))) continue;
                 const double ext = c.shape == 1 ? (0.5 * c.length - c.radius) * fabs(o.t[k]) + c.radius
                                                 : 0.5 * c.length * fabs(o.t[k]) +
                                                       c.radius * sqrt(fmax(0.0, 1.0 - o.t[k] * o.t[k]));
-                const double nk = k == 0 ? double(g.nx) : double(g.ny);
+                const double nk = k == 0 ? double(g.nx) : (k == 1 ? double(g.ny) : double(g.nz));
                 if (o.X[k] - ext < 1.0 || o.X[k] + ext > nk - 2.0) atomicOr(&pd.ctr->err_wall, 1u);
             }
         }

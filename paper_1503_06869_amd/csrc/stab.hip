@@ -27,14 +27,7 @@ __device__ __forceinline__ void cell_momentum(const S *__restrict__ f, const Geo
     for (int q = 1; q < Q; ++q) {
         uint32_t src = (z + 1) * g.nxy + y * g.nx + x;
         int qq = q;
-        if (swapped && !side_in(g, x, y, z, q)) {
-            const uint32_t sx = (x + g.nx - CX[q]) % g.nx, sy = (y + g.ny - CY[q]) % g.ny;
-            const int32_t szi = int32_t(z) - CZ[q];
-            const uint32_t szs =
-                g.zper ? uint32_t((szi + int32_t(g.nz)) % int32_t(g.nz)) + 1 : uint32_t(szi + 1);
-            src = szs * g.nxy + sy * g.nx + sx;
-            qq = opp(q);
-        }
+        if (swapped) src = swapped_src(g, x, y, z, q, qq);
         const double v = double(St<S>::ld(f, uint64_t(qq) * g.qstride + src, inv));
         j[0] += CX[q] * v;
         j[1] += CY[q] * v;

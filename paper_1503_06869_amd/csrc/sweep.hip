@@ -85,14 +85,7 @@ __global__ void k_decode(const S *__restrict__ f, const uint8_t *__restrict__ fl
         for (int q = 0; q < Q; ++q) {
             uint32_t src = (z + 1) * g.nxy + y * g.nx + x;
             int qq = q;
-            if (swapped && !side_in(g, x, y, z, q)) {
-                const uint32_t sx = (x + g.nx - CX[q]) % g.nx, sy = (y + g.ny - CY[q]) % g.ny;
-                const int32_t szi = int32_t(z) - CZ[q];
-                const uint32_t szs = g.zper ? uint32_t((szi + int32_t(g.nz)) % int32_t(g.nz)) + 1
-                                            : uint32_t(szi + 1);
-                src = szs * g.nxy + sy * g.nx + sx;
-                qq = opp(q);
-            }
+            if (swapped) src = swapped_src(g, x, y, z, q, qq);
             fv[q] = double(St<S>::ld(f, uint64_t(qq) * g.qstride + src, R(ph.inv_scale)));
         }
         const bool solid = flags[cell] & F_SOLID;
@@ -128,14 +121,7 @@ __global__ void k_encode(S *__restrict__ f, Geo g, double rho0, double scale, in
         for (int q = 0; q < Q; ++q) {
             uint32_t dst = (z + 1) * g.nxy + y * g.nx + x;
             int qq = q;
-            if (swapped && !side_in(g, x, y, z, q)) {
-                const uint32_t sx = (x + g.nx - CX[q]) % g.nx, sy = (y + g.ny - CY[q]) % g.ny;
-                const int32_t szi = int32_t(z) - CZ[q];
-                const uint32_t szs = g.zper ? uint32_t((szi + int32_t(g.nz)) % int32_t(g.nz)) + 1
-                                            : uint32_t(szi + 1);
-                dst = szs * g.nxy + sy * g.nx + sx;
-                qq = opp(q);
-            }
+            if (swapped) dst = swapped_src(g, x, y, z, q, qq);
             const double dev = fin[uint64_t(q) * g.ncell + cell] - wq(q) * rho0;
             St<S>::st(f, uint64_t(qq) * g.qstride + dst, typename St<S>::R(dev),
                       typename St<S>::R(scale));
@@ -163,7 +149,7 @@ static hipError_t sweep_t(bool odd, void *f, const uint8_t *flags, const Geo &g,
     if (!sweep_grid) return hipSuccess;
     if (ev0) hipEventRecord(ev0, st);
     const dim3 gr(sweep_grid), bl(256);
-    const int mode = (odd ? 1 : 0) | (stab ? 2 : 0) | ((g.xw || g.yw) ? 4 : 0);
+    const int mode = (odd ? 1 : 0) | (stab ? 2 : 0) | ((g.xw || g.yw || g.zs) ? 4 : 0);
     switch (mode) {
     case 0: hipLaunchKernelGGL((k_sweep_bulk<S, false, false, false>), gr, bl, 0, st, (S *)f, flags, g, p, stab, part); break;
     case 1: hipLaunchKernelGGL((k_sweep_bulk<S, true, false, false>), gr, bl, 0, st, (S *)f, flags, g, p, stab, part); break;

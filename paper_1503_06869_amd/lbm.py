@@ -57,7 +57,7 @@ class lbm_params(C.Structure):
                 ("storage", C.c_int32), ("init_profile", C.c_int32), ("coupling", C.c_int32),
                 ("fp16_scale_log2", C.c_int32), ("history_capacity", C.c_int64),
                 ("stream", C.c_void_p), ("sweep_grid", C.c_int32), ("q_pad", C.c_int32),
-                ("stabilize", C.c_int32), ("reserved", C.c_int32),
+                ("stabilize", C.c_int32), ("z_free_slip", C.c_int32),
                 ("contact_stiffness", C.c_double), ("contact_range", C.c_double),
                 ("x_walls", C.c_int32), ("y_walls", C.c_int32)]
 
@@ -213,6 +213,15 @@ def copy_bytes(dst_ptr, src_ptr, nbytes, stream=None):
         raise LBMError(r, "copy failed")
 
 
+WALLS = {"periodic": 0, "no-slip": 1, "free-slip": 2}
+
+
+def _wall_code(v):
+    if isinstance(v, str):
+        return WALLS[v]
+    return 1 if v else 0
+
+
 class Context:
     """One lattice with its fibers (owns an lbm_ctx)."""
 
@@ -220,11 +229,13 @@ class Context:
                  z_periodic=False, collision="trt", storage="f32", init_couette=False,
                  coupling="implicit", body_force=(0.0, 0.0, 0.0), fp16_scale_log2=14,
                  history_capacity=4096, stream=None, sweep_grid=0, q_pad=-1, stabilize=False,
-                 contact_k=0.0, contact_range=1.0, x_walls=False, y_walls=False):
+                 contact_k=0.0, contact_range=1.0, x_walls=False, y_walls=False, z_free_slip=False):
         """stabilize: momentum stabilization (subtract the mean fluid velocity
         in every equilibrium), for fully periodic boxes with forced particles.
         contact_k, contact_range: short-range repulsion between fibers (off at 0).
-        x_walls, y_walls: resting no-slip walls on the x (y) faces instead of periodicity."""
+        x_walls, y_walls: walls on the x (y) faces instead of periodicity --
+        True or "no-slip" (resting), "free-slip" (specular reflection).
+        z_free_slip: the z walls (z_periodic False, wall_u 0) are free-slip."""
         L = load()
         p = lbm_params()
         L.lbm_params_default(C.byref(p))
@@ -244,8 +255,9 @@ class Context:
         p.stabilize = int(bool(stabilize))
         p.contact_stiffness = float(contact_k)
         p.contact_range = float(contact_range)
-        p.x_walls = int(bool(x_walls))
-        p.y_walls = int(bool(y_walls))
+        p.x_walls = _wall_code(x_walls)
+        p.y_walls = _wall_code(y_walls)
+        p.z_free_slip = int(bool(z_free_slip))
         h = C.c_void_p()
         r = L.lbm_create(C.byref(p), C.byref(h))
         if r != LBM_OK:

@@ -88,7 +88,16 @@ def test_params_default_and_argument_errors(libso):
     assert L.lbm_create(C.byref(bad), C.byref(h)) == lbm.LBM_E_ARG
     bad.contact_stiffness = -1.0
     assert L.lbm_create(C.byref(bad), C.byref(h)) == lbm.LBM_E_ARG
-    bad.contact_stiffness, bad.x_walls = 0.0, 2
+    bad.contact_stiffness, bad.x_walls = 0.0, 3
+    assert L.lbm_create(C.byref(bad), C.byref(h)) == lbm.LBM_E_ARG
+    bad.x_walls, bad.y_walls = 0, -1
+    assert L.lbm_create(C.byref(bad), C.byref(h)) == lbm.LBM_E_ARG
+    # free-slip z walls need non-periodic z and resting walls
+    bad.y_walls, bad.z_free_slip, bad.z_periodic = 0, 1, 1
+    assert L.lbm_create(C.byref(bad), C.byref(h)) == lbm.LBM_E_ARG
+    bad.z_periodic, bad.wall_u = 0, 0.01
+    assert L.lbm_create(C.byref(bad), C.byref(h)) == lbm.LBM_E_ARG
+    bad.wall_u, bad.z_free_slip = 0.0, 2
     assert L.lbm_create(C.byref(bad), C.byref(h)) == lbm.LBM_E_ARG
     assert L.lbm_step(None, 1) == lbm.LBM_E_ARG
 
