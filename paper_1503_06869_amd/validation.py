@@ -1,8 +1,12 @@
-"""Single-spherocylinder rotation under a constant torque (the paper's
-rotational validation, Sec. 5.1 setup and its appendix table).
+"""The paper's single-particle validations (Sec. 5.1 setup and its appendix
+table) -- a spherocylinder rotating under a constant torque, and one
+sedimenting under a constant force in a box closed by free-slip walls --
+and the tumbling pair of Sec. 6.
 
     python -m paper_1503_06869_amd.validation [--aspect 4] [--n 816] [--steps 40000]
     python -m paper_1503_06869_amd.validation --case tumbling [--aspect 12] [--dist 14.8] [--n 576]
+    python -m paper_1503_06869_amd.validation --case sedimentation [--aspect 8]
+        [--orientation lengthwise|sidewise] [--nxy 160] [--nz 1200] [--steps 80000]
 
 The paper's setup: spherocylinders of radius r = 4 dx and L = (1/eps) r
 (L including the caps), dx = 1e-5 m, water (nu = 1e-6 m^2/s, rho_f =
@@ -205,9 +209,90 @@ def run_tumbling(aspect, n, dist, steps, every, storage="f32", contact_k=0.0, co
             "history": h.tolist()}
 
 
+# ---------------------------------------------------------------------------
+# Translational validation (Sec. 5.1 setup): the same spherocylinders under
+# the constant force F_z = 5.128e-10 N (the buoyancy-corrected weight of a
+# sphere of radius 4 dx) in a cuboid closed by free-slip walls, the particle
+# centred in x and y and 100 r below the top wall (z = 0), falling towards
+# +z.  The appendix table's LBM velocities U*_LBM [1e-6 m/s] (2560^2 x 2688
+# box) and the Tirado values for a cylinder of the full length (wC) and of
+# the length without the caps (nC), by orientation of the axis relative to
+# the force.
+SED_FORCE = 5.128e-10    # kg m/s^2
+U_LBM = {"lengthwise": {4: 503, 6: 419, 8: 363, 10: 324, 12: 294, 14: 269},
+         "sidewise": {4: 447, 6: 349, 8: 291, 10: 252, 12: 223, 14: 201}}
+U_TIR_WC = {"lengthwise": {4: 481, 6: 409, 8: 361, 10: 325, 12: 297, 14: 273},
+            "sidewise": {4: 429, 6: 344, 8: 292, 10: 255, 12: 227, 14: 205}}
+
+
+def tirado_translation(force, length, radius, orientation, mu=RHO_F * NU):
+    """Sedimentation velocity F / gamma_t of a cylinder (Eqs.
+    CapsTheorVelLengthwSidesMotionTirado, EndeffLengthwMotionTirado,
+    EndeffCorrSidewMotionTirado): gamma_par = 2 pi mu L / (ln a + v_par),
+    gamma_perp = 4 pi mu L / (ln a + v_perp), a = L / (2 r),
+    v_par = -0.207 + 0.980/a - 0.133/a^2, v_perp = 0.839 + 0.185/a + 0.233/a^2."""
+    a = length / (2.0 * radius)
+    if orientation == "lengthwise":
+        gamma = 2.0 * math.pi * mu * length / (math.log(a) - 0.207 + 0.980 / a - 0.133 / a ** 2)
+    else:
+        gamma = 4.0 * math.pi * mu * length / (math.log(a) + 0.839 + 0.185 / a + 0.233 / a ** 2)
+    return force / gamma
+
+
+def run_sedimentation(aspect, orientation, nxy, nz, steps, every=200, storage="f32", window=0.34, log=print):
+    """One spherocylinder sedimenting in a free-slip nxy x nxy x nz box.
+    The terminal velocity is the mean of the samples (every `every` steps)
+    in the last `window` of the run, as the paper averages its samples."""
+    from . import lbm
+    L = aspect * R_CELLS
+    F = lattice_force(SED_FORCE, DX, dt())
+    g = lbm.Context(nxy, nxy, nz, tau=TAU, storage=storage, x_walls="free-slip", y_walls="free-slip",
+                    z_free_slip=True)
+    c = 0.5 * (nxy - 1)
+    z0 = 100.0 * R_CELLS - 0.5            # the top wall lies half a cell above cell 0
+    axis = (0.0, 0.0, 1.0) if orientation == "lengthwise" else (1.0, 0.0, 0.0)
+    t = np.asarray(axis)
+    q = np.array([1.0 + t[0], 0.0, -t[2], t[1]])
+    q = q / np.linalg.norm(q)
+    g.add_fiber((c, c, z0), q, L, R_CELLS, RHO_P / RHO_F, shape="spherocylinder", force=(0.0, 0.0, F))
+    ts, us, zs = [], [], []
+    t0 = time.time()
+    done = 0
+    while done < steps:
+        k = min(every, steps - done)
+        g.step(k)
+        done += k
+        X, _, V, _ = g.fiber_state()
+        ts.append(done)
+        us.append(float(V[0][2]))
+        zs.append(float(X[0][2]))
+        if len(ts) % max(1, 5000 // every) == 0 or done == steps:
+            log("step %7d  U_z %.6e (lattice)  %.2f um/s  z %.1f  %.0f s" % (
+                done, us[-1], us[-1] * DX / dt() * 1e6, zs[-1], time.time() - t0))
+    g.close()
+    tail = np.asarray(us[int(len(us) * (1.0 - window)):])
+    u_lat = float(tail.mean())
+    u = u_lat * DX / dt()
+    return {
+        "aspect": aspect, "orientation": orientation, "nxy": nxy, "nz": nz, "steps": steps,
+        "storage": storage, "walls": "free-slip on all six faces",
+        "length_cells": L, "radius_cells": R_CELLS, "tau": TAU, "dt_s": dt(), "force_lattice": F,
+        "u_lattice": u_lat, "u_m_s": u,
+        "delta_u_pct": float(100.0 * (tail.max() - tail.min()) / abs(u_lat)) if u_lat else None,
+        "re_p_d": u * 2.0 * R_CELLS * DX / NU,
+        "z_end": zs[-1],
+        "u_paper_lbm_2560": U_LBM[orientation][aspect] * 1e-6,
+        "u_tirado_wc": tirado_translation(SED_FORCE, L * DX, R_CELLS * DX, orientation),
+        "history": list(zip(ts, us, zs)),
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--case", default="rotation", choices=("rotation", "tumbling"))
+    ap.add_argument("--case", default="rotation", choices=("rotation", "tumbling", "sedimentation"))
+    ap.add_argument("--orientation", default="lengthwise", choices=("lengthwise", "sidewise"))
+    ap.add_argument("--nxy", type=int, default=160)
+    ap.add_argument("--nz", type=int, default=1200)
     ap.add_argument("--aspect", type=int, default=None)
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--dist", type=float, default=14.8)
@@ -219,6 +304,15 @@ def main(argv=None):
     ap.add_argument("--all-walls", action="store_true", help="rotation: no-slip walls on all six faces")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
+    if a.case == "sedimentation":
+        res = run_sedimentation(a.aspect or 8, a.orientation, a.nxy, a.nz, a.steps or 80000, a.every or 200,
+                                a.storage, log=lambda s: print(s, flush=True))
+        line = {k: v for k, v in res.items() if k != "history"}
+        print(json.dumps(line), flush=True)
+        if a.out:
+            with open(a.out, "w") as fh:
+                json.dump(res, fh)
+        return 0
     if a.case == "tumbling":
         res = run_tumbling(a.aspect or 12, a.n or 576, a.dist, a.steps or 50000, a.every or 200, a.storage,
                            a.contact_k, a.contact_range, log=lambda s: print(s, flush=True))

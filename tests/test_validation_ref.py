@@ -6,6 +6,7 @@ import json
 import os
 
 import numpy as np
+import pytest
 
 from paper_1503_06869_amd import validation as V
 
@@ -108,3 +109,45 @@ def test_period_detection_on_a_uniform_tumble():
     for k, (s, z) in enumerate(ends[1:], 1):
         assert abs(s - k * np.pi / w) < 1e-6 * s
         assert abs(z - v * k * np.pi / w) < 1e-6 * z
+
+
+# ------------------------------------------------- translational validation (Sec. 5.1)
+SED = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "sedimentation_validation.json")))
+
+
+def test_sedimentation_parameters_are_the_papers():
+    assert V.SED_FORCE == SED["force_z_kg_m_s2"]
+    for o in ("lengthwise", "sidewise"):
+        for i, A in enumerate(SED["aspect_ratios"]):
+            assert V.U_LBM[o][A] == SED[o]["u_lbm_1e-6_m_s"][i]
+            assert V.U_TIR_WC[o][A] == SED[o]["u_tirado_wc_1e-6_m_s"][i]
+
+
+@pytest.mark.parametrize("orientation", ["lengthwise", "sidewise"])
+def test_tirado_translation_reproduces_the_printed_values(orientation):
+    """U = F / gamma_t for cylinders of the full length (wC) and of the
+    length without the caps (nC), to the printed three digits."""
+    r = V.R_CELLS * V.DX
+    for i, A in enumerate(SED["aspect_ratios"]):
+        L = A * r
+        wc = V.tirado_translation(V.SED_FORCE, L, r, orientation) * 1e6
+        nc = V.tirado_translation(V.SED_FORCE, L - 2 * r, r, orientation) * 1e6
+        assert abs(wc / SED[orientation]["u_tirado_wc_1e-6_m_s"][i] - 1) < 3e-3, (A, wc)
+        assert abs(nc / SED[orientation]["u_tirado_nc_1e-6_m_s"][i] - 1) < 3e-3, (A, nc)
+
+
+@pytest.mark.parametrize("orientation", ["lengthwise", "sidewise"])
+def test_printed_reynolds_numbers_follow_from_the_printed_velocities(orientation):
+    """Re_p,d = U* 2 r / nu (Eq. ParticleReynoldsNr with the diameter):
+    the conversion the driver reports, against the printed Reynolds numbers."""
+    for i, A in enumerate(SED["aspect_ratios"]):
+        u = SED[orientation]["u_lbm_1e-6_m_s"][i] * 1e-6
+        re = u * 2 * V.R_CELLS * V.DX / V.NU
+        assert abs(re - SED[orientation]["re_p_d"][i]) <= 0.0006, (A, re)
+
+
+def test_sedimentation_force_in_lattice_units():
+    """F_lat = F dt^2 / (rho_f dx^4) with dt = 183e-6 s: about 1.72."""
+    F = V.lattice_force(V.SED_FORCE, V.DX, V.dt())
+    np.testing.assert_allclose(F * V.RHO_F * V.DX ** 4 / V.dt() ** 2, V.SED_FORCE, rtol=1e-14)
+    assert 1.70 < F < 1.75
