@@ -204,7 +204,8 @@ def time_sbf(torch, m=1024, steps=10, warmup=2):
     GMRES to 1e-10, the velocities and the Adams-Bashforth-2 update.
     Roofline of its two kernels: the moments (FP64 ALU: per pair
     Q^2 (33 + 15 (N + 1)) + 21 Q (N + 1)^2 flops over m (m - 1)/2 pairs) and
-    the product with the moment matrix (HBM: D^2 x 8 bytes, D = 3 m (N + 1))."""
+    the product with the symmetric moment matrix (HBM: its D (D + 1)/2
+    distinct entries x 8 bytes, D = 3 m (N + 1))."""
     from paper_1503_06869_amd import scenarios, sbf
     N, nq = 5, 16
     sc = scenarios.sbf_cloud(seed=0, m=m)
@@ -232,8 +233,8 @@ def time_sbf(torch, m=1024, steps=10, warmup=2):
                         "peak_tflops": FP64_VECTOR_PEAK_TFLOPS,
                         "frac": round(flops / (th_ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS, 4)},
             "gemv": {"bound": "hbm", "ms": round(gv_ms, 4), "launches_per_step": round(ng / steps, 1),
-                     "achieved_gbs": round(D * D * 8 / (gv_ms * 1e-3) / 1e9, 1),
-                     "frac": round(D * D * 8 / (gv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+                     "achieved_gbs": round(D * (D + 1) / 2 * 8 / (gv_ms * 1e-3) / 1e9, 1),
+                     "frac": round(D * (D + 1) / 2 * 8 / (gv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
 
 
 def sweep_sources_sha1():

@@ -59,8 +59,9 @@ typedef struct {
  * restart 30, 200 iterations, L = 1, eps = 0.1, mu = 1, tolerance 1e-12. */
 lbm_status sbf_params_default(sbf_params *p);
 
-/* Allocate a context for up to max_fibers fibers: the moment matrix of
- * (3 M (N + 1))^2 doubles and the GMRES basis.  LBM_E_ARG for invalid
+/* Allocate a context for up to max_fibers fibers: the moment matrix (it
+ * is symmetric; its upper triangle of 64 x 64 tiles, about
+ * (3 M (N + 1))^2 / 2 doubles) and the GMRES basis.  LBM_E_ARG for invalid
  * parameters (including nq and N whose moment workgroup would need more
  * than 64 KiB of LDS: 8 (N + 1)(21 nq + 7 (N + 1)) bytes), LBM_E_NOMEM
  * when the device memory does not suffice. */

@@ -1,5 +1,9 @@
-"""Training and use of the learned force/torque closure (driver; every
-numeric step runs in the library's HIP kernels).
+"""Training and use of the learned force/torque closure.  The simulations,
+feature sampling, network forward and backward passes and the Adam updates
+run in the library's HIP kernels; this driver prepares the training data
+on the host with numpy (the fine-minus-coarse targets, their rotation into
+the body frame, the scaling by rho0 nu gamma L^k and the feature and
+target normalisation) and chooses which runs to make.
 
 Pairs of runs under diffusive scaling at fixed tau: a resolved fine case
 (fiber diameter 4) and its coarse twin (lattice spacing 2, diameter 2).  One

@@ -5,7 +5,7 @@
 // force_exp, solved by restarted GMRES, the velocities of Eqs. xadot and
 // padot, and Adams-Bashforth-2 time stepping.  C ABI in include/sbf.h.
 //
-// Layout.  The moments are kept in one dense FP64 matrix W of order
+// Layout.  The moments form one dense symmetric FP64 matrix W of order
 // D = 3 M (N + 1): row (m, n, a), column (m', k, b) holds
 //   Theta^{n,k}_{mm'}[a][b] = int int G(R(s, s'))_ab P_k(s'/l) P_n(s/l) ds' ds,
 //   R = x_m + s p_m - x_m' - s' p_m',
@@ -16,10 +16,20 @@
 // system operator is that GEMV followed by 3x3 block operations per (m, n),
 // and the velocities come from the n = 0 and n = 1 rows of W [F/(2l); a].
 //
+// G(R) and G(-R) are equal and symmetric, so Theta^{k,n}_{m'm} is the
+// transpose of Theta^{n,k}_{mm'} and W = W^T.  Only its upper triangle is
+// stored, as 64 x 64 tiles (i, j), i <= j, packed row after row, each tile
+// row-major; the diagonal tiles are stored whole, padding rows and columns
+// beyond D are zero.  A product y = W x reads every stored tile once and
+// uses it twice, W_ij x_j for the rows of block i and W_ij^T x_i for the
+// rows of block j (i < j), writing each into its own slot of a partial-sum
+// array part[slot][row] (row sums per chunk of tiles of a tile row, column
+// sums per tile); a second pass adds the slots of each row in a fixed order.
+//
 // Bound: the moments are FP64 ALU work (M^2/2 pairs x (3 nq)^2 Green's
-// function evaluations; G(R) and G(-R) are equal and symmetric, so a pair's
-// moments give both blocks of W); each GMRES iteration streams W once
-// (D^2 x 8 bytes, HBM bound).
+// function evaluations, each pair giving both of its blocks of W); each
+// GMRES iteration streams the stored half of W once (about D^2/2 x 8
+// bytes, HBM bound).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,79 +45,140 @@ namespace sbfk {
 
 constexpr int MAXN = 8;        // Legendre modes supported (N <= 8)
 constexpr int MAXR = 64;       // Krylov dimension
+constexpr int TS = 64;         // tile edge of the packed moment matrix
 
 struct Consts {
     int M, N, Q, D;            // fibers, modes, quadrature points per fiber, order of W
+    int nt;                    // tiles per side, ceil(D / TS)
     double l, L, r, d, mu;
 };
 
+// first element of tile (i, j), i <= j, in the packed upper triangle
+__host__ __device__ __forceinline__ size_t tile_base(int i, int j, int nt)
+{
+    // rows r < i hold nt - r tiles each: i nt - i (i - 1)/2 = i (2 nt - i + 1)/2
+    return (size_t(i) * (2 * size_t(nt) - size_t(i) + 1) / 2 + size_t(j - i)) * (TS * TS);
+}
+
+// packed tiles of the upper triangle for nt tiles per side
+__host__ __device__ __forceinline__ size_t packed_tiles(int nt) { return size_t(nt) * size_t(nt + 1) / 2; }
+
 // ------------------------------------------------------------------ moments
-// One 64-thread block per ordered pair (m, mp); blocks with m > mp return at
-// once (their block of W is written by the pair (mp, m)); m = mp zeroes the
-// diagonal block.  Thread i < Q takes the outer quadrature point s_i and
-// sums over the inner points s'_j, per trial mode k, the scalar part
-// alpha and the six components of beta R R^T of G = alpha I + beta R R^T;
-// the outer sums with P_n(s_i) follow from LDS.
+// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton steps
+// y <- y + y (1 - x y^2)/2 (each at least doubles the correct bits).
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
+// entry (R, C), R < C, of the symmetric matrix into the packed upper
+// triangle (a diagonal tile is stored whole: its mirror entry too)
+__device__ __forceinline__ void put_sym(double *W, int nt, int R, int C, double v)
+{
+    const int bi = R / TS, bj = C / TS, ri = R % TS, ci = C % TS;
+    double *t = W + tile_base(bi, bj, nt);
+    t[ri * TS + ci] = v;
+    if (bi == bj) t[ci * TS + ri] = v;
+}
+
+// Sums over the inner points s'_j for the outer point s_i of the pair:
+// acc[k] = sum_j w_j P_k(s_j) (alpha, beta R R^T entries) of G(R_ij).
+template <int NP1>
+__device__ __forceinline__ void moment_point(int i, const double (&xm)[3], const double (&pm)[3],
+                                             const double (&xn)[3], const double (&pn)[3], double h,
+                                             const Consts &c, const double *__restrict__ sq,
+                                             const double *__restrict__ wl, double (&acc)[NP1][7])
+{
+#pragma unroll
+    for (int k = 0; k < NP1; ++k)
+#pragma unroll
+        for (int e = 0; e < 7; ++e) acc[k][e] = 0.0;
+    const double si = sq[i];
+    const double b0 = xm[0] + si * pm[0] - xn[0], b1 = xm[1] + si * pm[1] - xn[1], b2 = xm[2] + si * pm[2] - xn[2];
+    for (int j = 0; j < c.Q; ++j) {
+        const double sj = sq[j];
+        const double R0 = b0 - sj * pn[0], R1 = b1 - sj * pn[1], R2 = b2 - sj * pn[2];
+        const double r2 = R0 * R0 + R1 * R1 + R2 * R2;
+        const double inv = rsqrt_nr(r2);
+        const double inv2 = inv * inv, inv3 = inv * inv2;
+        const double alpha = inv + h * inv3;
+        const double beta = inv3 - 3.0 * h * inv3 * inv2;
+        const double g[7] = {alpha, beta * R0 * R0, beta * R0 * R1, beta * R0 * R2,
+                             beta * R1 * R1, beta * R1 * R2, beta * R2 * R2};
+#pragma unroll
+        for (int k = 0; k < NP1; ++k) {
+            const double wk = wl[k * c.Q + j];
+#pragma unroll
+            for (int e = 0; e < 7; ++e) acc[k][e] += wk * g[e];
+        }
+    }
+}
+
+// One 64-thread block per ordered pair (m, mp); blocks with m >= mp return
+// at once (the pair (mp, m) writes both blocks; the diagonal blocks stay at
+// the zero the packed matrix was cleared to).  Thread i < Q takes the outer
+// quadrature point s_i and sums over the inner points s'_j, per trial mode
+// k, the scalar part alpha and the six components of beta R R^T of
+// G = alpha I + beta R R^T; the outer sums with P_n(s_i) follow from LDS.
+// wl[k][j] = w_j P_k(s_j) (quadrature weight times Legendre value).
 template <int NP1>
 __global__ __launch_bounds__(64) void k_theta(const double *__restrict__ X, const double *__restrict__ p, Consts c,
-                                              const double *__restrict__ sq, const double *__restrict__ wq,
-                                              const double *__restrict__ leg, double *__restrict__ W)
+                                              const double *__restrict__ sq, const double *__restrict__ wl,
+                                              double *__restrict__ W)
 {
     const int m = int(blockIdx.x) / c.M, mp = int(blockIdx.x) % c.M;
     const int st = 3 * NP1;
-    if (m > mp) return;
-    if (m == mp) {
-        for (int e = threadIdx.x; e < st * st; e += 64)
-            W[size_t(m * st + e / st) * c.D + size_t(mp * st + e % st)] = 0.0;
-        return;
-    }
-    extern __shared__ double sh[];            // [Q][NP1][7], then out[NP1][NP1][7]
-    double *out = sh + size_t(c.Q) * NP1 * 7;
+    if (m >= mp) return;
+    extern __shared__ double sh[];
     const double xm[3] = {X[3 * m], X[3 * m + 1], X[3 * m + 2]};
     const double pm[3] = {p[3 * m], p[3 * m + 1], p[3 * m + 2]};
     const double xn[3] = {X[3 * mp], X[3 * mp + 1], X[3 * mp + 2]};
     const double pn[3] = {p[3 * mp], p[3 * mp + 1], p[3 * mp + 2]};
     const double h = 0.5 * c.r * c.r;
-    for (int i = threadIdx.x; i < c.Q; i += 64) {
-        double acc[NP1][7];
+    double acc[NP1][7];
+    double *out;
+    if (c.Q <= 64) {
+        // one outer point per thread; the projections on P_n go one trial
+        // mode k at a time through a [Q][7] buffer (small LDS, more blocks
+        // per CU)
+        out = sh + size_t(c.Q) * 7;            // [Q][7], then out[NP1][NP1][7]
+        if (int(threadIdx.x) < c.Q) moment_point<NP1>(int(threadIdx.x), xm, pm, xn, pn, h, c, sq, wl, acc);
 #pragma unroll
-        for (int k = 0; k < NP1; ++k)
+        for (int k = 0; k < NP1; ++k) {
+            if (int(threadIdx.x) < c.Q)
 #pragma unroll
-            for (int e = 0; e < 7; ++e) acc[k][e] = 0.0;
-        const double si = sq[i];
-        const double b0 = xm[0] + si * pm[0] - xn[0], b1 = xm[1] + si * pm[1] - xn[1],
-                     b2 = xm[2] + si * pm[2] - xn[2];
-        for (int j = 0; j < c.Q; ++j) {
-            const double sj = sq[j];
-            const double R0 = b0 - sj * pn[0], R1 = b1 - sj * pn[1], R2 = b2 - sj * pn[2];
-            const double r2 = R0 * R0 + R1 * R1 + R2 * R2;
-            const double inv = 1.0 / sqrt(r2);
-            const double inv2 = inv * inv, inv3 = inv * inv2;
-            const double alpha = inv + h * inv3;
-            const double beta = inv3 - 3.0 * h * inv3 * inv2;
-            const double g[7] = {alpha, beta * R0 * R0, beta * R0 * R1, beta * R0 * R2,
-                                 beta * R1 * R1, beta * R1 * R2, beta * R2 * R2};
-            const double wj = wq[j];
-#pragma unroll
-            for (int k = 0; k < NP1; ++k) {
-                const double wk = wj * leg[k * c.Q + j];
-#pragma unroll
-                for (int e = 0; e < 7; ++e) acc[k][e] += wk * g[e];
+                for (int e = 0; e < 7; ++e) sh[threadIdx.x * 7 + e] = acc[k][e];
+            __syncthreads();
+            if (int(threadIdx.x) < NP1 * 7) {
+                const int n = threadIdx.x / 7, cc = threadIdx.x % 7;
+                double s = 0.0;
+                for (int i = 0; i < c.Q; ++i) s += wl[n * c.Q + i] * sh[i * 7 + cc];
+                out[(n * NP1 + k) * 7 + cc] = s;
             }
+            __syncthreads();
         }
+    } else {
+        out = sh + size_t(c.Q) * NP1 * 7;      // [Q][NP1][7], then out[NP1][NP1][7]
+        for (int i = threadIdx.x; i < c.Q; i += 64) {
+            moment_point<NP1>(i, xm, pm, xn, pn, h, c, sq, wl, acc);
 #pragma unroll
-        for (int k = 0; k < NP1; ++k)
+            for (int k = 0; k < NP1; ++k)
 #pragma unroll
-            for (int e = 0; e < 7; ++e) sh[(size_t(i) * NP1 + k) * 7 + e] = acc[k][e];
+                for (int e = 0; e < 7; ++e) sh[(size_t(i) * NP1 + k) * 7 + e] = acc[k][e];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < NP1 * NP1 * 7; e += 64) {
+            const int n = e / (NP1 * 7), k = (e / 7) % NP1, cc = e % 7;
+            double s = 0.0;
+            for (int i = 0; i < c.Q; ++i) s += wl[n * c.Q + i] * sh[(size_t(i) * NP1 + k) * 7 + cc];
+            out[e] = s;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < NP1 * NP1 * 7; e += 64) {
-        const int n = e / (NP1 * 7), k = (e / 7) % NP1, cc = e % 7;
-        double s = 0.0;
-        for (int i = 0; i < c.Q; ++i) s += wq[i] * leg[n * c.Q + i] * sh[(size_t(i) * NP1 + k) * 7 + cc];
-        out[e] = s;
-    }
-    __syncthreads();
     // symmetric 3x3 index of (a, b) into the six beta components
     const int sym[3][3] = {{1, 2, 3}, {2, 4, 5}, {3, 5, 6}};
     for (int e = threadIdx.x; e < st * st; e += 64) {
@@ -115,22 +186,128 @@ __global__ __launch_bounds__(64) void k_theta(const double *__restrict__ X, cons
         const int n = row / 3, a = row % 3, k = col / 3, b = col % 3;
         const double *o = out + (n * NP1 + k) * 7;
         const double v = o[sym[a][b]] + (a == b ? o[0] : 0.0);
-        W[size_t(m * st + row) * c.D + size_t(mp * st + col)] = v;     // Theta^{n,k}_{m,mp}
-        W[size_t(mp * st + col) * c.D + size_t(m * st + row)] = v;     // Theta^{k,n}_{mp,m} = its transpose
+        // Theta^{n,k}_{m,mp} at (m st + row, mp st + col); its transpose,
+        // Theta^{k,n}_{mp,m}, is the mirror entry of the symmetric matrix
+        put_sym(W, c.nt, m * st + row, mp * st + col, v);
     }
 }
 
-// y = W x, one wave per row
-__global__ __launch_bounds__(256) void k_gemv(const double *__restrict__ W, const double *__restrict__ x,
-                                              double *__restrict__ y, int D)
+// Partial products of the packed symmetric matrix.  Workgroup w takes a
+// chunk of up to SG consecutive stored tiles of one tile row i, (i, j0) ..
+// (i, j0 + ng - 1) (ch[w] = (i, j0, ng, slot)); lane l owns column l of a
+// tile, wave v its rows 16 v .. 16 v + 15.  Row sums W_ij x_j build up in
+// registers over the chunk and go to part[slot][rows of block i], slot =
+// i + (j0 - i)/SG; column sums W_ij^T x_i of each off-diagonal tile go to
+// part[i][rows of block j].  For the rows of block b the slots 0 .. b - 1
+// hold column sums and b .. b + ceil((nt - b)/SG) - 1 row-sum chunks, each
+// written exactly once.  x entries beyond D read as zero.
+constexpr int SG = 8;          // tiles per workgroup
+
+__global__ __launch_bounds__(256) void k_symv(const double *__restrict__ W, const double *__restrict__ x,
+                                              double *__restrict__ part, const int4 *__restrict__ ch, int D, int nt)
 {
-    const int row = int(blockIdx.x) * 4 + int(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (row >= D) return;
-    const double *w = W + size_t(row) * D;
+    const int4 cw = ch[blockIdx.x];
+    const int i = cw.x, j0 = cw.y, ng = cw.z, slot = cw.w;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const size_t ntT = size_t(nt) * TS;
+    const double *tile = W + tile_base(i, j0, nt) + size_t(wv * 16) * TS + lane;
+    double xr[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int ri = i * TS + wv * 16 + k;
+        xr[k] = ri < D ? x[ri] : 0.0;
+    }
+    __shared__ double cs[SG][4][TS];
+    double rp[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) rp[k] = 0.0;
+    double v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = tile[k * TS];
+    for (int g = 0; g < ng; ++g) {
+        const int j = j0 + g;
+        const int cj = j * TS + lane;
+        const double xc = cj < D ? x[cj] : 0.0;
+        double col = 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            col = fma(v[k], xr[k], col);
+            rp[k] = fma(v[k], xc, rp[k]);
+        }
+        cs[g][wv][lane] = col;
+        if (g + 1 < ng) {
+            tile += TS * TS;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[k] = tile[k * TS];
+        }
+    }
+    // row sums over the lanes: halve the values held per lane while pairing
+    // lanes 32, 16, 8, 4 apart, then add over the last two lane bits; lane l
+    // ends with the sum of row 16 v + 8 b5 + 4 b4 + 2 b3 + b2 (b: bits of l)
+    const int b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const double send = b5 ? rp[k] : rp[k + 8], keep = b5 ? rp[k + 8] : rp[k];
+        rp[k] = keep + __shfl_xor(send, 32, 64);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double send = b4 ? rp[k] : rp[k + 4], keep = b4 ? rp[k + 4] : rp[k];
+        rp[k] = keep + __shfl_xor(send, 16, 64);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double send = b3 ? rp[k] : rp[k + 2], keep = b3 ? rp[k + 2] : rp[k];
+        rp[k] = keep + __shfl_xor(send, 8, 64);
+    }
+    {
+        const double send = b2 ? rp[0] : rp[1], keep = b2 ? rp[1] : rp[0];
+        rp[0] = keep + __shfl_xor(send, 4, 64);
+    }
+    double rs = rp[0] + __shfl_xor(rp[0], 2, 64);
+    rs = rs + __shfl_xor(rs, 1, 64);
+    if ((lane & 3) == 0) {
+        const int r = wv * 16 + 8 * b5 + 4 * b4 + 2 * b3 + b2;
+        part[size_t(slot) * ntT + size_t(i) * TS + r] = rs;
+    }
+    __syncthreads();
+    // column sums of the off-diagonal tiles, the four waves' parts in order
+    for (int g = wv; g < ng; g += 4) {
+        const int j = j0 + g;
+        if (j == i) continue;
+        part[size_t(i) * ntT + size_t(j) * TS + lane] = (cs[g][0][lane] + cs[g][1][lane]) + (cs[g][2][lane] + cs[g][3][lane]);
+    }
+}
+
+// y[R] = sum over the partial sums of row R (block b = R / TS): slots
+// 0 .. b + ceil((nt - b)/SG) - 1, in order
+__global__ __launch_bounds__(256) void k_symv_sum(const double *__restrict__ part, double *__restrict__ y, int D,
+                                                  int nt)
+{
+    const int r = int(blockIdx.x * blockDim.x + threadIdx.x);
+    if (r >= D) return;
+    const int b = r / TS, ns = b + (nt - b + SG - 1) / SG;
+    const size_t ntT = size_t(nt) * TS;
     double s = 0.0;
-    for (int j = lane; j < D; j += 64) s += w[j] * x[j];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) y[row] = s;
+    for (int t = 0; t < ns; ++t) s += part[size_t(t) * ntT + r];
+    y[r] = s;
+}
+
+// the chunks of k_symv for nt tiles per side: (i, j0, ng, slot) per workgroup
+static std::vector<int4> symv_chunks(int nt)
+{
+    std::vector<int4> out;
+    for (int i = 0; i < nt; ++i)
+        for (int j0 = i, c = 0; j0 < nt; j0 += SG, ++c) out.push_back(make_int4(i, j0, std::min(SG, nt - j0), i + c));
+    return out;
+}
+
+static size_t symv_chunk_count(int nt)
+{
+    size_t n = 0;
+    for (int i = 0; i < nt; ++i) n += size_t((nt - i + SG - 1) / SG);
+    return n;
 }
 
 // per-fiber 3x3 blocks: Lambda = d (I + p p^T) + 2 (I - p p^T), K = I + p p^T
@@ -429,8 +606,11 @@ struct sbf_ctx {
     int M = 0, Dmax = 0;
     // device
     double *X = nullptr, *pd = nullptr, *F = nullptr, *Mt = nullptr;
-    double *sq = nullptr, *wq = nullptr, *leg = nullptr;
-    double *W = nullptr;
+    double *sq = nullptr, *wl = nullptr;   // quadrature nodes; weights times P_k at the nodes
+    double *W = nullptr;                   // packed upper triangle of the moment matrix
+    double *part = nullptr;                // [nt][nt TS] partial sums of a product with W
+    int4 *chunks = nullptr;                // work list of the product kernel
+    unsigned nchunks = 0;
     double *x = nullptr, *b = nullptr, *r = nullptr, *w = nullptr, *y = nullptr, *kn = nullptr, *z = nullptr;
     double *t = nullptr, *u = nullptr;     // preconditioned vectors
     double *Vb = nullptr;                   // [restart + 1][D]
@@ -470,9 +650,10 @@ static inline unsigned nblk(size_t n) { return unsigned((n + 255) / 256); }
 template <int NP1>
 static hipError_t theta_t(sbf_ctx *c)
 {
-    const size_t lds = (size_t(c->c.Q) * NP1 * 7 + size_t(NP1) * NP1 * 7) * sizeof(double);
+    const size_t lds = ((c->c.Q <= 64 ? size_t(c->c.Q) * 7 : size_t(c->c.Q) * NP1 * 7) + size_t(NP1) * NP1 * 7) *
+                       sizeof(double);
     hipLaunchKernelGGL((k_theta<NP1>), dim3(unsigned(c->M) * unsigned(c->M)), dim3(64), lds, c->st, c->X, c->pd,
-                       c->c, c->sq, c->wq, c->leg, c->W);
+                       c->c, c->sq, c->wl, c->W);
     return hipGetLastError();
 }
 
@@ -530,7 +711,9 @@ static hipError_t gemv(sbf_ctx *c, const double *xin, double *yout)
 {
     hipError_t e = mark(c, 1, true);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gemv, dim3(unsigned((c->c.D + 3) / 4)), dim3(256), 0, c->st, c->W, xin, yout, c->c.D);
+    hipLaunchKernelGGL(k_symv, dim3(c->nchunks), dim3(256), 0, c->st, c->W, xin, c->part, c->chunks, c->c.D,
+                       c->c.nt);
+    hipLaunchKernelGGL(k_symv_sum, dim3(nblk(size_t(c->c.D))), dim3(256), 0, c->st, c->part, yout, c->c.D, c->c.nt);
     e = hipGetLastError();
     return e != hipSuccess ? e : mark(c, 1, false);
 }
@@ -672,7 +855,7 @@ static void release(sbf_ctx *c)
 {
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
-    double **bufs[] = {&c->X, &c->pd, &c->F, &c->Mt, &c->sq, &c->wq, &c->leg, &c->W, &c->x, &c->b, &c->r,
+    double **bufs[] = {&c->X, &c->pd, &c->F, &c->Mt, &c->sq, &c->wl, &c->W, &c->part, &c->x, &c->b, &c->r,
                        &c->w, &c->y, &c->kn, &c->z, &c->t, &c->u, &c->Vb, &c->H, &c->cs, &c->sn, &c->g, &c->h1, &c->h2,
                        &c->ys, &c->nrm, &c->res, &c->V, &c->Pd, &c->Vp, &c->Pp};
     for (double **b : bufs)
@@ -680,6 +863,10 @@ static void release(sbf_ctx *c)
             (void)hipFree(*b);
             *b = nullptr;
         }
+    if (c->chunks) {
+        (void)hipFree(c->chunks);
+        c->chunks = nullptr;
+    }
 }
 
 extern "C" {
@@ -712,7 +899,7 @@ lbm_status sbf_create(const sbf_params *p, sbf_ctx **out)
     const size_t lds = size_t(p->nmodes + 1) * 7 * (3 * size_t(p->nq) + size_t(p->nmodes + 1)) * sizeof(double);
     if (lds > 65536) return LBM_E_ARG;
     const double dmax = 3.0 * p->max_fibers * (p->nmodes + 1);
-    if (dmax * dmax > 4.0e10) return LBM_E_ARG;   // the moment matrix would exceed 320 GB
+    if (dmax * dmax > 6.0e10) return LBM_E_ARG;   // the packed moment matrix would exceed 240 GB
     sbf_ctx *c = new (std::nothrow) sbf_ctx;
     if (!c) return LBM_E_NOMEM;
     c->p = *p;
@@ -727,6 +914,7 @@ lbm_status sbf_create(const sbf_params *p, sbf_ctx **out)
     const int N = p->nmodes, Q = 3 * p->nq, Mx = p->max_fibers, R = p->gmres_restart;
     c->Dmax = 3 * Mx * (N + 1);
     const size_t Dm = size_t(c->Dmax);
+    const int ntm = (c->Dmax + TS - 1) / TS;
     c->c.N = N;
     c->c.Q = Q;
     c->c.L = p->length;
@@ -747,9 +935,10 @@ lbm_status sbf_create(const sbf_params *p, sbf_ctx **out)
     A(&c->Vp, 3 * size_t(Mx));
     A(&c->Pp, 3 * size_t(Mx));
     A(&c->sq, size_t(Q));
-    A(&c->wq, size_t(Q));
-    A(&c->leg, size_t(Q) * (N + 1));
-    A(&c->W, Dm * Dm);
+    A(&c->wl, size_t(Q) * (N + 1));
+    A(&c->W, packed_tiles(ntm) * TS * TS);
+    A(&c->part, size_t(ntm) * size_t(ntm) * TS);
+    if (e == hipSuccess) e = hipMalloc((void **)&c->chunks, std::max<size_t>(symv_chunk_count(ntm), 1) * sizeof(int4));
     for (double **v : {&c->x, &c->b, &c->r, &c->w, &c->y, &c->kn, &c->z, &c->t, &c->u}) A(v, Dm);
     A(&c->Vb, Dm * size_t(R + 1));
     A(&c->H, size_t(MAXR) * MAXR);
@@ -783,9 +972,11 @@ lbm_status sbf_create(const sbf_params *p, sbf_ctx **out)
                 p1 = p2;
             }
         }
+    std::vector<double> wl(leg.size());
+    for (int k = 0; k <= N; ++k)
+        for (int j = 0; j < Q; ++j) wl[size_t(k) * Q + j] = wq[j] * leg[size_t(k) * Q + j];
     if (hipMemcpyAsync(c->sq, sq.data(), Q * sizeof(double), hipMemcpyHostToDevice, c->st) != hipSuccess ||
-        hipMemcpyAsync(c->wq, wq.data(), Q * sizeof(double), hipMemcpyHostToDevice, c->st) != hipSuccess ||
-        hipMemcpyAsync(c->leg, leg.data(), leg.size() * sizeof(double), hipMemcpyHostToDevice, c->st) != hipSuccess ||
+        hipMemcpyAsync(c->wl, wl.data(), wl.size() * sizeof(double), hipMemcpyHostToDevice, c->st) != hipSuccess ||
         hipStreamSynchronize(c->st) != hipSuccess) {
         release(c);
         if (c->own_stream) (void)hipStreamDestroy(c->st);
@@ -822,12 +1013,18 @@ lbm_status sbf_set_fibers(sbf_ctx *c, int32_t m, const double *X, const double *
     c->M = m;
     c->c.M = m;
     c->c.D = 3 * m * (c->c.N + 1);
+    c->c.nt = (c->c.D + TS - 1) / TS;
     const size_t b3 = 3 * size_t(m) * sizeof(double);
     SCHK(c, hipMemcpyAsync(c->X, X, b3, hipMemcpyHostToDevice, c->st));
     SCHK(c, hipMemcpyAsync(c->pd, pn.data(), b3, hipMemcpyHostToDevice, c->st));
     SCHK(c, hipMemcpyAsync(c->F, F ? F : zero.data(), b3, hipMemcpyHostToDevice, c->st));
     SCHK(c, hipMemcpyAsync(c->Mt, M ? M : zero.data(), b3, hipMemcpyHostToDevice, c->st));
     SCHK(c, hipMemsetAsync(c->x, 0, size_t(c->c.D) * sizeof(double), c->st));
+    // the diagonal blocks and the padding of the packed matrix stay zero
+    SCHK(c, hipMemsetAsync(c->W, 0, packed_tiles(c->c.nt) * TS * TS * sizeof(double), c->st));
+    const std::vector<int4> chunks = symv_chunks(c->c.nt);
+    c->nchunks = unsigned(chunks.size());
+    SCHK(c, hipMemcpyAsync(c->chunks, chunks.data(), chunks.size() * sizeof(int4), hipMemcpyHostToDevice, c->st));
     SCHK(c, hipStreamSynchronize(c->st));
     c->first = true;
     c->solved = false;
