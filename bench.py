@@ -44,8 +44,8 @@ HBM_PEAK_GBS = 8000.0
 # scaled by the counters' readings for a plain copy of known size.  Valid only
 # for the sources it was measured on (SHA-1 of sweep.hip followed by
 # lbm_sweep_dev.h, below); otherwise reported null.
-SWEEP_TRAFFIC = {"sweep_sha1": "0fec919608e506aec09f60faf9299d3b7463f3eb",
-                 "bytes_per_launch": 2.5724e+09}
+SWEEP_TRAFFIC = {"sweep_sha1": "0faaf7ca95c52b06ca254e84f08c38c1ffc95d3a",
+                 "bytes_per_launch": 2.5726e+09}
 # algorithmic bytes per lattice update of the bulk sweep: 19 loads + 19
 # stores of the population type + the 1-byte cell flag
 BYTES_PER_LUP = {"f32": 19 * 4 * 2 + 1, "f16": 19 * 2 * 2 + 1, "bf16": 19 * 2 * 2 + 1,

@@ -27,8 +27,10 @@
  *
  * Conventions: every call returns lbm_status (include/lbm.h); the context
  * is not thread-safe; work is ordered on its HIP stream; host arrays are
- * FP64 [m][3] in the caller's memory.  sbf_solve synchronises the stream
- * once per GMRES iteration (the convergence test reads the residual).
+ * FP64 [m][3] in the caller's memory.  sbf_solve waits once per GMRES
+ * iteration for the previous iteration's residual (the convergence test)
+ * while the next iteration runs, so it may take one iteration more than
+ * the tolerance needs.
  */
 #ifndef SBF_H
 #define SBF_H

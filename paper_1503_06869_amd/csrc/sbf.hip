@@ -281,17 +281,30 @@ __global__ __launch_bounds__(256) void k_symv(const double *__restrict__ W, cons
 }
 
 // y[R] = sum over the partial sums of row R (block b = R / TS): slots
-// 0 .. b + ceil((nt - b)/SG) - 1, in order
+// 0 .. ns - 1, ns = b + ceil((nt - b)/SG).  One workgroup per block of 64
+// rows; wave w adds the slots w, w + 4, w + 8, ... (independent loads, four
+// accumulators), the four waves' sums are then added in order.
 __global__ __launch_bounds__(256) void k_symv_sum(const double *__restrict__ part, double *__restrict__ y, int D,
                                                   int nt)
 {
-    const int r = int(blockIdx.x * blockDim.x + threadIdx.x);
-    if (r >= D) return;
-    const int b = r / TS, ns = b + (nt - b + SG - 1) / SG;
+    const int b = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r = b * TS + lane;
+    const int ns = b + (nt - b + SG - 1) / SG;
     const size_t ntT = size_t(nt) * TS;
-    double s = 0.0;
-    for (int t = 0; t < ns; ++t) s += part[size_t(t) * ntT + r];
-    y[r] = s;
+    const double *pc = part + r;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int t = wv;
+    for (; t + 12 < ns; t += 16) {
+        a0 += pc[size_t(t) * ntT];
+        a1 += pc[size_t(t + 4) * ntT];
+        a2 += pc[size_t(t + 8) * ntT];
+        a3 += pc[size_t(t + 12) * ntT];
+    }
+    for (; t < ns; t += 4) a0 += pc[size_t(t) * ntT];
+    __shared__ double ws[4][TS];
+    ws[wv][lane] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (wv == 0 && r < D) y[r] = (ws[0][lane] + ws[1][lane]) + (ws[2][lane] + ws[3][lane]);
 }
 
 // the chunks of k_symv for nt tiles per side: (i, j0, ng, slot) per workgroup
@@ -616,6 +629,8 @@ struct sbf_ctx {
     double *Vb = nullptr;                   // [restart + 1][D]
     double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *h1 = nullptr, *h2 = nullptr, *ys = nullptr;
     double *nrm = nullptr, *res = nullptr;  // scalars
+    double *resh = nullptr;                 // pinned host copies of the residual, one per iteration
+    hipEvent_t rev[MAXR] = {};              // recorded after each copy
     double *V = nullptr, *Pd = nullptr, *Vp = nullptr, *Pp = nullptr;
     bool first = true, solved = false;
     // event timing: pairs recorded around the moment kernel and each GEMV
@@ -713,7 +728,7 @@ static hipError_t gemv(sbf_ctx *c, const double *xin, double *yout)
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_symv, dim3(c->nchunks), dim3(256), 0, c->st, c->W, xin, c->part, c->chunks, c->c.D,
                        c->c.nt);
-    hipLaunchKernelGGL(k_symv_sum, dim3(nblk(size_t(c->c.D))), dim3(256), 0, c->st, c->part, yout, c->c.D, c->c.nt);
+    hipLaunchKernelGGL(k_symv_sum, dim3(unsigned(c->c.nt)), dim3(256), 0, c->st, c->part, yout, c->c.D, c->c.nt);
     e = hipGetLastError();
     return e != hipSuccess ? e : mark(c, 1, false);
 }
@@ -811,15 +826,27 @@ static lbm_status do_solve(sbf_ctx *c)
                                c->res, i);
             hipLaunchKernelGGL(k_normalize, dim3(gd), dim3(256), 0, c->st, c->w, vn, c->nrm, D);
             SCHK(c, hipGetLastError());
+            // the residual of this iteration to pinned host memory; the host
+            // tests the previous iteration's while this one runs, so the
+            // stream never drains for the test (at most one iteration more
+            // than needed, which only lowers the residual)
+            SCHK(c, hipMemcpyAsync(c->resh + i, c->res, sizeof(double), hipMemcpyDeviceToHost, c->st));
+            SCHK(c, hipEventRecord(c->rev[i], c->st));
             ++it;
             k = i + 1;
-            double ri = 0.0;
-            if ((s = read_scalar(c, c->res, &ri)) != LBM_OK) return s;
-            rel = ri / bnorm;
-            if (rel <= c->p.gmres_tol) {
-                conv = true;
-                break;
+            if (i >= 1) {
+                SCHK(c, hipEventSynchronize(c->rev[i - 1]));
+                rel = c->resh[i - 1] / bnorm;
+                if (rel <= c->p.gmres_tol) {
+                    conv = true;
+                    break;
+                }
             }
+        }
+        if (!conv && k > 0) {
+            SCHK(c, hipEventSynchronize(c->rev[k - 1]));
+            rel = c->resh[k - 1] / bnorm;
+            conv = rel <= c->p.gmres_tol;
         }
         // x += B^-1 sum_j y_j V_j
         hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, c->st, c->H, c->g, c->ys, k);
@@ -867,6 +894,15 @@ static void release(sbf_ctx *c)
         (void)hipFree(c->chunks);
         c->chunks = nullptr;
     }
+    if (c->resh) {
+        (void)hipHostFree(c->resh);
+        c->resh = nullptr;
+    }
+    for (hipEvent_t &e : c->rev)
+        if (e) {
+            (void)hipEventDestroy(e);
+            e = nullptr;
+        }
 }
 
 extern "C" {
@@ -939,6 +975,8 @@ lbm_status sbf_create(const sbf_params *p, sbf_ctx **out)
     A(&c->W, packed_tiles(ntm) * TS * TS);
     A(&c->part, size_t(ntm) * size_t(ntm) * TS);
     if (e == hipSuccess) e = hipMalloc((void **)&c->chunks, std::max<size_t>(symv_chunk_count(ntm), 1) * sizeof(int4));
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->resh, MAXR * sizeof(double), hipHostMallocDefault);
+    for (int i = 0; i < MAXR && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&c->rev[i], hipEventDisableTiming);
     for (double **v : {&c->x, &c->b, &c->r, &c->w, &c->y, &c->kn, &c->z, &c->t, &c->u}) A(v, Dm);
     A(&c->Vb, Dm * size_t(R + 1));
     A(&c->H, size_t(MAXR) * MAXR);
