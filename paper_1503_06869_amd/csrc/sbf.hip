@@ -118,17 +118,99 @@ __device__ __forceinline__ void moment_point(int i, const double (&xm)[3], const
     }
 }
 
-// One 64-thread block per ordered pair (m, mp); blocks with m >= mp return
-// at once (the pair (mp, m) writes both blocks; the diagonal blocks stay at
-// the zero the packed matrix was cleared to).  Thread i < Q takes the outer
-// quadrature point s_i and sums over the inner points s'_j, per trial mode
-// k, the scalar part alpha and the six components of beta R R^T of
-// G = alpha I + beta R R^T; the outer sums with P_n(s_i) follow from LDS.
-// wl[k][j] = w_j P_k(s_j) (quadrature weight times Legendre value).
+// Moments for Q <= 64: workgroup b takes the pairs b PB .. b PB + PB - 1
+// of the list of pairs m < m' (row by row; the pair gives both blocks of W,
+// the diagonal blocks stay at the zero the packed matrix was cleared to).
+// Thread t serves pair slot t / Q and its outer quadrature point
+// s_i, i = t % Q: it sums over the inner points s'_j, per trial mode k, the
+// scalar part alpha and the six components of beta R R^T of
+// G = alpha I + beta R R^T (moment_point); the outer sums with P_n(s_i)
+// follow one trial mode k at a time through LDS ([Q][7] per pair, then
+// out[NP1][NP1][7] per pair).  wl[k][j] = w_j P_k(s_j).
+__device__ __forceinline__ void pair_of(long long p, int M, int &m, int &mp)
+{
+    // start(m) = m (2M - m - 1)/2 pairs precede row m
+    const double b = 2.0 * M - 1.0;
+    long long r = (long long)((b - sqrt(b * b - 8.0 * double(p))) * 0.5);
+    r = r < 0 ? 0 : (r > M - 2 ? M - 2 : r);
+    while (r > 0 && r * (2LL * M - r - 1) / 2 > p) --r;
+    while (r + 1 <= M - 2 && (r + 1) * (2LL * M - r - 2) / 2 <= p) ++r;
+    m = int(r);
+    mp = int(r + 1 + (p - r * (2LL * M - r - 1) / 2));
+}
+
+// symmetric 3x3 index of (a, b) into the six beta components
+__device__ __forceinline__ int sym_index(int a, int b) { return a == b ? (a == 0 ? 1 : (a == 1 ? 4 : 6)) : (a + b == 1 ? 2 : (a + b == 2 ? 3 : 5)); }
+
 template <int NP1>
-__global__ __launch_bounds__(64) void k_theta(const double *__restrict__ X, const double *__restrict__ p, Consts c,
-                                              const double *__restrict__ sq, const double *__restrict__ wl,
-                                              double *__restrict__ W)
+__global__ __launch_bounds__(256) void k_theta(const double *__restrict__ X, const double *__restrict__ p, Consts c,
+                                               const double *__restrict__ sq, const double *__restrict__ wl,
+                                               double *__restrict__ W, int PB, long long P)
+{
+    // LDS: wl [NP1][Q]; the pairs' (m, m') [PB][2]; per pair [Q][7] then out[NP1][NP1][7]
+    extern __shared__ double sh[];
+    const int st = 3 * NP1, per = c.Q * 7 + NP1 * NP1 * 7;
+    double *swl = sh;
+    int *pairs = reinterpret_cast<int *>(sh + NP1 * c.Q);
+    double *pd = sh + NP1 * c.Q + (PB + 1) / 2 * 2;
+    const int t = int(threadIdx.x), slot = t / c.Q, i = t % c.Q;
+    const long long p0 = (long long)blockIdx.x * PB;
+    const bool act = slot < PB && p0 + slot < P;
+    for (int e = t; e < NP1 * c.Q; e += int(blockDim.x)) swl[e] = wl[e];
+    int m = 0, mp = 0;
+    if (act) {
+        pair_of(p0 + slot, c.M, m, mp);
+        if (i == 0) {
+            pairs[2 * slot] = m;
+            pairs[2 * slot + 1] = mp;
+        }
+    }
+    double acc[NP1][7];
+    if (act) {
+        const double xm[3] = {X[3 * m], X[3 * m + 1], X[3 * m + 2]};
+        const double pm[3] = {p[3 * m], p[3 * m + 1], p[3 * m + 2]};
+        const double xn[3] = {X[3 * mp], X[3 * mp + 1], X[3 * mp + 2]};
+        const double pn[3] = {p[3 * mp], p[3 * mp + 1], p[3 * mp + 2]};
+        moment_point<NP1>(i, xm, pm, xn, pn, 0.5 * c.r * c.r, c, sq, wl, acc);
+    }
+#pragma unroll
+    for (int k = 0; k < NP1; ++k) {
+        if (act)
+#pragma unroll
+            for (int e = 0; e < 7; ++e) pd[size_t(slot) * per + i * 7 + e] = acc[k][e];
+        __syncthreads();
+        for (int e = t; e < PB * NP1 * 7; e += int(blockDim.x)) {
+            const int s2 = e / (NP1 * 7), r = e % (NP1 * 7), n = r / 7, cc = r % 7;
+            if (p0 + s2 >= P) continue;
+            const double *b = pd + size_t(s2) * per;
+            const double *w = swl + n * c.Q;
+            double sum = 0.0;
+            for (int q = 0; q < c.Q; ++q) sum += w[q] * b[q * 7 + cc];
+            pd[size_t(s2) * per + c.Q * 7 + (n * NP1 + k) * 7 + cc] = sum;
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < PB * st * st; e += int(blockDim.x)) {
+        const int s3 = e / (st * st), r = e % (st * st);
+        if (p0 + s3 >= P) continue;
+        const int m3 = pairs[2 * s3], mp3 = pairs[2 * s3 + 1];
+        const int row = r / st, col = r % st;
+        const int n = row / 3, a = row % 3, k = col / 3, b = col % 3;
+        const double *o = pd + size_t(s3) * per + c.Q * 7 + (n * NP1 + k) * 7;
+        const double v = o[sym_index(a, b)] + (a == b ? o[0] : 0.0);
+        // Theta^{n,k}_{m,mp} at (m st + row, mp st + col); its transpose,
+        // Theta^{k,n}_{mp,m}, is the mirror entry of the symmetric matrix
+        put_sym(W, c.nt, m3 * st + row, mp3 * st + col, v);
+    }
+}
+
+// Moments for Q > 64: one 64-thread block per ordered pair (m, mp), blocks
+// with m >= mp return at once; each thread takes outer points i, i + 64, ...
+// and keeps their sums in LDS ([Q][NP1][7], then out[NP1][NP1][7]).
+template <int NP1>
+__global__ __launch_bounds__(64) void k_theta_wide(const double *__restrict__ X, const double *__restrict__ p,
+                                                   Consts c, const double *__restrict__ sq,
+                                                   const double *__restrict__ wl, double *__restrict__ W)
 {
     const int m = int(blockIdx.x) / c.M, mp = int(blockIdx.x) % c.M;
     const int st = 3 * NP1;
@@ -140,54 +222,27 @@ __global__ __launch_bounds__(64) void k_theta(const double *__restrict__ X, cons
     const double pn[3] = {p[3 * mp], p[3 * mp + 1], p[3 * mp + 2]};
     const double h = 0.5 * c.r * c.r;
     double acc[NP1][7];
-    double *out;
-    if (c.Q <= 64) {
-        // one outer point per thread; the projections on P_n go one trial
-        // mode k at a time through a [Q][7] buffer (small LDS, more blocks
-        // per CU)
-        out = sh + size_t(c.Q) * 7;            // [Q][7], then out[NP1][NP1][7]
-        if (int(threadIdx.x) < c.Q) moment_point<NP1>(int(threadIdx.x), xm, pm, xn, pn, h, c, sq, wl, acc);
+    double *out = sh + size_t(c.Q) * NP1 * 7;
+    for (int i = threadIdx.x; i < c.Q; i += 64) {
+        moment_point<NP1>(i, xm, pm, xn, pn, h, c, sq, wl, acc);
 #pragma unroll
-        for (int k = 0; k < NP1; ++k) {
-            if (int(threadIdx.x) < c.Q)
+        for (int k = 0; k < NP1; ++k)
 #pragma unroll
-                for (int e = 0; e < 7; ++e) sh[threadIdx.x * 7 + e] = acc[k][e];
-            __syncthreads();
-            if (int(threadIdx.x) < NP1 * 7) {
-                const int n = threadIdx.x / 7, cc = threadIdx.x % 7;
-                double s = 0.0;
-                for (int i = 0; i < c.Q; ++i) s += wl[n * c.Q + i] * sh[i * 7 + cc];
-                out[(n * NP1 + k) * 7 + cc] = s;
-            }
-            __syncthreads();
-        }
-    } else {
-        out = sh + size_t(c.Q) * NP1 * 7;      // [Q][NP1][7], then out[NP1][NP1][7]
-        for (int i = threadIdx.x; i < c.Q; i += 64) {
-            moment_point<NP1>(i, xm, pm, xn, pn, h, c, sq, wl, acc);
-#pragma unroll
-            for (int k = 0; k < NP1; ++k)
-#pragma unroll
-                for (int e = 0; e < 7; ++e) sh[(size_t(i) * NP1 + k) * 7 + e] = acc[k][e];
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < NP1 * NP1 * 7; e += 64) {
-            const int n = e / (NP1 * 7), k = (e / 7) % NP1, cc = e % 7;
-            double s = 0.0;
-            for (int i = 0; i < c.Q; ++i) s += wl[n * c.Q + i] * sh[(size_t(i) * NP1 + k) * 7 + cc];
-            out[e] = s;
-        }
-        __syncthreads();
+            for (int e = 0; e < 7; ++e) sh[(size_t(i) * NP1 + k) * 7 + e] = acc[k][e];
     }
-    // symmetric 3x3 index of (a, b) into the six beta components
-    const int sym[3][3] = {{1, 2, 3}, {2, 4, 5}, {3, 5, 6}};
+    __syncthreads();
+    for (int e = threadIdx.x; e < NP1 * NP1 * 7; e += 64) {
+        const int n = e / (NP1 * 7), k = (e / 7) % NP1, cc = e % 7;
+        double s = 0.0;
+        for (int i = 0; i < c.Q; ++i) s += wl[n * c.Q + i] * sh[(size_t(i) * NP1 + k) * 7 + cc];
+        out[e] = s;
+    }
+    __syncthreads();
     for (int e = threadIdx.x; e < st * st; e += 64) {
         const int row = e / st, col = e % st;
         const int n = row / 3, a = row % 3, k = col / 3, b = col % 3;
         const double *o = out + (n * NP1 + k) * 7;
-        const double v = o[sym[a][b]] + (a == b ? o[0] : 0.0);
-        // Theta^{n,k}_{m,mp} at (m st + row, mp st + col); its transpose,
-        // Theta^{k,n}_{mp,m}, is the mirror entry of the symmetric matrix
+        const double v = o[sym_index(a, b)] + (a == b ? o[0] : 0.0);
         put_sym(W, c.nt, m * st + row, mp * st + col, v);
     }
 }
@@ -472,19 +527,33 @@ __global__ __launch_bounds__(256) void k_velocity(const double *__restrict__ z, 
 }
 
 // ------------------------------------------------------------------ GMRES pieces
-// h[j] = <V_j, w> for j < nj (block j), fixed summation order
+// h[j] = <V_j, w> for j < nj in two passes with a fixed summation order:
+// workgroup (j, p) sums chunk p of DP chunks of the vectors into
+// part[j DP + p]; k_dots_sum adds the DP partial sums of each j in order.
+constexpr int DP = 16;
+
 __global__ __launch_bounds__(256) void k_dots(const double *__restrict__ Vb, const double *__restrict__ w,
-                                              double *__restrict__ h, int D)
+                                              double *__restrict__ part, int D)
 {
-    const int j = blockIdx.x;
+    const int j = blockIdx.y, pc = blockIdx.x;
+    const int chunk = (D + DP - 1) / DP, e0 = pc * chunk, e1 = min(D, e0 + chunk);
     const double *v = Vb + size_t(j) * D;
     double s = 0.0;
-    for (int e = threadIdx.x; e < D; e += 256) s += v[e] * w[e];
+    for (int e = e0 + int(threadIdx.x); e < e1; e += 256) s += v[e] * w[e];
     __shared__ double red[4];
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) h[j] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x == 0) part[j * DP + pc] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(64) void k_dots_sum(const double *__restrict__ part, double *__restrict__ h, int nj)
+{
+    const int j = int(threadIdx.x);
+    if (j >= nj) return;
+    double s = 0.0;
+    for (int p = 0; p < DP; ++p) s += part[j * DP + p];
+    h[j] = s;
 }
 
 // w -= sum_{j < nj} h[j] V_j; acc[j] += h[j] (the column of H)
@@ -623,6 +692,7 @@ struct sbf_ctx {
     double *W = nullptr;                   // packed upper triangle of the moment matrix
     double *part = nullptr;                // [nt][nt TS] partial sums of a product with W
     int4 *chunks = nullptr;                // work list of the product kernel
+    double *dpart = nullptr;               // [MAXR][DP] partial dot products
     unsigned nchunks = 0;
     double *x = nullptr, *b = nullptr, *r = nullptr, *w = nullptr, *y = nullptr, *kn = nullptr, *z = nullptr;
     double *t = nullptr, *u = nullptr;     // preconditioned vectors
@@ -665,10 +735,32 @@ static inline unsigned nblk(size_t n) { return unsigned((n + 255) / 256); }
 template <int NP1>
 static hipError_t theta_t(sbf_ctx *c)
 {
-    const size_t lds = ((c->c.Q <= 64 ? size_t(c->c.Q) * 7 : size_t(c->c.Q) * NP1 * 7) + size_t(NP1) * NP1 * 7) *
-                       sizeof(double);
-    hipLaunchKernelGGL((k_theta<NP1>), dim3(unsigned(c->M) * unsigned(c->M)), dim3(64), lds, c->st, c->X, c->pd,
-                       c->c, c->sq, c->wl, c->W);
+    const int Q = c->c.Q;
+    if (c->M < 2) return hipSuccess;
+    if (Q > 64) {
+        const size_t lds = (size_t(Q) * NP1 * 7 + size_t(NP1) * NP1 * 7) * sizeof(double);
+        hipLaunchKernelGGL((k_theta_wide<NP1>), dim3(unsigned(c->M) * unsigned(c->M)), dim3(64), lds, c->st, c->X,
+                           c->pd, c->c, c->sq, c->wl, c->W);
+        return hipGetLastError();
+    }
+    // pairs per workgroup: the most lanes busy (PB Q over whole waves), then
+    // the most pairs, within 64 KiB of LDS
+    const size_t per_pair = (size_t(Q) * 7 + size_t(NP1) * NP1 * 7) * sizeof(double);
+    const size_t fixed = size_t(NP1) * Q * sizeof(double);   // the weights; (m, m') pairs below
+    int pb = 1;
+    double best = 0.0;
+    for (int k = 1; k * Q <= 256 && fixed + size_t((k + 1) / 2 * 2) * 8 + size_t(k) * per_pair <= 65536; ++k) {
+        const double use = double(k * Q) / double(((k * Q + 63) / 64) * 64);
+        if (use >= best) {
+            best = use;
+            pb = k;
+        }
+    }
+    const unsigned threads = unsigned(((pb * Q + 63) / 64) * 64);
+    const long long P = (long long)c->M * (c->M - 1) / 2;
+    const size_t lds = fixed + size_t((pb + 1) / 2 * 2) * sizeof(double) + size_t(pb) * per_pair;
+    hipLaunchKernelGGL((k_theta<NP1>), dim3(unsigned((P + pb - 1) / pb)), dim3(threads), lds, c->st, c->X, c->pd,
+                       c->c, c->sq, c->wl, c->W, pb, P);
     return hipGetLastError();
 }
 
@@ -752,11 +844,15 @@ static hipError_t precond(sbf_ctx *c, const double *in, double *out)
 }
 
 // nrm = <v, v>
-static hipError_t dot_self(sbf_ctx *c, const double *v)
+// h[0 .. nj) = <V_j, w> for the nj vectors starting at Vb
+static hipError_t dots(sbf_ctx *c, const double *Vb, const double *w, double *h, int nj)
 {
-    hipLaunchKernelGGL(k_dots, dim3(1), dim3(256), 0, c->st, v, v, c->nrm, c->c.D);
+    hipLaunchKernelGGL(k_dots, dim3(DP, unsigned(nj)), dim3(256), 0, c->st, Vb, w, c->dpart, c->c.D);
+    hipLaunchKernelGGL(k_dots_sum, dim3(1), dim3(64), 0, c->st, c->dpart, h, nj);
     return hipGetLastError();
 }
+
+static hipError_t dot_self(sbf_ctx *c, const double *v) { return dots(c, v, v, c->nrm, 1); }
 
 static lbm_status read_scalar(sbf_ctx *c, const double *dptr, double *out)
 {
@@ -816,9 +912,9 @@ static lbm_status do_solve(sbf_ctx *c)
             SCHK(c, precond(c, vi, c->t));
             SCHK(c, apply(c, c->t, c->w));
             // classical Gram-Schmidt, twice
-            hipLaunchKernelGGL(k_dots, dim3(unsigned(i + 1)), dim3(256), 0, c->st, c->Vb, c->w, c->h1, D);
+            SCHK(c, dots(c, c->Vb, c->w, c->h1, i + 1));
             hipLaunchKernelGGL(k_orth, dim3(gd), dim3(256), 0, c->st, c->Vb, c->w, c->h1, i + 1, D);
-            hipLaunchKernelGGL(k_dots, dim3(unsigned(i + 1)), dim3(256), 0, c->st, c->Vb, c->w, c->h2, D);
+            SCHK(c, dots(c, c->Vb, c->w, c->h2, i + 1));
             hipLaunchKernelGGL(k_orth, dim3(gd), dim3(256), 0, c->st, c->Vb, c->w, c->h2, i + 1, D);
             SCHK(c, hipGetLastError());
             SCHK(c, dot_self(c, c->w));
@@ -882,7 +978,7 @@ static void release(sbf_ctx *c)
 {
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
-    double **bufs[] = {&c->X, &c->pd, &c->F, &c->Mt, &c->sq, &c->wl, &c->W, &c->part, &c->x, &c->b, &c->r,
+    double **bufs[] = {&c->X, &c->pd, &c->F, &c->Mt, &c->sq, &c->wl, &c->W, &c->part, &c->dpart, &c->x, &c->b, &c->r,
                        &c->w, &c->y, &c->kn, &c->z, &c->t, &c->u, &c->Vb, &c->H, &c->cs, &c->sn, &c->g, &c->h1, &c->h2,
                        &c->ys, &c->nrm, &c->res, &c->V, &c->Pd, &c->Vp, &c->Pp};
     for (double **b : bufs)
@@ -974,6 +1070,7 @@ lbm_status sbf_create(const sbf_params *p, sbf_ctx **out)
     A(&c->wl, size_t(Q) * (N + 1));
     A(&c->W, packed_tiles(ntm) * TS * TS);
     A(&c->part, size_t(ntm) * size_t(ntm) * TS);
+    A(&c->dpart, size_t(MAXR) * DP);
     if (e == hipSuccess) e = hipMalloc((void **)&c->chunks, std::max<size_t>(symv_chunk_count(ntm), 1) * sizeof(int4));
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->resh, MAXR * sizeof(double), hipHostMallocDefault);
     for (int i = 0; i < MAXR && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&c->rev[i], hipEventDisableTiming);

@@ -53,10 +53,11 @@ def test_single_fiber_closed_forms_on_the_device():
     g.close()
 
 
-@pytest.mark.parametrize("N,nq", [(5, 16), (3, 8), (8, 10)])
+@pytest.mark.parametrize("N,nq", [(5, 16), (3, 8), (8, 10), (4, 24)])
 def test_random_fibers_match_the_reference(N, nq):
     """Eight fibers, random poses, forces and torques: Legendre
-    coefficients and velocities against the reference."""
+    coefficients and velocities against the reference (nq = 24: more than
+    64 quadrature points per fiber, the one-pair-per-workgroup kernel)."""
     rng = np.random.default_rng(40 + N)
     m, L, eps = 8, 48.0, 1 / 12.0
     sc = scenarios.sbf_cloud(seed=N, m=m, length=L, eps=eps, spacing=1.2)
