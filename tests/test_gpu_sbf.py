@@ -120,3 +120,54 @@ def test_cloud_beyond_one_restart_cycle():
     assert nm == 1 and tm > 0.0 and ng >= st["iterations"] and tg > 0.0
     assert np.abs(V - V_o).max() < 1e-10 * np.abs(V_o).max()
     assert np.abs(W - W_o).max() < 1e-10 * np.abs(W_o).max()
+
+
+def test_bench_cloud_sampled_fibers_full_size():
+    """The bench workload (1024 fibers, N = 5, 48 points, GMRES to 1e-10):
+    for sampled fibers the reference recomputes, from the device's
+    coefficients of all 1024 fibers, the interaction moments I_n = sum over
+    the 1023 partners of Theta^{n,k} f^k (Eq. Ucontr_def projected on P_n),
+    then the velocities of Eqs. xadot and padot and the residual of each
+    Legendre row of Eqs. sev_fils/extra_cond.  Checks the packed moment
+    matrix and its product at full size (288 tiles per side)."""
+    N, nq, tol = 5, 16, 1e-10
+    sc = scenarios.sbf_cloud(seed=0, m=1024)
+    L, eps = sc.length, sc.eps
+    g = _gpu_sbf(1024, L, eps, nmodes=N, nq=nq, gmres_tol=tol)
+    g.set_fibers(sc.X, sc.p, sc.F, sc.M)
+    g.solve()
+    V, W = g.velocities()
+    a = g.coefficients()
+    st = g.stats()
+    g.close()
+    ref = S.SBF(L, eps, N=N, nq=nq)
+    l, mu, d = ref.l, ref.mu, ref.d
+    Ln = S.kbar_eigenvalues(N)
+    m_all = sc.X.shape[0]
+    for m in (0, 517, 1023):
+        I = np.zeros((N + 1, 3))
+        for mp in range(m_all):
+            if mp == m:
+                continue
+            th = S.theta_pair(sc.X[m], sc.p[m], sc.X[mp], sc.p[mp], l, ref.r, N, nq)
+            fk = np.vstack([sc.F[mp] / (2 * l), a[mp]])            # [N + 1][3]
+            I += np.einsum("nkab,kb->na", th, fk)
+        p = sc.p[m]
+        pp = np.outer(p, p)
+        lam = d * (np.eye(3) + pp) + 2 * (np.eye(3) - pp)
+        K = np.eye(3) + pp
+        V_ref = (lam @ sc.F[m] + I[0]) / (8 * np.pi * mu * L)
+        W_ref = 3 / (2 * np.pi * mu * L ** 3) * (d * np.cross(sc.M[m], p) + (np.eye(3) - pp) @ (l * I[1]))
+        eV = np.abs(V[m] - V_ref).max() / np.abs(V_ref).max()
+        eW = np.abs(W[m] - W_ref).max() / max(np.abs(W_ref).max(), 1e-30)
+        res, scale = 0.0, 0.0
+        for n in range(2, N + 1):
+            cn = (2 * n + 1) / (2 * l)
+            self_term = (lam + Ln[n] * K) @ a[m][n - 1]
+            res = max(res, np.abs(self_term + cn * I[n]).max())
+            scale = max(scale, np.abs(cn * I[n]).max())
+        r1 = p @ ((lam + Ln[1] * K) @ a[m][0] + 1.5 / l * I[1])
+        print("fiber %d: velocity %.2e, rotation %.2e, Legendre rows %.2e of %.2e, p-row %.2e (GMRES %d it, %.1e)"
+              % (m, eV, eW, res, scale, abs(r1), st["iterations"], st["residual"]), flush=True)
+        assert eV < 1e-11 and eW < 1e-9
+        assert res < 1e-7 * scale and abs(r1) < 1e-7 * scale
