@@ -120,16 +120,25 @@ def test_stabilized_forced_particles_match_oracle(storage, tol_u, tol_ft, tol_m)
     g.close()
 
 
-@pytest.mark.parametrize("storage,z_periodic,tol", [("f32", True, 2e-6), ("f16", True, 5e-6),
-                                                    ("bf16", True, 3e-5), ("f32", False, 2e-6)])
-def test_bookkept_mean_equals_decoded_field_mean(storage, z_periodic, tol):
+@pytest.mark.parametrize("storage,z_periodic,tol,walls", [("f32", True, 2e-6, None), ("f16", True, 5e-6, None),
+                                                          ("bf16", True, 3e-5, None), ("f32", False, 2e-6, None),
+                                                          ("f32", True, 2e-6, "free-slip"),
+                                                          ("f32", False, 2e-6, "free-slip z")])
+def test_bookkept_mean_equals_decoded_field_mean(storage, z_periodic, tol, walls):
     """The mean the device keeps without a pass over the lattice equals the
     mean of the decoded velocity over the fluid cells, after steps with
-    moving fibers (and, without z periodicity, moving-wall bounce-back), and
+    moving fibers (and, without z periodicity, moving-wall bounce-back;
+    with free-slip walls, reflections that reverse one component), and
     again after a state change from the host (recomputed by a full pass)."""
     nx, ny, nz = 40, 36, 32
-    g = lbm.Context(nx, ny, nz, tau=0.8, z_periodic=z_periodic, wall_u=0.0 if z_periodic else 0.02,
-                    init_couette=not z_periodic, storage=storage, stabilize=True)
+    kw = {}
+    if walls == "free-slip":
+        kw = dict(x_walls="free-slip", y_walls="free-slip")
+    elif walls == "free-slip z":
+        kw = dict(x_walls="free-slip", z_free_slip=True)
+    g = lbm.Context(nx, ny, nz, tau=0.8, z_periodic=z_periodic,
+                    wall_u=0.0 if (z_periodic or walls) else 0.02,
+                    init_couette=not z_periodic and not walls, storage=storage, stabilize=True, **kw)
     for X, t, L, r, shape, F in FIBERS:
         q = scenarios.quat_from_axis(np.asarray(t) / np.linalg.norm(t))
         g.add_fiber(X, q, L, r, 1.0, shape=shape, force=F)
