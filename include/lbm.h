@@ -4,12 +4,14 @@
  * Ruede, "Two computational models for simulating the tumbling motion of
  * elongated particles in fluids" (Computers & Fluids, 2015), Sec. 4.
  *
- * One context holds one periodic-in-x,y shear cell: a D3Q19 lattice with
- * TRT or SRT collision (Sec. 4.1, Eqs. discrLBE-LBMStream), walls half-way
- * below z = 0 and above z = nz-1 that move at -U and +U along x (Eq.
- * LBMMovWall applied to a wall; or periodic z for tests), and rigid
- * cylindrical fibers coupled by moving-obstacle bounce-back and momentum
- * exchange (Sec. 4.2, Eqs. LBMMovWall, TransferredMomentum,
+ * One context holds one lattice: by default a periodic-in-x,y shear cell, a
+ * D3Q19 lattice with TRT or SRT collision (Sec. 4.1, Eqs. discrLBE-
+ * LBMStream), walls half-way below z = 0 and above z = nz-1 that move at -U
+ * and +U along x (Eq. LBMMovWall applied to a wall); optionally periodic z,
+ * resting no-slip or free-slip walls on the x and y faces and free-slip z
+ * walls (Eqs. BBBC, FreeSlipBC; lbm_params below), and rigid cylindrical or
+ * spherocylindrical fibers coupled by moving-obstacle bounce-back and
+ * momentum exchange (Sec. 4.2, Eqs. LBMMovWall, TransferredMomentum,
  * LBMhydrodynForce) to a rigid-body update on the device (Sec. 4.3).
  *
  * Conventions for every call:
