@@ -123,3 +123,47 @@ def test_body_force_along_free_slip_walls_accelerates_uniformly():
     # 19 roundings per step into the momentum
     assert abs(uz.mean() - g * (steps + 0.5)) < steps * 19 * 2.0 ** -54
     assert np.abs(u[:2]).max() < 1e-16
+
+
+def _quat_from_axis(t):
+    """A unit quaternion (w, x, y, z) turning e_x into the unit vector t
+    (test-local; only the axis matters for an axisymmetric fiber)."""
+    t = np.asarray(t, dtype=np.float64) / np.linalg.norm(t)
+    q = np.array([1.0 + t[0], 0.0, -t[2], t[1]])
+    return q / np.linalg.norm(q)
+
+
+@pytest.mark.parametrize("coupling", ["implicit", "explicit"])
+def test_particle_beside_a_free_slip_wall_equals_its_mirrored_pair(coupling):
+    """A forced spherocylinder two cells from a free-slip x wall moves
+    exactly like one of a mirror-symmetric pair in the periodic box of twice
+    the width: same populations in the first half, mirrored position and
+    velocity, angular velocity mirrored as a pseudovector (W_x kept, W_y and
+    W_z reversed), mirrored force and torque histories.  Pins the reflection
+    together with the particle coupling next to the wall (cell maps,
+    bounce-back, momentum exchange and rigid update near it)."""
+    nx, ny, nz, steps = 12, 14, 14, 60
+    X = np.array([4.25, 7.3, 6.7])
+    t = np.array([0.3, 0.8, 0.5])
+    F = np.array([2e-2, 1e-2, -1.5e-2])
+    L, r = 8.0, 2.0
+    mir = np.array([-1.0, 1.0, 1.0])
+    Xm = np.array([2 * nx - 1 - X[0], X[1], X[2]])
+    kw = dict(tau=0.8, z_periodic=True, coupling=coupling)
+    a = O.Sim(nx, ny, nz, x_walls="free-slip", **kw)
+    a.add_fiber(X, _quat_from_axis(t), L, r, 1.5, shape="spherocylinder", force=F)
+    b = O.Sim(2 * nx, ny, nz, **kw)
+    b.add_fiber(X, _quat_from_axis(t), L, r, 1.5, shape="spherocylinder", force=F)
+    b.add_fiber(Xm, _quat_from_axis(mir * t), L, r, 1.5, shape="spherocylinder", force=mir * F)
+    a.step(steps)
+    b.step(steps)
+    np.testing.assert_allclose(a.populations(), b.populations()[:, :, :, :nx], rtol=0, atol=1e-13)
+    ha, hb = a.history(), b.history()
+    np.testing.assert_allclose(ha[:, 0, :], hb[:, 0, :], rtol=0, atol=1e-12)
+    pv = np.array([1.0, -1.0, -1.0])               # pseudovector under the mirror x -> -x
+    np.testing.assert_allclose(hb[:, 1, 0:3], mir * hb[:, 0, 0:3], rtol=0, atol=1e-12)   # force
+    np.testing.assert_allclose(hb[:, 1, 3:6], pv * hb[:, 0, 3:6], rtol=0, atol=1e-12)    # torque
+    np.testing.assert_allclose(hb[:, 1, 13:16], mir * hb[:, 0, 13:16], rtol=0, atol=1e-13)  # V
+    np.testing.assert_allclose(hb[:, 1, 16:19], pv * hb[:, 0, 16:19], rtol=0, atol=1e-13)  # W
+    np.testing.assert_allclose(hb[:, 1, 6], 2 * nx - 1 - hb[:, 0, 6], rtol=0, atol=1e-12)  # x
+    assert np.abs(ha[-1, 0, 13:16]).max() > 1e-4      # the particle moves
