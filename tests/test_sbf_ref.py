@@ -179,3 +179,30 @@ def test_solution_satisfies_the_integral_equation():
             proj = (res * (Pn[n] * wsp)[:, None]).sum(0) * (2 * n + 1) / (2 * l)
             scale = np.abs(lhs).max()
             assert np.abs(proj).max() < 2e-5 * scale, (m, n, proj, scale)
+
+
+def test_time_stepping_is_second_order_against_the_exact_rotation():
+    """One fiber under a constant torque M perpendicular to its axis turns
+    about M at the constant rate 3 d |M| / (2 pi mu L^3) (Eq. SB_Torque; p
+    stays perpendicular to M).  The Adams-Bashforth-2 trajectory of `run`
+    (Euler start, p renormalised) converges to that exact rotation at second
+    order in dt (an Euler or a mis-weighted scheme gives first order)."""
+    L, eps, mu = 30.0, 1 / 10.0, 1.3
+    sb = S.SBF(L, eps, mu=mu, N=3, nq=4)
+    d = S.geometry_parameter(eps)
+    p0 = np.array([1.0, 0.0, 0.0])
+    M = np.array([0.0, 0.0, 2.0e3])
+    F = np.array([0.0, 0.5, 0.0])
+    rate = 3 * d * np.linalg.norm(M) / (2 * np.pi * mu * L ** 3)
+    T = 0.6 / rate                                   # a turn of 0.6 rad
+    errs = []
+    for n in (40, 80, 160):
+        Xs, ps = sb.run([[0, 0, 0]], [p0], [F], [M], T / n, n)
+        ang = rate * T
+        exact = np.array([np.cos(ang), np.sin(ang), 0.0])       # p turns about +z (M x p)
+        errs.append(np.linalg.norm(ps[-1, 0] - exact))
+        # force and axis stay in the plane z = 0, and so does the centre
+        assert abs(Xs[-1, 0, 2]) < 1e-12
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    print("AB2 errors", errs, "ratios", r1, r2)
+    assert 3.5 < r1 < 4.5 and 3.5 < r2 < 4.5
