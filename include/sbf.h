@@ -21,8 +21,8 @@
  * SBFGeomParam), U_m the velocity (times 8 pi mu) induced by the other
  * fibers.  The interaction integrals are taken with a composite three-point
  * Gauss rule on nq sub-intervals of each fiber (3 nq points per fiber; the
- * paper uses 48); time integration is Adams-Bashforth of second order (an
- * explicit second-order scheme with a fixed step, as the paper states),
+ * paper uses 48); time integration is Adams-Bashforth of second order (the
+ * paper asks only for an explicit method of second order with constant dt),
  * started with one Euler step, with p renormalised after every step.
  *
  * Conventions: every call returns lbm_status (include/lbm.h); the context

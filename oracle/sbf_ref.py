@@ -37,9 +37,10 @@ evaluated with composite three-point Gauss rules on nq sub-intervals of
 each fiber (the paper integrates the inner integral analytically with
 formulas it does not print; both integrals are taken by the same rule
 here).  The linear system is solved directly (numpy), the library uses
-GMRES as the paper does.  Time integration: the paper uses an explicit
-second-order scheme with a fixed step; this reference uses Adams-Bashforth
-of order two with one Euler step to start, and renormalises p.
+GMRES as the paper does.  Time integration: the paper names only an
+explicit method of second order with constant dt; this reference uses
+Adams-Bashforth of order two with one Euler step to start, and renormalises
+p.
 """
 import numpy as np
 
