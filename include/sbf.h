@@ -93,7 +93,9 @@ lbm_status sbf_get_coefficients(sbf_ctx *ctx, double *a);
 
 /* n time steps of size dt > 0: solve, then Adams-Bashforth 2
  * x += dt (3/2 v_n - 1/2 v_{n-1}) (Euler for the first step after
- * sbf_set_fibers), p likewise and renormalised. */
+ * sbf_set_fibers), p likewise and renormalised.  From the third step on,
+ * GMRES starts from the linear extrapolation of the two previous steps'
+ * coefficients. */
 lbm_status sbf_step(sbf_ctx *ctx, int64_t n, double dt);
 
 /* Current centres and directions, host [m][3] each (either may be NULL). */

@@ -653,6 +653,17 @@ __global__ __launch_bounds__(256) void k_add(const double *a, const double *b, d
     if (e < D) out[e] = a[e] + b[e];
 }
 
+// GMRES start of a time step: the linear extrapolation 2 a_n - a_{n-1} of
+// the last two solutions (x holds a_n, xh a_{n-1}); xh takes a_n
+__global__ __launch_bounds__(256) void k_extrap(double *__restrict__ x, double *__restrict__ xh, int D)
+{
+    const int e = int(blockIdx.x * blockDim.x + threadIdx.x);
+    if (e >= D) return;
+    const double a = x[e];
+    x[e] = 2.0 * a - xh[e];
+    xh[e] = a;
+}
+
 // Adams-Bashforth 2 (Euler when first), p renormalised
 __global__ __launch_bounds__(256) void k_advance(double *__restrict__ X, double *__restrict__ p,
                                                  const double *__restrict__ V, const double *__restrict__ Pd,
@@ -696,6 +707,8 @@ struct sbf_ctx {
     unsigned nchunks = 0;
     double *x = nullptr, *b = nullptr, *r = nullptr, *w = nullptr, *y = nullptr, *kn = nullptr, *z = nullptr;
     double *t = nullptr, *u = nullptr;     // preconditioned vectors
+    double *xh = nullptr;                   // the solution of the previous time step
+    int nsol = 0;                           // solutions of time steps since the fibers were set
     double *Vb = nullptr;                   // [restart + 1][D]
     double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *h1 = nullptr, *h2 = nullptr, *ys = nullptr;
     double *nrm = nullptr, *res = nullptr;  // scalars
@@ -978,7 +991,7 @@ static void release(sbf_ctx *c)
 {
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
-    double **bufs[] = {&c->X, &c->pd, &c->F, &c->Mt, &c->sq, &c->wl, &c->W, &c->part, &c->dpart, &c->x, &c->b, &c->r,
+    double **bufs[] = {&c->X, &c->pd, &c->F, &c->Mt, &c->sq, &c->wl, &c->W, &c->part, &c->dpart, &c->x, &c->xh, &c->b, &c->r,
                        &c->w, &c->y, &c->kn, &c->z, &c->t, &c->u, &c->Vb, &c->H, &c->cs, &c->sn, &c->g, &c->h1, &c->h2,
                        &c->ys, &c->nrm, &c->res, &c->V, &c->Pd, &c->Vp, &c->Pp};
     for (double **b : bufs)
@@ -1074,7 +1087,7 @@ lbm_status sbf_create(const sbf_params *p, sbf_ctx **out)
     if (e == hipSuccess) e = hipMalloc((void **)&c->chunks, std::max<size_t>(symv_chunk_count(ntm), 1) * sizeof(int4));
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->resh, MAXR * sizeof(double), hipHostMallocDefault);
     for (int i = 0; i < MAXR && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&c->rev[i], hipEventDisableTiming);
-    for (double **v : {&c->x, &c->b, &c->r, &c->w, &c->y, &c->kn, &c->z, &c->t, &c->u}) A(v, Dm);
+    for (double **v : {&c->x, &c->xh, &c->b, &c->r, &c->w, &c->y, &c->kn, &c->z, &c->t, &c->u}) A(v, Dm);
     A(&c->Vb, Dm * size_t(R + 1));
     A(&c->H, size_t(MAXR) * MAXR);
     for (double **v : {&c->cs, &c->sn, &c->g, &c->h1, &c->h2, &c->ys}) A(v, size_t(MAXR + 1));
@@ -1164,6 +1177,7 @@ lbm_status sbf_set_fibers(sbf_ctx *c, int32_t m, const double *X, const double *
     c->first = true;
     c->solved = false;
     c->steps = 0;
+    c->nsol = 0;
     return LBM_OK;
 }
 
@@ -1205,8 +1219,18 @@ lbm_status sbf_step(sbf_ctx *c, int64_t n, double dt)
     if (n < 0 || !(dt > 0.0)) return sfail(c, LBM_E_ARG, "sbf_step: n >= 0 and dt > 0 required");
     if (c->M < 1) return sfail(c, LBM_E_STATE, "sbf_step: no fibers set");
     for (int64_t s = 0; s < n; ++s) {
+        // GMRES starts from the extrapolation of the last two solutions
+        // (from the last one after the first step)
+        const unsigned gd = nblk(size_t(c->c.D));
+        if (c->nsol >= 2) {
+            hipLaunchKernelGGL(k_extrap, dim3(gd), dim3(256), 0, c->st, c->x, c->xh, c->c.D);
+            SCHK(c, hipGetLastError());
+        } else if (c->nsol == 1) {
+            SCHK(c, hipMemcpyAsync(c->xh, c->x, size_t(c->c.D) * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+        }
         lbm_status st = do_solve(c);
         if (st != LBM_OK) return st;
+        c->nsol += 1;
         hipLaunchKernelGGL(k_advance, dim3(nblk(size_t(c->M))), dim3(256), 0, c->st, c->X, c->pd, c->V, c->Pd,
                            c->Vp, c->Pp, c->M, dt, c->first ? 1 : 0);
         SCHK(c, hipGetLastError());
