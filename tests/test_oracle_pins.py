@@ -791,6 +791,42 @@ def test_uncovered_cells_are_refilled_with_equilibrium():
         np.testing.assert_array_equal(f[:, z, y, x], fe)
 
 
+def test_refill_uses_each_old_owners_rigid_motion_at_its_old_pose():
+    """Sec. 4.2 with two moving fibers: each uncovered cell is refilled with
+    f_eq(rho0, u_s) where u_s = V + W x (x - X) is the rigid-body velocity
+    of the fiber that covered the cell, taken with that fiber's motion and
+    centre before the step.  Fiber 0 only translates; fiber 1 translates and
+    spins about z, so the rotational part, its sign and the choice of the
+    old centre (against the new one: a difference W x V) all show."""
+    n = 24
+    s = O.Sim(n, n, n, tau=0.8, z_periodic=True)
+    qx = np.array([1.0, 0, 0, 0])                       # axis along x
+    X = [np.array([8.0, 8.0, 7.0]), np.array([13.0, 14.0, 16.0])]
+    V = [np.array([0.3, 0.0, 0.0]), np.array([0.2, 0.1, 0.0])]
+    W = [np.zeros(3), np.array([0.0, 0.0, 0.08])]
+    for k in range(2):
+        s.add_fiber(X[k], qx, 6.0, 1.5, 1.0, V=V[k], W=W[k])
+    q1 = np.array([np.cos(0.04), 0.0, 0.0, np.sin(0.04)])   # 0.08 rad about z
+    s.set_kinematics(0, np.r_[X[0] + V[0], qx, V[0], W[0]][None, :])
+    s.set_kinematics(1, np.r_[X[1] + V[1], q1, V[1], W[1]][None, :])
+    _, _, fl0, pid0 = s.fields()
+    s.step(1)
+    _, _, fl1, _ = s.fields()
+    f = s.populations()
+    unc = (fl0 == 1) & (fl1 == 0)
+    counts = [int((unc & (pid0 == k)).sum()) for k in range(2)]
+    assert min(counts) > 0, counts
+    worst_new_centre = 0.0
+    for z, y, x in zip(*np.nonzero(unc)):
+        p = pid0[z, y, x]
+        r = np.array([x, y, z], dtype=np.float64) - X[p]
+        us = V[p] + np.cross(W[p], r)
+        np.testing.assert_allclose(f[:, z, y, x], O.feq(1.0, 1.0, us), rtol=0, atol=1e-15)
+        us_new = V[p] + np.cross(W[p], r - V[p])      # the new centre instead
+        worst_new_centre = max(worst_new_centre, np.abs(O.feq(1.0, 1.0, us_new) - f[:, z, y, x]).max())
+    assert worst_new_centre > 1e-4        # the pin tells the two poses apart
+
+
 # ---------------------------------------------------------------- P15 Jeffery
 def test_two_step_average_removes_the_period_two_torque_mode():
     """At density ratio 1 and tau = 0.6 the implicit coupling without the
