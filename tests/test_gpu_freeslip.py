@@ -36,18 +36,20 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("collision", ["trt", "srt"])
 @pytest.mark.parametrize("storage,tol", [("f32", 2e-7), ("f64", 1e-14)])
 @pytest.mark.parametrize("case", list(CASES))
-def test_free_slip_random_state_matches_oracle(case, storage, tol):
+def test_free_slip_random_state_matches_oracle(case, storage, tol, collision):
     """A random state in a 20 x 18 x 16 box after 1, 2 and 41 steps (the
-    populations read back in the swapped layout after odd counts)."""
+    populations read back in the swapped layout after odd counts), with the
+    two-relaxation-time and the single-relaxation-time collision."""
     nx, ny, nz = 20, 18, 16
     kw = CASES[case]
     _, w, _ = O.lattice()
     rng = np.random.default_rng(len(case))
     f0 = w[:, None, None, None] * (1.0 + 0.05 * rng.standard_normal((19, nz, ny, nx)))
-    g = lbm.Context(nx, ny, nz, tau=0.7, storage=storage, **kw)
-    o = O.Sim(nx, ny, nz, tau=0.7, **kw)
+    g = lbm.Context(nx, ny, nz, tau=0.7, storage=storage, collision=collision, **kw)
+    o = O.Sim(nx, ny, nz, tau=0.7, srt=(collision == "srt"), **kw)
     g.set_populations(to_lib_order(f0))
     o.set_populations(f0)
     done = 0
@@ -56,7 +58,7 @@ def test_free_slip_random_state_matches_oracle(case, storage, tol):
         o.step(n - done)
         done = n
         d = np.abs(to_oracle_order(g.populations()) - o.populations()).max()
-        print("%s %s step %d: max |df| %.3g" % (case, storage, n, d), flush=True)
+        print("%s %s %s step %d: max |df| %.3g" % (case, storage, collision, n, d), flush=True)
         assert d < tol
     g.close()
 
