@@ -237,8 +237,10 @@ def in_envelope(norm, X):
 
 
 def relative_errors(Y, P):
-    """Mean over samples of |target - prediction| for force and torque
-    components, relative to the mean |target| (prediction 0 = no closure)."""
+    """Mean over samples of |target - prediction| for the force and for the
+    torque (in the targets' scaled units).  With prediction 0 (no closure)
+    this is the mean |target|, so the ratio of two calls is the relative
+    error."""
     eF = np.linalg.norm(Y[:, 0:3] - P[:, 0:3], axis=1).mean()
     eM = np.linalg.norm(Y[:, 3:6] - P[:, 3:6], axis=1).mean()
     return eF, eM
