@@ -33,6 +33,11 @@ static const double W0 = 1.0 / 3.0, W1 = 1.0 / 18.0, W2 = 1.0 / 36.0;
 
 static double weight(int q) { return q == 0 ? W0 : (q <= 6 ? W1 : W2); }
 
+/* Planted mistakes for the tests that show each pin can fail (0: none).   */
+/* Every site computes the correct expression unchanged when the code is 0. */
+static int g_mutation = 0;
+void or_set_mutation(int code) { g_mutation = code; }
+
 /* opposite direction: c_opp(q) = -c_q, found by search (no index tricks) */
 static int opposite(int q)
 {
@@ -65,7 +70,7 @@ void or_feq(double rho, double rho0, const double u[3], double *feq)
     double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     for (int q = 0; q < Q; ++q) {
         double cu = CV[q][0] * u[0] + CV[q][1] * u[1] + CV[q][2] * u[2];
-        feq[q] = weight(q) * (rho + rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+        feq[q] = weight(q) * (rho + rho0 * (3.0 * cu + (g_mutation == 6 ? 3.0 : 4.5) * cu * cu - 1.5 * uu));
     }
 }
 
@@ -95,18 +100,19 @@ void or_collide_cell_shift(const double *f, double rho0, double omega_e, double 
         for (int k = 0; k < 3; ++k) j[k] += CV[q][k] * f[q];
     }
     double u[3];
-    for (int k = 0; k < 3; ++k) u[k] = j[k] / rho0 + 0.5 * g[k] - ubar[k];
+    for (int k = 0; k < 3; ++k)
+        u[k] = g_mutation == 14 ? j[k] / rho0 + 0.5 * g[k] + ubar[k] : j[k] / rho0 + 0.5 * g[k] - ubar[k];
     double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     for (int q = 0; q < Q; ++q) {
         int qb = opposite(q);
         double w = weight(q);
         double cu = CV[q][0] * u[0] + CV[q][1] * u[1] + CV[q][2] * u[2];
         double cg = CV[q][0] * g[0] + CV[q][1] * g[1] + CV[q][2] * g[2];
-        double feq_e = w * (rho - 1.5 * rho0 * uu + 4.5 * rho0 * cu * cu);
+        double feq_e = w * (rho - 1.5 * rho0 * uu + (g_mutation == 7 ? 0.0 : 4.5) * rho0 * cu * cu);
         double feq_o = w * 3.0 * rho0 * cu;
         double fe = 0.5 * (f[q] + f[qb]);
         double fo = 0.5 * (f[q] - f[qb]);
-        fpost[q] = f[q] - omega_e * (fe - feq_e) - omega_o * (fo - feq_o)
+        fpost[q] = f[q] - omega_e * (fe - feq_e) - (g_mutation == 5 ? omega_e : omega_o) * (fo - feq_o)
                  + (1.0 - 0.5 * omega_o) * 3.0 * w * rho0 * cg;
     }
 }
@@ -234,8 +240,6 @@ void or_map_shapes(int nx, int ny, int nz, int zper, int np, const double *X, co
 /* ------------------------------------------------------------------------ */
 /* Planted mistakes for the tests that show each pin can fail (0: none).     */
 /* Only the pins' own tests set this; every other caller leaves it at 0.    */
-static int g_mutation = 0;
-void or_set_mutation(int code) { g_mutation = code; }
 
 static void quat_mul(const double a[4], const double b[4], double out[4])
 {
@@ -783,12 +787,13 @@ static void one_step(or_sim *s)
                     if (wz && !p->z_free_slip) {
                         /* moving wall, half-way: bottom -U, top +U along x */
                         double uw = (yz < 0) ? -p->wall_u : p->wall_u;
-                        *slot(s->fb, s, qb, c) = ft - 6.0 * w * rho0 * (CV[q][0] * uw);
+                        double mw = 6.0 * w * rho0 * (CV[q][0] * uw);
+                        *slot(s->fb, s, qb, c) = g_mutation == 8 ? ft + mw : ft - mw;
                         continue;
                     }
                     if ((wx && p->x_walls == 1) || (wy && p->y_walls == 1)) {
                         /* resting no-slip wall in x or y, half-way (Eq. BBBC) */
-                        *slot(s->fb, s, qb, c) = ft;
+                        *slot(s->fb, s, g_mutation == 15 ? q : qb, c) = ft;
                         continue;
                     }
                     if (wx || wy || wz) {
@@ -797,7 +802,7 @@ static void one_step(or_sim *s)
                            neighbour along the remaining components */
                         int e[3] = {wx ? -CV[q][0] : CV[q][0], wy ? -CV[q][1] : CV[q][1],
                                     wz ? -CV[q][2] : CV[q][2]};
-                        int qr = direction_of(e);
+                        int qr = g_mutation == 12 ? qb : direction_of(e);
                         int dx = wx ? x : yx, dy = wy ? y : yy, dz = wz ? z : wrapi(yz, nz);
                         *slot(s->fb, s, qr, cidx(s, dx, dy, dz)) = ft;
                         continue;
@@ -808,7 +813,7 @@ static void one_step(or_sim *s)
                         double us[3];
                         surface_velocity(s, s->fib[s->pid[cy]].st, yx, yy, yz, us);
                         double cu = CV[q][0] * us[0] + CV[q][1] * us[1] + CV[q][2] * us[2];
-                        *slot(s->fb, s, qb, c) = ft - 6.0 * w * rho0 * cu;
+                        *slot(s->fb, s, qb, c) = g_mutation == 9 ? ft : ft - 6.0 * w * rho0 * cu;
                     } else {
                         *slot(s->fb, s, q, cy) = ft;
                     }
@@ -846,7 +851,7 @@ static void one_step(or_sim *s)
                     surface_velocity(s, f->st, yx, yy, yz, us);
                     double cu = CV[q][0] * us[0] + CV[q][1] * us[1] + CV[q][2] * us[2];
                     double ftq = *slot(s->ft, s, q, c);
-                    double mag = 2.0 * ftq - 6.0 * weight(q) * rho0 * cu;
+                    double mag = (g_mutation == 10 ? 1.0 : 2.0) * ftq - 6.0 * weight(q) * rho0 * cu;
                     double dF[3] = {mag * CV[q][0], mag * CV[q][1], mag * CV[q][2]};
                     double r[3];
                     r[0] = min_image(yx - f->st[0], nx, 1);
@@ -855,9 +860,15 @@ static void one_step(or_sim *s)
                     double *acc = part + ((size_t)z * nfb + ip) * 39;
                     /* direct formula, every term at the old velocity */
                     for (int k = 0; k < 3; ++k) acc[k] += dF[k];
-                    acc[3] += r[1] * dF[2] - r[2] * dF[1];
-                    acc[4] += r[2] * dF[0] - r[0] * dF[2];
-                    acc[5] += r[0] * dF[1] - r[1] * dF[0];
+                    if (g_mutation == 11) {
+                        acc[3] += dF[1] * r[2] - dF[2] * r[1];
+                        acc[4] += dF[2] * r[0] - dF[0] * r[2];
+                        acc[5] += dF[0] * r[1] - dF[1] * r[0];
+                    } else {
+                        acc[3] += r[1] * dF[2] - r[2] * dF[1];
+                        acc[4] += r[2] * dF[0] - r[0] * dF[2];
+                        acc[5] += r[0] * dF[1] - r[1] * dF[0];
+                    }
                     /* split for the implicit update: velocity-free part and the  */
                     /* matrices of the part linear in u_s = V + W x r            */
                     double m0 = 2.0 * ftq;
@@ -999,7 +1010,7 @@ static void one_step(or_sim *s)
                     int po = s->pid[c];
                     if (po >= 0 && pn[c] < 0) {
                         double us[3], feq[Q];
-                        surface_velocity(s, old + 16 * po, x, y, z, us);
+                        surface_velocity(s, g_mutation == 13 ? s->fib[po].st : old + 16 * po, x, y, z, us);
                         or_feq(rho0, rho0, us, feq);
                         for (int q = 0; q < Q; ++q) *slot(s->fb, s, q, c) = feq[q];
                     }

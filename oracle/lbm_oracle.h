@@ -134,7 +134,15 @@ int64_t or_overlaps(const or_sim *s);
 void    or_get_exchange_sums(const or_sim *s, double *out);
 /* test hook: plant a known mistake (1: B instead of B^T in the torque row of
    the implicit solve; 2: -C instead of C there; 3: B accumulated transposed;
-   4: the two-step mean without its factor 1/2); 0 restores the oracle */
+   4: the two-step mean without its factor 1/2; 5: the odd part relaxed with
+   omega_e; 6: 3 instead of 9/2 for (c.u)^2 in f_eq; 7: the collision's even
+   equilibrium without its (c.u)^2 term; 8: the moving-wall term with the
+   wrong sign; 9: fiber bounce-back without the surface velocity; 10: the
+   link force without its factor 2; 11: the torque as dF x r; 12: free-slip
+   walls bouncing back; 13: the refill at the new pose and motion; 14: the
+   stabilization shift added; 15: resting side walls returning the
+   population in its own direction); 0 restores the oracle, whose results are
+   then bit-identical to a build without the hook */
 void    or_set_mutation(int code);
 /* OpenMP threads of the following steps (timing on one core or all), and
    the current count */

@@ -1,0 +1,51 @@
+"""Each pin can fail: a plausible mistake planted in the LBM oracle's core
+steps (collision, equilibrium, moving walls, fiber bounce-back, momentum
+exchange, free-slip reflection, refill, stabilization, side walls) makes
+the named pins fail (the rest of the suite runs every pin with none
+planted).  The planted mistakes of the coupled rigid-body update are in
+test_oracle_coupling_pins.py."""
+import pytest
+
+from oracle import pyoracle as O
+
+import test_oracle_freeslip as FS
+import test_oracle_pins as P
+
+MUTATIONS = {
+    5: ("odd part relaxed with omega_e",
+        [P.test_trt_rates_act_on_even_and_odd_parts, P.test_collision_conserves_mass_and_momentum,
+         lambda: P.test_stabilized_total_momentum_decays_by_one_minus_omega_odd(0.8, False)]),
+    6: ("3 instead of 9/2 for (c.u)^2 in f_eq",
+        [P.test_equilibrium_moments, P.test_equilibrium_even_odd_split]),
+    7: ("collision's even equilibrium without (c.u)^2",
+        [P.test_collision_conserves_mass_and_momentum, lambda: P.test_mass_conservation(False, 0.01),
+         P.test_closed_box_conserves_mass_and_stops]),
+    8: ("moving-wall term with the wrong sign", [P.test_couette_closed_form]),
+    9: ("fiber bounce-back without the surface velocity",
+        [P.test_external_force_enters_the_momentum_budget,
+         P.test_stabilized_momentum_budget_with_a_forced_particle]),
+    10: ("link force without its factor 2",
+         [P.test_external_force_enters_the_momentum_budget, P.test_drag_balance_fixed_fiber]),
+    11: ("torque as dF x r", [P.test_force_and_torque_signs]),
+    12: ("free-slip walls bouncing back",
+         [lambda: FS.test_free_slip_box_is_half_of_the_mirrored_periodic_box("x", False),
+          FS.test_body_force_along_free_slip_walls_accelerates_uniformly]),
+    13: ("refill at the new pose and motion", [P.test_refill_uses_each_old_owners_rigid_motion_at_its_old_pose]),
+    14: ("stabilization shift added instead of subtracted",
+         [lambda: P.test_stabilized_total_momentum_decays_by_one_minus_omega_odd(0.8, False),
+          P.test_stabilized_momentum_with_body_force_reaches_its_fixed_point]),
+    15: ("resting side wall returns the population in its own direction",
+         [P.test_closed_box_conserves_mass_and_stops]),
+}
+
+
+@pytest.mark.parametrize("code", sorted(MUTATIONS))
+def test_pins_fail_on_planted_mistakes(code):
+    what, pins = MUTATIONS[code]
+    try:
+        O.set_mutation(code)
+        for pin in pins:
+            with pytest.raises(AssertionError):
+                pin()
+    finally:
+        O.set_mutation(0)
