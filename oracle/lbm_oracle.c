@@ -134,6 +134,11 @@ void or_fiber_axis(const double q[4], double t[3])
 {
     double w = q[0], x = q[1], y = q[2], z = q[3];
     t[0] = 1.0 - 2.0 * (y * y + z * z);
+    if (g_mutation == 17) {     /* the axis of the conjugate rotation */
+        t[1] = 2.0 * (x * y - w * z);
+        t[2] = 2.0 * (x * z + w * y);
+        return;
+    }
     t[1] = 2.0 * (x * y + w * z);
     t[2] = 2.0 * (x * z - w * y);
 }
@@ -166,11 +171,12 @@ int or_cell_inside_shape(const double c[3], const double X[3], const double t[3]
     double hl = 0.5 * length;
     double q = dd - a * a, r2 = radius * radius;
     if (shape == 1) {
-        double e = fabs(a) - (hl - radius);
+        double e = fabs(a) - (g_mutation == 19 ? hl : hl - radius);
         if (e <= 0.0) return q <= r2;
         return q + e * e <= r2;
     }
-    return (a * a <= hl * hl) && (q <= r2);
+    double hb = g_mutation == 16 ? length : hl;
+    return (a * a <= hb * hb) && (q <= r2);
 }
 
 int or_cell_inside(const double c[3], const double X[3], const double t[3],
@@ -222,7 +228,10 @@ void or_map_shapes(int nx, int ny, int nz, int zper, int np, const double *X, co
                         continue;
                     int64_t idx = ((int64_t)z * ny + y) * nx + x;
                     if (pid[idx] < 0) pid[idx] = p;
-                    else if (pid[idx] != p) ++ov; /* claimed twice: lowest id keeps it */
+                    else if (pid[idx] != p) {     /* claimed twice: lowest id keeps it */
+                        ++ov;
+                        if (g_mutation == 18) pid[idx] = p;
+                    }
                 }
             }
         }

@@ -141,7 +141,10 @@ void    or_get_exchange_sums(const or_sim *s, double *out);
    link force without its factor 2; 11: the torque as dF x r; 12: free-slip
    walls bouncing back; 13: the refill at the new pose and motion; 14: the
    stabilization shift added; 15: resting side walls returning the
-   population in its own direction); 0 restores the oracle, whose results are
+   population in its own direction; 16: the cylinder's axial bound at L
+   instead of L/2; 17: the axis of the conjugate quaternion; 18: the highest
+   id keeping a cell claimed twice; 19: the spherocylinder's caps centred
+   at the cylinder's ends); 0 restores the oracle, whose results are
    then bit-identical to a build without the hook */
 void    or_set_mutation(int code);
 /* OpenMP threads of the following steps (timing on one core or all), and

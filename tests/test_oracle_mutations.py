@@ -1,6 +1,7 @@
 """Each pin can fail: a plausible mistake planted in the LBM oracle's core
 steps (collision, equilibrium, moving walls, fiber bounce-back, momentum
-exchange, free-slip reflection, refill, stabilization, side walls) makes
+exchange, free-slip reflection, refill, stabilization, side walls, cell
+mapping) makes
 the named pins fail (the rest of the suite runs every pin with none
 planted).  The planted mistakes of the coupled rigid-body update are in
 test_oracle_coupling_pins.py."""
@@ -36,6 +37,15 @@ MUTATIONS = {
           P.test_stabilized_momentum_with_body_force_reaches_its_fixed_point]),
     15: ("resting side wall returns the population in its own direction",
          [P.test_closed_box_conserves_mass_and_stops]),
+    16: ("cylinder's axial bound at L instead of L/2",
+         [P.test_mapping_hand_counted, P.test_mapping_volume_converges]),
+    17: ("axis of the conjugate quaternion",
+         [P.test_mapping_hand_counted, P.test_quaternion_update_constant_rotation,
+          P.test_free_precession_conserves_angular_momentum]),
+    18: ("highest id keeps a cell claimed twice", [P.test_mapping_overlap_lowest_id_wins]),
+    19: ("spherocylinder caps centred at the cylinder's ends",
+         [P.test_spherocylinder_predicate_is_the_distance_to_the_axis_segment,
+          P.test_spherocylinder_cell_count_converges_to_its_volume]),
 }
 
 
