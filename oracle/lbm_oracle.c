@@ -146,7 +146,7 @@ void or_fiber_axis(const double q[4], double t[3])
 /* minimum-image component of a periodic difference */
 static double min_image(double d, int n, int periodic)
 {
-    if (!periodic) return d;
+    if (!periodic || g_mutation == 24) return d;
     double h = 0.5 * n;
     if (d > h) return d - n;
     if (d < -h) return d + n;
@@ -279,11 +279,12 @@ void or_rigid_step(const double *s, double mass, double i_par, double i_perp,
     int n[3] = {nx, ny, nz}, per[3] = {1, 1, zper};
     for (int k = 0; k < 3; ++k) {
         Vn[k] = V[k] + F[k] / mass;
-        Xn[k] = wrap_pos(X[k] + Vn[k], n[k], per[k]);
+        Xn[k] = wrap_pos(X[k] + (g_mutation == 20 ? V[k] : Vn[k]), n[k], per[k]);
         Ln[k] = La[k] + M[k];
     }
     double tl = t[0] * Ln[0] + t[1] * Ln[1] + t[2] * Ln[2];
-    for (int k = 0; k < 3; ++k) Wn[k] = Ln[k] / i_perp + (1.0 / i_par - 1.0 / i_perp) * tl * t[k];
+    const double ia = g_mutation == 21 ? i_perp : i_par, ie = g_mutation == 21 ? i_par : i_perp;
+    for (int k = 0; k < 3; ++k) Wn[k] = Ln[k] / ie + (1.0 / ia - 1.0 / ie) * tl * t[k];
     double ang = sqrt(Wn[0] * Wn[0] + Wn[1] * Wn[1] + Wn[2] * Wn[2]);
     double dq[4] = {1.0, 0.0, 0.0, 0.0};
     if (ang > 0.0) {
@@ -472,10 +473,12 @@ double or_contact_pair(const double tp[3], double hp, double rp,
     double C[3];                 /* middle of the gap, relative to X_p */
     for (int i = 0; i < 3; ++i) {
         C[i] = P[i] + (rp + 0.5 * gap) * n[i];
-        Fp[i] = -mag * n[i];
-        Fq[i] = mag * n[i];
+        Fp[i] = g_mutation == 22 ? mag * n[i] : -mag * n[i];
+        Fq[i] = g_mutation == 22 ? -mag * n[i] : mag * n[i];
     }
     double Cq[3] = {C[0] - dpq[0], C[1] - dpq[1], C[2] - dpq[2]};   /* relative to X_q */
+    if (g_mutation == 23)
+        for (int i = 0; i < 3; ++i) Cq[i] = C[i];  /* q's lever measured from X_p */
     Mp[0] = C[1] * Fp[2] - C[2] * Fp[1];
     Mp[1] = C[2] * Fp[0] - C[0] * Fp[2];
     Mp[2] = C[0] * Fp[1] - C[1] * Fp[0];

@@ -144,7 +144,10 @@ void    or_get_exchange_sums(const or_sim *s, double *out);
    population in its own direction; 16: the cylinder's axial bound at L
    instead of L/2; 17: the axis of the conjugate quaternion; 18: the highest
    id keeping a cell claimed twice; 19: the spherocylinder's caps centred
-   at the cylinder's ends); 0 restores the oracle, whose results are
+   at the cylinder's ends; 20: the explicit rigid step moving with the old
+   velocity; 21: I_par and I_perp swapped; 22: an attractive contact force;
+   23: the contact torque on q taken about the centre of p; 24: no minimum
+   image across periodic faces); 0 restores the oracle, whose results are
    then bit-identical to a build without the hook */
 void    or_set_mutation(int code);
 /* OpenMP threads of the following steps (timing on one core or all), and

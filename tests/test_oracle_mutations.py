@@ -1,7 +1,7 @@
 """Each pin can fail: a plausible mistake planted in the LBM oracle's core
 steps (collision, equilibrium, moving walls, fiber bounce-back, momentum
 exchange, free-slip reflection, refill, stabilization, side walls, cell
-mapping) makes
+mapping, rigid step, contacts, periodic images) makes
 the named pins fail (the rest of the suite runs every pin with none
 planted).  The planted mistakes of the coupled rigid-body update are in
 test_oracle_coupling_pins.py."""
@@ -46,6 +46,13 @@ MUTATIONS = {
     19: ("spherocylinder caps centred at the cylinder's ends",
          [P.test_spherocylinder_predicate_is_the_distance_to_the_axis_segment,
           P.test_spherocylinder_cell_count_converges_to_its_volume]),
+    20: ("explicit rigid step moving with the old velocity", [P.test_rigid_translation_and_wrap]),
+    21: ("I_par and I_perp swapped in the inverse inertia",
+         [P.test_free_precession_conserves_angular_momentum, P.test_quaternion_update_constant_rotation]),
+    22: ("attractive contact force",
+         [P.test_contact_side_by_side_closed_form, P.test_contact_is_a_central_pair_force]),
+    23: ("contact torque on q about the centre of p", [P.test_contact_is_a_central_pair_force]),
+    24: ("no minimum image across periodic faces", [P.test_mapping_periodic_translation]),
 }
 
 
