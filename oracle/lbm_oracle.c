@@ -616,8 +616,9 @@ void or_body_inertia(int shape, double length, double radius, double rho, double
         double ms = rho * (4.0 / 3.0) * M_PI * radius * radius * radius;
         out[0] = mc + ms;
         out[1] = mc * radius * radius / 2.0 + 2.0 * ms * radius * radius / 5.0;
-        out[2] = mc * (3.0 * radius * radius + h * h) / 12.0 +
-                 ms * (2.0 * radius * radius / 5.0 + h * h / 4.0 + 3.0 * h * radius / 8.0);
+        out[2] = g_mutation == 26 ? mc * (3.0 * radius * radius + h * h) / 12.0 + ms * (2.0 * radius * radius / 5.0)
+                                  : mc * (3.0 * radius * radius + h * h) / 12.0 +
+                                    ms * (2.0 * radius * radius / 5.0 + h * h / 4.0 + 3.0 * h * radius / 8.0);
     } else {
         double m = rho * M_PI * radius * radius * length;
         out[0] = m;
@@ -737,7 +738,10 @@ int64_t or_mean_velocity(const or_sim *s, double ubar[3])
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < p->nx; ++x) {
                 int64_t c = cidx(s, x, y, z);
-                if (s->flag[c]) continue;
+                if (s->flag[c]) {
+                    if (g_mutation == 25) part[4 * z + 3] += 1.0;   /* solid cells counted */
+                    continue;
+                }
                 double *a = part + 4 * z;
                 for (int q = 0; q < Q; ++q) {
                     double fq = *slot(s->fa, s, q, c);
@@ -944,8 +948,8 @@ static void one_step(or_sim *s)
         const double *rd = red + 39 * i;
         double fe[3], me[3];   /* external plus contact load */
         for (int k = 0; k < 3; ++k) {
-            fe[k] = f->fext[k] + cl[6 * i + k];
-            me[k] = f->mext[k] + cl[6 * i + 3 + k];
+            fe[k] = (g_mutation == 27 ? 0.0 : f->fext[k]) + cl[6 * i + k];
+            me[k] = (g_mutation == 28 ? 0.0 : f->mext[k]) + cl[6 * i + 3 + k];
         }
         memcpy(old + 16 * i, f->st, 16 * sizeof(double));
         memcpy(f->sums, rd, 39 * sizeof(double));

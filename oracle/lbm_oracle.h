@@ -147,7 +147,10 @@ void    or_get_exchange_sums(const or_sim *s, double *out);
    at the cylinder's ends; 20: the explicit rigid step moving with the old
    velocity; 21: I_par and I_perp swapped; 22: an attractive contact force;
    23: the contact torque on q taken about the centre of p; 24: no minimum
-   image across periodic faces); 0 restores the oracle, whose results are
+   image across periodic faces; 25: the mean velocity counting solid cells;
+   26: the spherocylinder caps' inertia without the parallel-axis shift;
+   27: the external force dropped; 28: the external torque dropped); 0
+   restores the oracle, whose results are
    then bit-identical to a build without the hook */
 void    or_set_mutation(int code);
 /* OpenMP threads of the following steps (timing on one core or all), and

@@ -1,7 +1,7 @@
 """Each pin can fail: a plausible mistake planted in the LBM oracle's core
 steps (collision, equilibrium, moving walls, fiber bounce-back, momentum
 exchange, free-slip reflection, refill, stabilization, side walls, cell
-mapping, rigid step, contacts, periodic images) makes
+mapping, rigid step, contacts, periodic images, external loads) makes
 the named pins fail (the rest of the suite runs every pin with none
 planted).  The planted mistakes of the coupled rigid-body update are in
 test_oracle_coupling_pins.py."""
@@ -53,6 +53,14 @@ MUTATIONS = {
          [P.test_contact_side_by_side_closed_form, P.test_contact_is_a_central_pair_force]),
     23: ("contact torque on q about the centre of p", [P.test_contact_is_a_central_pair_force]),
     24: ("no minimum image across periodic faces", [P.test_mapping_periodic_translation]),
+    25: ("mean velocity over all cells, solid ones included",
+         [P.test_mean_velocity_is_the_fluid_cell_mean, P.test_stabilized_momentum_budget_with_a_forced_particle]),
+    26: ("spherocylinder caps' inertia without the parallel-axis shift",
+         [lambda: P.test_body_mass_and_inertia_by_quadrature("spherocylinder")]),
+    27: ("external force dropped",
+         [P.test_external_force_enters_the_momentum_budget,
+          lambda: P.test_external_load_enters_the_first_explicit_step("cylinder")]),
+    28: ("external torque dropped", [lambda: P.test_external_load_enters_the_first_explicit_step("spherocylinder")]),
 }
 
 

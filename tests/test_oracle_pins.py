@@ -447,6 +447,30 @@ def test_external_force_enters_the_momentum_budget():
     assert np.linalg.norm(W[0]) > 0.0
 
 
+@pytest.mark.parametrize("shape", ["cylinder", "spherocylinder"])
+def test_external_load_enters_the_first_explicit_step(shape):
+    """Sec. 4.3 with the constant load of Eq. ForceDensDiff: a fiber at rest
+    takes one explicit step from the recorded hydrodynamic force and torque
+    plus its external load, m V_1 = F_h + F_e and I(q_0) W_1 = M_h + M_e,
+    with I(q_0) = I_perp + (I_par - I_perp) t t^T about the axis t of the
+    starting pose (to rounding)."""
+    n = 24
+    sim = O.Sim(n, n, n, tau=0.8, z_periodic=True, coupling="explicit")
+    Fe = np.array([2e-3, -1e-3, 5e-4])
+    Me = np.array([4e-2, -3e-2, 5e-2])
+    L, r, rho = 10.0, 2.0, 1.7
+    t = np.array([0.3, 0.8, 0.52]) / np.linalg.norm([0.3, 0.8, 0.52])
+    sim.add_fiber([12.2, 11.7, 12.4], _quat_to(t), L, r, rho, shape=shape, force=Fe, torque=Me)
+    sim.step(1)
+    h = sim.history(0, 1)[0, 0]
+    m, i_par, i_perp = O.body_inertia(shape, L, r, rho)
+    Fh, Mh, V1, W1 = h[0:3], h[3:6], h[13:16], h[16:19]
+    np.testing.assert_allclose(m * V1, Fh + Fe, rtol=1e-13, atol=1e-18)
+    I0 = i_perp * np.eye(3) + (i_par - i_perp) * np.outer(t, t)
+    np.testing.assert_allclose(I0 @ W1, Mh + Me, rtol=1e-12, atol=1e-16)
+    assert np.linalg.norm(Me) > 10 * np.linalg.norm(Mh)     # the external torque dominates
+
+
 # ------------------------------------------------- momentum stabilization (Sec. 4.1)
 def _periodic_random_box(n, tau, seed, srt=False, g=(0.0, 0.0, 0.0)):
     sim = O.Sim(n, n, n, tau=tau, z_periodic=True, srt=srt, g=g, stabilize=True)
