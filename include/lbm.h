@@ -190,7 +190,11 @@ lbm_status lbm_lattice(int32_t *c, double *w);
 /* Add a fiber before the first step (Sec. 4.2 mapping).  *id receives its
  * index (dense from 0).  LBM_E_GEOM if the fiber leaves the domain or comes
  * within one cell of a wall, or if it shares a cell with another fiber;
- * the fiber is then not added.  LBM_E_STATE after the first step. */
+ * the fiber is then not added.  LBM_E_STATE after the first step.
+ * LBM_E_ARG beyond 302 fibers per context (248 with contacts): the
+ * rigid-body update of all fibers runs in one workgroup that keeps their
+ * momentum-exchange sums (27 doubles per fiber) in 64 KiB of LDS.  Each
+ * insertion re-maps the lattice, so setting up np fibers costs O(np^2). */
 lbm_status lbm_add_fiber(lbm_ctx *ctx, const lbm_fiber *f, int32_t *id);
 
 /* Prescribe the motion of fiber id for its next nsteps steps.  traj is a
