@@ -41,6 +41,11 @@ GMRES as the paper does.  Time integration: the paper names only an
 explicit method of second order with constant dt; this reference uses
 Adams-Bashforth of order two with one Euler step to start, and renormalises
 p.
+
+Parity unpinned: geometry_parameter.  d = -ln(eps^2 e) is Eq. SBFGeomParam
+written out; the single-fiber closed forms of Sec. 5 that pin the rest are
+expressed in the same d, and the paper prints no slender-body value for a
+free-space configuration that would check it independently.
 """
 import numpy as np
 
