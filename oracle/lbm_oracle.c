@@ -210,8 +210,17 @@ void or_map_shapes(int nx, int ny, int nz, int zper, int np, const double *X, co
         double ext = 0.5 * length[p] + radius[p];
         int lo[3], hi[3], n[3] = {nx, ny, nz};
         for (int k = 0; k < 3; ++k) {
-            lo[k] = (int)floor(X[3 * p + k] - ext) - 1;
-            hi[k] = (int)ceil(X[3 * p + k] + ext) + 1;
+            const double a = X[3 * p + k] - ext, b = X[3 * p + k] + ext;
+            if (!(a > -1e6 && b < 1e6)) {
+                /* a centre that is not finite or lies far off the lattice (a run
+                   that has diverged): no integer box; scan the whole axis and let
+                   the predicate decide */
+                lo[k] = 0;
+                hi[k] = n[k] - 1;
+                continue;
+            }
+            lo[k] = (int)floor(a) - 1;
+            hi[k] = (int)ceil(b) + 1;
             if (hi[k] - lo[k] + 1 > n[k]) { lo[k] = 0; hi[k] = n[k] - 1; }
         }
         int zp = zper;

@@ -322,6 +322,19 @@ def test_mapping_periodic_translation():
     assert np.array_equal(np.roll(np.roll(pid_a, -12, axis=2), -10, axis=1), pid_b)
 
 
+def test_mapping_of_a_diverged_centre_claims_no_cell():
+    """A centre that is not finite, or lies far off the lattice (a run that
+    has blown up), claims no cell and leaves the other fibers' cells as
+    they are."""
+    q = np.array([1.0, 0.0, 0.0, 0.0])
+    ref, _ = O.map_fibers((16, 12, 10), [8.0, 6.0, 5.0], q, 6.0, 1.5, z_periodic=True)
+    assert (ref == 0).sum() > 0
+    for bad in ([np.nan, 6.0, 5.0], [8.0, np.inf, 5.0], [8.0, 6.0, -1e12]):
+        pid, ov = O.map_fibers((16, 12, 10), [[8.0, 6.0, 5.0], bad], np.r_[q, q], [6.0, 6.0], [1.5, 1.5],
+                               z_periodic=True)
+        assert np.array_equal(pid, ref) and ov == 0, bad
+
+
 def test_mapping_overlap_lowest_id_wins():
     """Two crossing fibers: shared cells go to the lowest id and are counted."""
     pid, ov = O.map_fibers((20, 20, 20), [[10, 10, 10], [10, 10, 10]],
