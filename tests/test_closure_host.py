@@ -3,7 +3,8 @@ rotation R(q), the fine-to-coarse coordinate map and trajectory scaling of
 the diffusively scaled pairs (coarse spacing 2: velocities x 2, angular
 velocities x 4), the constant-spin trajectories that prescribe part of the
 training data, the normalisation envelope and the error measure, each
-against a closed form."""
+against a closed form; and the training pairs against their stated
+recipe."""
 import numpy as np
 import pytest
 
@@ -125,3 +126,32 @@ def test_error_measure_is_the_mean_norm_of_the_miss():
     eF, eM = closure.relative_errors(Y, 0 * Y)
     assert eF == (5.0 + 0.0 + 2.0 + 1.0) / 4 and eM == 1.0
     assert closure.relative_errors(Y, Y) == (0.0, 0.0)
+
+
+def test_training_pairs_follow_the_stated_recipe():
+    """Fine 64^3 / coarse 32^3 twins, diameters 4 / 2, aspect ratio in
+    [2, 12] with the coarse length fitting 8 cells inside the cell, coarse
+    shear rate in [5e-4, 1.5e-3], the coarse fiber at the fine centre under
+    the coordinate map with velocities x 2 and angular velocities x 4, and
+    about half of the fine fibers turning at a prescribed rate."""
+    pairs = closure.training_pairs(seed=0, n=40, steps=50)
+    assert len(pairs) == 40
+    prescribed = 0
+    for pr in pairs:
+        f, c = pr.fine.fibers[0], pr.coarse.fibers[0]
+        assert (pr.fine.nx, pr.coarse.nx) == (64, 32)
+        assert (2 * f.radius, 2 * c.radius) == (4.0, 2.0)
+        assert 2.0 <= c.length / 2.0 <= 12.0 and c.length <= 32 - 8.0
+        assert f.length == 2 * c.length
+        assert 5e-4 <= pr.coarse.shear_rate <= 1.5e-3 + 1e-15
+        np.testing.assert_allclose(pr.fine.shear_rate, pr.coarse.shear_rate / 4.0, rtol=1e-14)
+        np.testing.assert_array_equal(c.X, closure.coarse_of(f.X))
+        np.testing.assert_allclose(c.V, 2.0 * f.V, rtol=0, atol=0)
+        np.testing.assert_allclose(c.W, 4.0 * f.W, rtol=0, atol=0)
+        if pr.fine_traj is not None:
+            prescribed += 1
+            assert pr.fine_traj.shape == (4 * 50, 13)
+            gf = 2.0 * pr.fine.wall_u / 64
+            assert np.all(np.abs(f.W) <= gf) and not f.V.any()
+            np.testing.assert_array_equal(pr.fine_traj[:, 10:13], np.broadcast_to(f.W, (200, 3)))
+    assert 10 <= prescribed <= 30
