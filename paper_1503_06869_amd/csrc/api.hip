@@ -689,14 +689,16 @@ lbm_status lbm_add_fiber(lbm_ctx *c, const lbm_fiber *f, int32_t *id)
         c->pch.pop_back();
         c->traj_h.pop_back();
         c->np--;
-        hipMemsetAsync(c->flags[0], 0, c->g.ncell, c->st);
-        hipMemsetAsync(c->flags[1], 0, c->g.ncell, c->st);
-        hipMemsetAsync(c->pid, 0xFF, size_t(c->g.ncell) * 4, c->st);
-        hipMemsetAsync(c->ctr, 0, sizeof(DevCounters), c->st);
+        hipError_t e = hipMemsetAsync(c->flags[0], 0, c->g.ncell, c->st);
+        if (e == hipSuccess) e = hipMemsetAsync(c->flags[1], 0, c->g.ncell, c->st);
+        if (e == hipSuccess) e = hipMemsetAsync(c->pid, 0xFF, size_t(c->g.ncell) * 4, c->st);
+        if (e == hipSuccess) e = hipMemsetAsync(c->ctr, 0, sizeof(DevCounters), c->st);
+        if (e != hipSuccess) return fail(c, LBM_E_HIP, hipGetErrorString(e));
         lbm_status s2 = upload_particles(c);
         if (s2 == LBM_OK) s2 = setup_mapping(c, nullptr);
         if (s2 != LBM_OK) return s2;
-        hipStreamSynchronize(c->st);
+        e = hipStreamSynchronize(c->st);
+        if (e != hipSuccess) return fail(c, LBM_E_HIP, hipGetErrorString(e));
         return fail(c, LBM_E_GEOM, h.err_capacity ? "internal capacity exceeded while mapping"
                                                  : "fiber overlaps another fiber");
     }
@@ -748,7 +750,11 @@ lbm_status lbm_step(lbm_ctx *c, int64_t n)
         if (c->timing) {
             while (c->ev.size() < c->ev_used + 2) {
                 hipEvent_t e;
-                hipEventCreate(&e);
+                const hipError_t ce = hipEventCreate(&e);
+                if (ce != hipSuccess) {   // no step without its events
+                    err = ce;
+                    return;
+                }
                 c->ev.push_back(e);
             }
             e0 = c->ev[c->ev_used];
